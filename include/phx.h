@@ -1,0 +1,195 @@
+/*
+ * phx: mixed-variational phononic band structures and adjoint design
+ * sensitivities on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Lu, Yang, Guest, Srivastava, "3-D phononic crystals with ultra-wide
+ * band gaps"):
+ *   - a periodic two-phase unit cell, voxelized into nv^3 elements laid along
+ *     the primitive vectors of an SC, BCC or FCC lattice (Methods, "Study of
+ *     cubic unit cells");
+ *   - displacement and stress expanded in the Bloch plane waves
+ *     exp[i 2 pi K.x], K = T^T (Q + n), n in [-M, M]^3 (Results, "Phononic band
+ *     structure calculation"), giving the mixed-variational eigenproblem
+ *     H Phi^{-1} H^* U = lambda Omega U, lambda = omega^2 (Eq. 4) with the
+ *     matrices of Eqs. (5)-(7) evaluated by the element-centroid rule
+ *     (Eqs. 16-19);
+ *   - design sensitivities d omega / d rho_e from the adjoint form of Eq. (15)
+ *     with the element derivative matrices of Eqs. (20)-(21).
+ *
+ * Conventions shared by every call:
+ *   - All arrays are owned by the caller.  Host-pointer calls copy in and out
+ *     and return only after the results are in the caller's arrays; the
+ *     library keeps no caller pointer after a call returns.
+ *   - Units: SI in (m, kg/m^3, Pa); omega out in rad/s; derivatives of omega
+ *     in rad/s per unit of rho_e.
+ *   - Design fields rho are nv^3 doubles in C order [i1][i2][i3], i_j along
+ *     primitive vector a_j; voxel e = (i1, i2, i3) has centroid
+ *     sum_j (i_j + 1/2)/nv a_j.  rho_e = 0 is phase0, rho_e = 1 is phase1;
+ *     density and compliance are affine in w_e = rho_e^simp_p.
+ *   - Bloch vectors are given in reciprocal coordinates Q (3 doubles per
+ *     k-point): K = sum_j (Q_j + n_j) b_j with a_i . b_j = delta_ij.
+ *   - Bands are numbered from 1 in ascending omega.
+ *   - Every call returns PHX_OK (0), a negative error or a positive warning;
+ *     phx_last_error() then describes it.  One context per host thread; calls
+ *     on a context are serialised on its HIP stream.
+ */
+#ifndef PHX_H
+#define PHX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHX_OK 0
+#define PHX_EINVAL (-1)  /* invalid argument (checked on the host before any device work) */
+#define PHX_ENOMEM (-2)  /* device allocation failed */
+#define PHX_EHIP (-3)    /* a HIP runtime call failed, or no device */
+#define PHX_ENOCONV (-4) /* eigensolver hit its iteration cap; outputs hold the last iterate */
+#define PHX_ENOTPD (-5)  /* a matrix that must be positive definite failed its Cholesky */
+
+typedef struct phx_ctx phx_ctx;
+
+typedef enum { PHX_SC = 0, PHX_BCC = 1, PHX_FCC = 2 } phx_lattice;
+
+/* PHX_FP64: every factorisation and solve in FP64.
+ * PHX_MIXED: the per-k pencil factorisation and the preconditioner solves in
+ * FP32 on the matrix cores; residuals, Rayleigh-Ritz and the material
+ * operators in FP64, so converged eigenvalues carry FP64 residuals. */
+typedef enum { PHX_FP64 = 0, PHX_MIXED = 1 } phx_precision;
+
+typedef struct {
+  double density; /* kg/m^3, > 0 */
+  double youngs;  /* Pa, > 0 */
+  double poisson; /* in (-1, 1/2) */
+} phx_material;
+
+typedef struct {
+  phx_lattice lattice;
+  double a;            /* conventional cube edge (m), > 0 */
+  int nv;              /* voxels per primitive axis; must satisfy nv >= 2M+1 */
+  int M;               /* plane-wave order, 1 <= M <= 8; N = (2M+1)^3 waves */
+  phx_material phase0; /* rho_e = 0 */
+  phx_material phase1; /* rho_e = 1 */
+  double simp_p;       /* w = rho^p, p >= 1 */
+} phx_cell;
+
+/* ------------------------------------------------------------------ context */
+
+/* Creates a context on HIP device `hip_device` with its own stream.
+ * Returns PHX_EHIP if the device is missing. */
+int phx_create(phx_ctx** out, int hip_device);
+int phx_destroy(phx_ctx* ctx);
+/* Message of the last failed call on ctx (valid until the next call). */
+const char* phx_last_error(const phx_ctx* ctx);
+
+/* Solver options.  Keys: "tol_fp64", "tol_mixed" (relative residual
+ * |K x - lambda Omega x| / ((lambda + sigma)|Omega x|) at which a band counts as
+ * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
+ * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
+ * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
+ * "mem_gb" (device memory budget for one k-chunk, default 64).
+ * Returns PHX_EINVAL for an unknown key or an out-of-range value. */
+int phx_set_option(phx_ctx* ctx, const char* key, double value);
+/* Statistics of the last solve: "iters" (eigensolver iterations of the
+ * slowest chunk), "chunks", "block", "kchunk". */
+int phx_get_stat(const phx_ctx* ctx, const char* key, double* value);
+
+/* ------------------------------------------------------------------ helpers */
+
+/* k-points along the edges of the irreducible Brillouin zone (Results, "A note
+ * on normalized band gaps"; Methods, "Study of cubic unit cells"), as
+ * reciprocal coordinates q_out[3*nk].  `path` names high-symmetry points (G for
+ * Gamma; SC: X M R; BCC: H N P; FCC: X W K L U) with "|" for a break; NULL
+ * selects G-X-M-G-R-X|M-R (SC), G-H-N-G-P-H|P-N (BCC), G-X-W-K-G-L-U-W-L-K|U-X
+ * (FCC).  Every vertex is included and the other points are spread over the
+ * segments in proportion to their length (largest remainder), evenly inside a
+ * segment.  Host-only; needs no context.  PHX_EINVAL if nk is smaller than the
+ * number of vertices or the path names an unknown point. */
+int phx_kpath(phx_lattice lattice, const char* path, int nk, double* q_out);
+
+/* Host-only argument check shared by every solver call: the cell (lattice,
+ * a > 0, 1 <= M <= 8, 2M+1 <= nv <= 256, materials, simp_p >= 1), rho (if not
+ * NULL: nv^3 finite non-negative values), q (if nk or q given: nk >= 1 finite
+ * triples), bands (if nbands or nsens given: 1 <= nbands <= min(16, 3N), band_no
+ * entries in [1, nbands]).  Writes a message into msg (msglen bytes, may be
+ * NULL).  Needs no device. */
+int phx_validate(const phx_cell* cell, const double* rho, int nk, const double* q, int nbands, int nsens,
+                 const int* band_no, char* msg, int msglen);
+
+/* ------------------------------------------------------------------ stages */
+
+/* Centroid-rule Fourier coefficients of the density and of the two Mandel
+ * compliance channels (1/(3K) and 1/(2G)) of the interpolated design, the
+ * building blocks of Eqs. (6)-(7) through Eqs. (16)-(19):
+ *   ghat(m) = v sum_e g_e exp(i 2 pi m . s_e),  m in [-2M, 2M]^3, v = V / nv^3.
+ * out: 3 * (4M+1)^3 complex values as (re, im) double pairs, order
+ * [field][m1+2M][m2+2M][m3+2M], fields (density, c_vol, c_dev), SI units
+ * (kg and m^3/Pa). */
+int phx_fourier(phx_ctx* ctx, const phx_cell* cell, const double* rho, double* out);
+
+/* The stress-eliminated operator of Eq. (4), K(Q) = H Phi^{-1} H^*, at one Bloch
+ * vector q (3 doubles), as a dense 3N x 3N complex matrix, column-major, rows
+ * and columns ordered (plane wave p, component c) -> 3p + c, plane waves in
+ * lexicographic order of (n1, n2, n3) with n1 slowest; SI units (N/m).
+ * out: 2 * (3N)^2 doubles. */
+int phx_schur(phx_ctx* ctx, const phx_cell* cell, const double* rho, const double* q, double* out);
+
+/* ------------------------------------------------------------------ band structure */
+
+/* Lowest `nbands` eigenfrequencies of Eq. (4) at nk Bloch vectors.
+ * omega: nk * nbands (rad/s, ascending per k).  err_bound (may be NULL):
+ * nk * nbands residual-based bounds on |omega - omega_exact| for the
+ * discretised problem.  1 <= nbands <= 16.  PHX_ENOCONV if a band did not reach
+ * the tolerance (outputs hold the last iterate). */
+int phx_bands(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+              phx_precision prec, double* omega, double* err_bound);
+
+/* Bands plus d omega_b / d rho_e (Eq. 15 with Eqs. 20-21) for the nsens bands
+ * band_no[0..nsens) (1-based, each <= nbands), at every k-point.
+ * domega_drho: nk * nsens * nv^3, order [k][sens][e].  A band with omega = 0
+ * (acoustic bands at Gamma) gets a zero derivative. */
+int phx_sens(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+             phx_precision prec, int nsens, const int* band_no, double* omega, double* domega_drho);
+
+/* Weighted adjoint: grad_e = sum_{k, j} weight[k * nsens + j] d omega_{band_no[j]}(k) / d rho_e,
+ * i.e. the gradient of any objective of the band frequencies given its
+ * partial derivatives (Eq. 15 followed by the chain rule through Eq. 10).
+ * omega: nk * nbands (may be NULL); grad: nv^3. */
+int phx_adjoint(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+                phx_precision prec, int nsens, const int* band_no, const double* weight, double* omega,
+                double* grad);
+
+/* Several designs (cells may differ in lattice, nv and M) through one call:
+ * omega[d] receives nk * nbands values for design d; if band_no is given,
+ * domega[d] (if not NULL) receives nk * nsens * nv_d^3 sensitivities. */
+int phx_bands_batch(phx_ctx* ctx, int ndesign, const phx_cell* cells, const double* const* rho, int nk,
+                    const double* q, int nbands, phx_precision prec, int nsens, const int* band_no,
+                    double* const* omega, double* const* domega);
+
+/* Device-pointer variants: rho, q, omega, domega_drho point to device memory
+ * and the call is ordered on `stream` (a hipStream_t) and synchronises it
+ * before returning; used by the PyTorch binding. */
+int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                 int nbands, phx_precision prec, int nsens, const int* band_no, double* omega_dev,
+                 double* domega_dev, void* stream);
+
+/* ------------------------------------------------------------------ dense building blocks */
+
+/* Batched complex GEMM on the matrix cores: C_b = alpha op(A_b) op(B_b) + beta C_b,
+ * column-major, op 'N' or 'C' (conjugate transpose); A_b = A + b*strideA etc.
+ * (element strides; 0 shares an operand).  prec selects FP64 or FP32
+ * arithmetic (FP32 operands are rounded from the FP64 host arrays).  Host
+ * arrays of (re, im) doubles. */
+int phx_zgemm(phx_ctx* ctx, phx_precision prec, char opa, char opb, int m, int n, int k, const double* alpha,
+              const double* A, long lda, long strideA, const double* B, long ldb, long strideB, const double* beta,
+              double* C, long ldc, long strideC, int batch);
+
+/* Batched Hermitian positive definite solve A_b X_b = B_b by Cholesky: A is
+ * batch x n x n (lower triangle read), B is batch x n x nrhs; X overwrites B.
+ * n must be a multiple of 64.  PHX_ENOTPD if a pivot is not positive. */
+int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, const double* A, double* B);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHX_H */

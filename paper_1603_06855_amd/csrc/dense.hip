@@ -1,0 +1,373 @@
+// Dense complex linear algebra on CDNA4 matrix cores (MFMA 16x16x4, FP64 and FP32).
+//
+// * zgemm:        batched C = alpha op(A) op(B) + beta C, op in {N, conjugate-transpose},
+//                 64x64 output tiles, 256 threads, optional lower-triangular tile grid
+//                 (Hermitian rank-k updates) and split-K with a deterministic reduction.
+// * potrf_diag:   Cholesky of one 64x64 diagonal block per matrix in LDS, plus the
+//                 explicit inverse of the factor (used to turn panel and block
+//                 triangular solves into GEMMs).
+//
+// Complex products are built from four real MFMA products.  The MFMA is fed the
+// B tile as its first operand and the A tile as its second, so the 16x16 result
+// it returns is C transposed: each lane then holds four consecutive *columns* of
+// one row, and lanes 0..15 cover 16 consecutive rows, which makes the stores to
+// column-major C contiguous.
+#include "phx_common.h"
+#include "phx_internal.h"
+
+namespace phx {
+
+template <typename R, int OPA, int OPB>
+__global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
+  typedef C_t<R> C;
+  typedef typename acc_t<R>::type ACC;
+  __shared__ R Asr[16][64 + 4], Asi[16][64 + 4], Bsr[16][64 + 4], Bsi[16][64 + 4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  int ti, tj;
+  if (g.tri) {
+    const long t = blockIdx.x;
+    long r = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    ti = (int)r;
+    tj = (int)(t - r * (r + 1) / 2);
+  } else {
+    const int tm = (g.M + 63) >> 6;
+    ti = blockIdx.x % tm;
+    tj = blockIdx.x / tm;
+  }
+  const int row0 = ti * 64, col0 = tj * 64;
+  const int b = blockIdx.y;
+  const int sp = blockIdx.z;
+  const C* A = g.A + (long)(b / g.dA) * g.sA;
+  const C* B = g.B + (long)(b / g.dB) * g.sB;
+
+  int kchunk = g.K;
+  if (g.ksplit > 1) kchunk = (((g.K + g.ksplit - 1) / g.ksplit) + 15) & ~15;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  ACC cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = (ACC){0, 0, 0, 0};
+      ci[i][j] = (ACC){0, 0, 0, 0};
+    }
+
+  C ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int i, k;
+      if (OPA == 0) { k = k0 + (tid >> 4); i = row0 + ((tid & 15) << 2) + q; }
+      else { i = row0 + (tid >> 2); k = k0 + ((tid & 3) << 2) + q; }
+      C v = mk<R>(0, 0);
+      if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+      ra[q] = v;
+      int j, kb;
+      if (OPB == 0) { j = col0 + (tid >> 2); kb = k0 + ((tid & 3) << 2) + q; }
+      else { kb = k0 + (tid >> 4); j = col0 + ((tid & 15) << 2) + q; }
+      C w = mk<R>(0, 0);
+      if (j < g.N && kb < kend) w = (OPB == 0) ? B[kb + (long)j * g.ldb] : B[j + (long)kb * g.ldb];
+      rb[q] = w;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (OPA == 0) {
+        const int kk = tid >> 4, ii = ((tid & 15) << 2) + q;
+        Asr[kk][ii] = ra[q].x; Asi[kk][ii] = ra[q].y;
+      } else {
+        const int ii = tid >> 2, kk = ((tid & 3) << 2) + q;
+        Asr[kk][ii] = ra[q].x; Asi[kk][ii] = -ra[q].y;
+      }
+      if (OPB == 0) {
+        const int jj = tid >> 2, kk = ((tid & 3) << 2) + q;
+        Bsr[kk][jj] = rb[q].x; Bsi[kk][jj] = rb[q].y;
+      } else {
+        const int kk = tid >> 4, jj = ((tid & 15) << 2) + q;
+        Bsr[kk][jj] = rb[q].x; Bsi[kk][jj] = -rb[q].y;
+      }
+    }
+  };
+
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + 16 < kend) load(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
+        ai[x] = Asi[kr][wr * 32 + x * 16 + (lane & 15)];
+        br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
+        bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
+          ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
+          cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
+          ci[x][y] = mfma16(br[y], ai[x], ci[x][y]);
+        }
+    }
+  }
+
+  // Epilogue.
+  const bool part = g.ksplit > 1;
+  C* Cb = part ? g.Cpart + ((long)sp * g.batch + b) * (long)g.M * g.N
+               : g.Cm + (long)(b / g.dC) * g.sC;
+  const long ldc = part ? g.M : g.ldc;
+  const bool useBeta = !part && (g.beta.x != 0 || g.beta.y != 0);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + x * 16 + (lane & 15);
+        const int col = col0 + wc * 32 + y * 16 + ((lane >> 4) << 2) + r;
+        if (row < g.M && col < g.N) {
+          C acc = mk<R>(cr[x][y][r], ci[x][y][r]);
+          C v = cmul(g.alpha, acc);
+          if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * ldc]));
+          Cb[row + (long)col * ldc] = v;
+        }
+      }
+}
+
+template <typename R>
+__global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
+  typedef C_t<R> C;
+  const long MN = (long)g.M * g.N;
+  const int b = blockIdx.y;
+  C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
+  const bool useBeta = (g.beta.x != 0 || g.beta.y != 0);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(e % g.M), col = (int)(e / g.M);
+    C s = mk<R>(0, 0);
+    for (int sp = 0; sp < g.ksplit; ++sp) s = cadd(s, g.Cpart[((long)sp * g.batch + b) * MN + e]);
+    if (useBeta) s = cadd(s, cmul(g.beta, Cb[row + (long)col * g.ldc]));
+    Cb[row + (long)col * g.ldc] = s;
+  }
+}
+
+template <typename R>
+int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
+  GemmArgs<R> g = g0;
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return 0;
+  if (g.dA <= 0) g.dA = 1;
+  if (g.dB <= 0) g.dB = 1;
+  if (g.dC <= 0) g.dC = 1;
+  if (g.ksplit < 1) g.ksplit = 1;
+  if (g.K <= 0) {  // C = beta C
+    g.ksplit = 1;
+  }
+  long ntiles;
+  const long tm = (g.M + 63) / 64, tn = (g.N + 63) / 64;
+  if (g.tri) ntiles = tm * (tm + 1) / 2;
+  else ntiles = tm * tn;
+  dim3 grid((unsigned)ntiles, (unsigned)g.batch, (unsigned)g.ksplit);
+  if (opa == 0 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 0, 0>), grid, dim3(256), 0, st, g);
+  else if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1>), grid, dim3(256), 0, st, g);
+  else if (opa == 1 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 1, 0>), grid, dim3(256), 0, st, g);
+  else hipLaunchKernelGGL((zgemm_kernel<R, 1, 1>), grid, dim3(256), 0, st, g);
+  if (g.ksplit > 1) {
+    long MN = (long)g.M * g.N;
+    unsigned nb = (unsigned)std::min<long>((MN + 255) / 256, 1024);
+    hipLaunchKernelGGL((zgemm_reduce_kernel<R>), dim3(nb, g.batch), dim3(256), 0, st, g);
+  }
+  return (int)hipGetLastError();
+}
+
+template int zgemm<double>(const GemmArgs<double>&, int, int, hipStream_t);
+template int zgemm<float>(const GemmArgs<float>&, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Cholesky of the 64x64 diagonal block at (j0, j0) of every matrix in a batch,
+// in place (lower triangle), and Dinv = L_jj^{-1} (lower, 64x64, ld 64).
+// A non-positive or non-finite pivot raises a flag and is replaced by 1 so the
+// factorisation stays finite; the host turns the flag into an error.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void potrf_diag_kernel(C_t<R>* A, long lda, long sA, int j0,
+                                                         C_t<R>* Dinv, long sD, int* flag) {
+  typedef C_t<R> C;
+  __shared__ C Ls[64][65];  // Ls[col][row]
+  __shared__ C Xs[64][65];
+  __shared__ R piv;
+  const int tid = threadIdx.x;
+  C* Ab = A + (long)blockIdx.x * sA + j0 + (long)j0 * lda;
+  for (int e = tid; e < 4096; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    Ls[j][i] = (i >= j) ? Ab[i + (long)j * lda] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  for (int k = 0; k < 64; ++k) {
+    if (tid == 0) {
+      R d = Ls[k][k].x;
+      if (!(d > 0) || !isfinite((double)d)) {
+        atomicOr(flag, isfinite((double)d) ? PHX_FLAG_NOTPD : PHX_FLAG_NONFINITE);
+        d = 1;
+      }
+      d = sqrt(d);
+      Ls[k][k] = mk<R>(d, 0);
+      piv = d;
+    }
+    __syncthreads();
+    const R inv = (R)1 / piv;
+    if (tid > k && tid < 64) Ls[k][tid] = cscale(Ls[k][tid], inv);
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 256) {
+      const int i = e & 63, j = e >> 6;
+      if (j > k && i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(Ls[k][i], Ls[k][j]));
+    }
+    __syncthreads();
+  }
+  // Inverse of the lower factor, one row at a time; thread t owns column t.
+  for (int i = 0; i < 64; ++i) {
+    if (tid < 64) {
+      const int t = tid;
+      C v = mk<R>(0, 0);
+      if (t <= i) {
+        C s = mk<R>(t == i ? (R)1 : (R)0, 0);
+        for (int l = t; l < i; ++l) s = csub(s, cmul(Ls[l][i], Xs[t][l]));
+        const R d = Ls[i][i].x;
+        v = cscale(s, (R)1 / d);
+      }
+      Xs[t][i] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 4096; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    if (i >= j) Ab[i + (long)j * lda] = Ls[j][i];
+    Dinv[(long)blockIdx.x * sD + (long)(j0 >> 6) * 4096 + i + 64 * j] = Xs[j][i];
+  }
+}
+
+template <typename R>
+int potrf_diag(C_t<R>* A, long lda, long sA, int batch, int j0, C_t<R>* Dinv, long sD, int* flag,
+               hipStream_t st) {
+  hipLaunchKernelGGL((potrf_diag_kernel<R>), dim3(batch), dim3(256), 0, st, A, lda, sA, j0, Dinv, sD, flag);
+  return (int)hipGetLastError();
+}
+template int potrf_diag<double>(double2*, long, long, int, int, double2*, long, int*, hipStream_t);
+template int potrf_diag<float>(float2*, long, long, int, int, float2*, long, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking Cholesky of a batch of n x n Hermitian matrices (n a
+// multiple of 64; lower triangle used and overwritten by L), keeping the
+// inverted diagonal blocks of L in Dinv (batch x n/64 blocks of 64x64).
+// ---------------------------------------------------------------------------
+template <typename R>
+int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
+                  hipStream_t st) {
+  typedef C_t<R> C;
+  const int T = n / 64;
+  for (int j = 0; j < T; ++j) {
+    const int j0 = j * 64;
+    int e = potrf_diag<R>(A, lda, sA, batch, j0, Dinv, sD, flag, st);
+    if (e) return e;
+    const int rem = n - j0 - 64;
+    if (rem <= 0) break;
+    C* panel = A + (j0 + 64) + (long)j0 * lda;
+    {  // panel <- panel * Dinv_j^H   (in place: one 64-wide column tile per row tile)
+      GemmArgs<R> g{};
+      g.M = rem; g.N = 64; g.K = 64; g.batch = batch;
+      g.A = panel; g.lda = lda; g.sA = sA;
+      g.B = Dinv + (long)j * 4096; g.ldb = 64; g.sB = sD;
+      g.Cm = panel; g.ldc = lda; g.sC = sA;
+      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      e = zgemm<R>(g, 0, 1, st);
+      if (e) return e;
+    }
+    {  // trailing lower tiles -= panel panel^H
+      GemmArgs<R> g{};
+      g.M = rem; g.N = rem; g.K = 64; g.batch = batch; g.tri = 1;
+      g.A = panel; g.lda = lda; g.sA = sA;
+      g.B = panel; g.ldb = lda; g.sB = sA;
+      g.Cm = A + (j0 + 64) + (long)(j0 + 64) * lda; g.ldc = lda; g.sC = sA;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      e = zgemm<R>(g, 0, 1, st);
+      if (e) return e;
+    }
+  }
+  return 0;
+}
+template int potrf_batched<double>(double2*, int, long, long, int, double2*, long, int*, hipStream_t);
+template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Solve (L L^H) Y = B for a batch of factors from potrf_batched; B is n x nc
+// (ld ldb, batch stride sB), Z is a work buffer of the same shape.  The result
+// overwrites B.  Every block step is a GEMM with an inverted diagonal block.
+// ---------------------------------------------------------------------------
+template <typename R>
+int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st) {
+  const int T = n / 64;
+  int e;
+  for (int j = 0; j < T; ++j) {  // forward: L Z = B
+    const int j0 = j * 64;
+    {
+      GemmArgs<R> g{};
+      g.M = 64; g.N = nc; g.K = 64; g.batch = batch;
+      g.A = Dinv + (long)j * 4096; g.lda = 64; g.sA = sD;
+      g.B = B + j0; g.ldb = ldb; g.sB = sB;
+      g.Cm = Z + j0; g.ldc = ldz; g.sC = sZ;
+      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      if ((e = zgemm<R>(g, 0, 0, st))) return e;
+    }
+    if (j0 + 64 < n) {
+      GemmArgs<R> g{};
+      g.M = n - j0 - 64; g.N = nc; g.K = 64; g.batch = batch;
+      g.A = L + (j0 + 64) + (long)j0 * lda; g.lda = lda; g.sA = sL;
+      g.B = Z + j0; g.ldb = ldz; g.sB = sZ;
+      g.Cm = B + j0 + 64; g.ldc = ldb; g.sC = sB;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      if ((e = zgemm<R>(g, 0, 0, st))) return e;
+    }
+  }
+  for (int j = T - 1; j >= 0; --j) {  // backward: L^H Y = Z, Y into B
+    const int j0 = j * 64;
+    {
+      GemmArgs<R> g{};
+      g.M = 64; g.N = nc; g.K = 64; g.batch = batch;
+      g.A = Dinv + (long)j * 4096; g.lda = 64; g.sA = sD;
+      g.B = Z + j0; g.ldb = ldz; g.sB = sZ;
+      g.Cm = B + j0; g.ldc = ldb; g.sC = sB;
+      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      if ((e = zgemm<R>(g, 1, 0, st))) return e;
+    }
+    if (j0 > 0) {
+      GemmArgs<R> g{};
+      g.M = j0; g.N = nc; g.K = 64; g.batch = batch;
+      g.A = L + j0; g.lda = lda; g.sA = sL;  // rows j0..j0+63, cols 0..j0-1; op = C
+      g.B = B + j0; g.ldb = ldb; g.sB = sB;
+      g.Cm = Z; g.ldc = ldz; g.sC = sZ;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      if ((e = zgemm<R>(g, 1, 0, st))) return e;
+    }
+  }
+  return 0;
+}
+template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
+                                   long, double2*, long, long, int, hipStream_t);
+template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
+                                  long, float2*, long, long, int, hipStream_t);
+
+}  // namespace phx

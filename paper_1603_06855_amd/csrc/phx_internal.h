@@ -1,0 +1,42 @@
+// Internal interfaces between the phx kernels and the host runtime.
+#pragma once
+#include <algorithm>
+
+#include "phx_common.h"
+
+namespace phx {
+
+// Batched complex GEMM: C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], column-major.
+// Operand X of batch item b starts at X + (b / dX) * sX (dX >= 1; sX = 0 shares it).
+// tri = 1: only the lower-triangular 64x64 tiles of a square M x M output are computed.
+// ksplit > 1: the K range is split over gridDim.z, partial products go to Cpart
+// ([ksplit][batch][M*N]) and a second kernel sums them in a fixed order.
+template <typename R>
+struct GemmArgs {
+  int M, N, K;
+  int batch;
+  const C_t<R>* A; long lda, sA; int dA;
+  const C_t<R>* B; long ldb, sB; int dB;
+  C_t<R>* Cm; long ldc, sC; int dC;
+  C_t<R> alpha, beta;
+  int tri;
+  int ksplit;
+  C_t<R>* Cpart;
+};
+
+template <typename R>
+int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);
+
+template <typename R>
+int potrf_diag(C_t<R>* A, long lda, long sA, int batch, int j0, C_t<R>* Dinv, long sD, int* flag,
+               hipStream_t st);
+
+template <typename R>
+int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
+                  hipStream_t st);
+
+template <typename R>
+int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st);
+
+}  // namespace phx

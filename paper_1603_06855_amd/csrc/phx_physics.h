@@ -1,0 +1,56 @@
+// Launchers for the method-specific kernels (physics.hip) and the per-k small
+// dense kernels (small.hip).
+#pragma once
+#include "phx_common.h"
+
+namespace phx {
+
+// Non-dimensional two-phase material, affine in w = rho^p.
+struct MaterialND {
+  double p;
+  double dens0, ddens;  // density / rho_ref
+  double cvol0, dcvol;  // 1/(3K) * E_ref   (Mandel volumetric compliance)
+  double cdev0, dcdev;  // 1/(2G) * E_ref   (Mandel deviatoric compliance)
+};
+
+// Rows are the reciprocal vectors b_j of the unit-edge primitive cell.
+struct Recip {
+  double t[3][3];
+};
+
+void launch_fields(const double* rho, int nvox, const MaterialND& mat, double* F, hipStream_t st);
+void launch_dft(const double* F, int nv, int M, double v, double2* G1, double2* G2, double2* T, hipStream_t st);
+void launch_gather(const double2* T, int M, int N, int Np, double2* out, hipStream_t st);
+void launch_split_inverse(double2* inv_v, double2* inv_d, long n, hipStream_t st);
+void launch_identity(double2* X, int n, int batch, hipStream_t st);
+void launch_kvec(const double* Q, const Recip& T, int M, int N, int Np, int nk, double* Kv, hipStream_t st);
+template <typename R>
+void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
+                     int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st);
+void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
+                   double2* tr, hipStream_t st);
+void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
+                  double2* KX, long ldk, long sK, hipStream_t st);
+void launch_zero(double2* X, long n, hipStream_t st);
+void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
+template <typename R>
+void launch_residual(const double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
+                     const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
+                     hipStream_t st);
+template <typename R>
+void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st);
+void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
+                       int Np, int nk, double2* Fc, hipStream_t st);
+void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int nsel, long n, int nk, double2* Y,
+                        long sY, hipStream_t st);
+void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, double2* H2, hipStream_t st);
+void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rho, const MaterialND& mat, double v,
+                   double c2, const double* lam_nd, double lscale, double* out, hipStream_t st);
+void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st);
+
+// small.hip: per-k dense kernels on m x m (m <= 64) Gram matrices, FP64.
+void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st);
+void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta,
+                   int* sweeps, hipStream_t st);
+
+}  // namespace phx

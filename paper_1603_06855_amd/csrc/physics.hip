@@ -1,0 +1,546 @@
+// Method-specific kernels: material fields, centroid-rule Fourier coefficients,
+// Toeplitz gathers, the k-dependent operators of the mixed eigenproblem and the
+// adjoint field energies.
+//
+// Notation (paper, "Phononic band structure calculation" and "Vectorization and
+// parallel computations"): N = (2M+1)^3 plane waves n_p, K_p = T^T (Q + n_p),
+// voxel fractions s_e = (i + 1/2)/N_v.  All quantities are non-dimensional:
+// lengths by the cube edge a, stresses by phase-0 Young's modulus, density by
+// phase-0 density.
+//
+// Compliance is handled in Mandel form, D_e = c_vol,e P_vol + c_dev,e P_dev, with
+// the two isotropic projectors shared by every voxel; hence the 6N x 6N matrix
+// of Eq. (7) is Phi_vol (x) P_vol + Phi_dev (x) P_dev and its inverse splits the
+// same way.  Displacement vectors are stored component-major: row c*Np + p.
+#include "phx_common.h"
+#include "phx_internal.h"
+#include "phx_physics.h"
+
+namespace phx {
+
+// exp(sgn * i 2 pi m (i + 1/2) / nv) with exact argument reduction.
+__device__ __forceinline__ double2 voxel_phase(int m, int i, int nv, int sgn) {
+  long t = (long)m * (2 * i + 1);
+  long mod = 2L * nv;
+  t %= mod;
+  if (t < 0) t += mod;
+  double s, c;
+  sincospi((double)t / (double)nv, &s, &c);
+  return make_double2(c, sgn * s);
+}
+
+// ---------------------------------------------------------------------------
+// a1: per-voxel density and Mandel compliance channels, affine in w = rho^p.
+// ---------------------------------------------------------------------------
+__global__ void fields_kernel(const double* rho, int nvox, MaterialND mat, double* F) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nvox) return;
+  const double r = rho[e];
+  const double w = pow(r, mat.p);
+  F[e] = mat.dens0 + w * mat.ddens;
+  F[nvox + e] = mat.cvol0 + w * mat.dcvol;
+  F[2 * nvox + e] = mat.cdev0 + w * mat.dcdev;
+}
+
+// ---------------------------------------------------------------------------
+// a2: ghat(m) = v sum_e g_e exp(i 2 pi m . s_e), m in [-2M, 2M]^3, by three
+// one-axis partial sums (exactly the centroid sum, re-associated).
+// ---------------------------------------------------------------------------
+__global__ void dft_pass1(const double* F, int nv, int M2, double2* G1, int nf) {
+  // G1[f][i1][i2][m3]
+  const int L = 2 * M2 + 1;
+  const long total = (long)nf * nv * nv * L;
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int m3 = (int)(id % L);
+  const long fi = id / L;  // f, i1, i2
+  const double* src = F + fi * nv;
+  double2 acc = make_double2(0, 0);
+  for (int i3 = 0; i3 < nv; ++i3) {
+    const double2 e = voxel_phase(m3 - M2, i3, nv, +1);
+    acc.x += e.x * src[i3];
+    acc.y += e.y * src[i3];
+  }
+  G1[id] = acc;
+}
+
+__global__ void dft_pass2(const double2* G1, int nv, int M2, double2* G2, int nf) {
+  // G2[f][i1][m2][m3] = sum_i2 e(m2,i2) G1[f][i1][i2][m3]
+  const int L = 2 * M2 + 1;
+  const long total = (long)nf * nv * L * L;
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int m3 = (int)(id % L);
+  const int m2 = (int)((id / L) % L);
+  const long fi1 = id / ((long)L * L);
+  const double2* src = G1 + fi1 * (long)nv * L + m3;
+  double2 acc = make_double2(0, 0);
+  for (int i2 = 0; i2 < nv; ++i2) acc = cadd(acc, cmul(voxel_phase(m2 - M2, i2, nv, +1), src[(long)i2 * L]));
+  G2[id] = acc;
+}
+
+__global__ void dft_pass3(const double2* G2, int nv, int M2, double v, double2* T, int nf) {
+  // T[f][m1][m2][m3] = v sum_i1 e(m1,i1) G2[f][i1][m2][m3]
+  const int L = 2 * M2 + 1;
+  const long LL = (long)L * L;
+  const long total = (long)nf * L * LL;
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const long m23 = id % LL;
+  const int m1 = (int)((id / LL) % L);
+  const int f = (int)(id / (L * LL));
+  const double2* src = G2 + (long)f * nv * LL + m23;
+  double2 acc = make_double2(0, 0);
+  for (int i1 = 0; i1 < nv; ++i1) acc = cadd(acc, cmul(voxel_phase(m1 - M2, i1, nv, +1), src[(long)i1 * LL]));
+  T[id] = cscale(acc, v);
+}
+
+// ---------------------------------------------------------------------------
+// a3: G[p, q] = ghat(n_p - n_q) for the three tables (Omega_s, Phi_vol,
+// Phi_dev), Np x Np column-major, identity on the padding.
+// ---------------------------------------------------------------------------
+__global__ void gather_kernel(const double2* T, int M, int N, int Np, double2* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  const int f = blockIdx.z;
+  if (p >= Np) return;
+  double2 v;
+  if (p < N && q < N) {
+    const int L = 2 * M + 1, L2 = 4 * M + 1, M2 = 2 * M;
+    const int a1 = p / (L * L), a2 = (p / L) % L, a3 = p % L;
+    const int b1 = q / (L * L), b2 = (q / L) % L, b3 = q % L;
+    const int d1 = a1 - b1 + M2, d2 = a2 - b2 + M2, d3 = a3 - b3 + M2;
+    v = T[(long)f * L2 * L2 * L2 + ((long)d1 * L2 + d2) * L2 + d3];
+  } else {
+    v = make_double2(p == q ? 1.0 : 0.0, 0.0);
+  }
+  out[(long)f * Np * Np + p + (long)q * Np] = v;
+}
+
+// Dm = Pv^{-1} - Pd^{-1}, Bm = Pd^{-1} (in place on the two inverses).
+__global__ void split_inverse_kernel(double2* inv_v, double2* inv_d, long n) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  inv_v[e] = csub(inv_v[e], inv_d[e]);
+}
+
+__global__ void identity_kernel(double2* X, int n, int batch) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nn = (long)n * n;
+  if (e >= nn * batch) return;
+  const long r = e % nn;
+  X[e] = make_double2((r % n) == (r / n) ? 1.0 : 0.0, 0.0);
+}
+
+// K_p = T^T (Q_k + n_p) for every k of a chunk; zero on the padding.
+__global__ void kvec_kernel(const double* Q, Recip Tm, int M, int N, int Np, int nk, double* Kv) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (p >= Np || k >= nk) return;
+  double* o = Kv + ((long)k * Np + p) * 3;
+  if (p >= N) { o[0] = o[1] = o[2] = 0; return; }
+  const int L = 2 * M + 1;
+  const double n1 = p / (L * L) - M, n2 = (p / L) % L - M, n3 = p % L - M;
+  const double x1 = Q[3 * k] + n1, x2 = Q[3 * k + 1] + n2, x3 = Q[3 * k + 2] + n3;
+  for (int c = 0; c < 3; ++c) o[c] = x1 * Tm.t[0][c] + x2 * Tm.t[1][c] + x3 * Tm.t[2][c];
+}
+
+// ---------------------------------------------------------------------------
+// a6: A(k) = K(k) + sigma Omega, the Schur complement of Eq. (4) in sandwich form
+//   K_pq = (2 pi V)^2 [ (Dm_pq / 3) K_p K_q^T + (Bm_pq / 2)((K_p . K_q) I + K_q K_p^T) ]
+// written on the lower 64x64 tiles of the 3Np x 3Np matrix for every k of the
+// chunk; each tile reads Dm, Bm, Omega_s once and emits it for all k.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void assemble_kernel(const double2* Dm, const double2* Bm, const double2* Os,
+                                                        const double* Kv, int N, int Np, int nk, double c2,
+                                                        const double* sigma, C_t<R>* A, long sA, int full) {
+  const long t = blockIdx.x;
+  int ti, tj;
+  const int nt = 3 * Np / 64;
+  if (full) {
+    ti = (int)(t % nt);
+    tj = (int)(t / nt);
+  } else {
+    long r = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    ti = (int)r;
+    tj = (int)(t - r * (r + 1) / 2);
+  }
+  const int i = threadIdx.x & 63;
+  const int row = ti * 64 + i;
+  const int ci = row / Np, p = row % Np;
+  const long n3 = 3L * Np;
+  for (int jj = threadIdx.x >> 6; jj < 64; jj += 4) {
+    const int col = tj * 64 + jj;
+    const int cj = col / Np, q = col % Np;
+    const bool pad = (p >= N) || (q >= N);
+    double2 dm = make_double2(0, 0), bm = dm, os = dm;
+    if (!pad) {
+      const long o = p + (long)q * Np;
+      dm = Dm[o];
+      bm = Bm[o];
+      os = Os[o];
+    }
+    for (int k = 0; k < nk; ++k) {
+      double2 v;
+      if (pad) {
+        v = make_double2(row == col ? 1.0 : 0.0, 0.0);
+      } else {
+        const double* kp = Kv + ((long)k * Np + p) * 3;
+        const double* kq = Kv + ((long)k * Np + q) * 3;
+        const double kk = kp[0] * kq[0] + kp[1] * kq[1] + kp[2] * kq[2];
+        const double a = c2 * kp[ci] * kq[cj] / 3.0;
+        const double b = c2 * 0.5 * ((ci == cj ? kk : 0.0) + kq[ci] * kp[cj]);
+        v.x = a * dm.x + b * bm.x;
+        v.y = a * dm.y + b * bm.y;
+        if (ci == cj) {
+          v.x += sigma[k] * os.x;
+          v.y += sigma[k] * os.y;
+        }
+      }
+      A[(long)k * sA + row + (long)col * n3] = mk<R>((R)v.x, (R)v.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Strain of a block of displacement vectors: Mandel strain coefficients
+// Y = B(K_p) X_p (6 per wave) and the trace t = K_p . X_p.
+// X: 3Np x ncol per k (ld ldx, k-stride sX).  Y: Np x 6 ncol per k, t: Np x ncol.
+// ---------------------------------------------------------------------------
+__global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
+                              double2* Y, double2* tr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (p >= Np) return;
+  const double* K = Kv + ((long)k * Np + p) * 3;
+  const double2* x = X + (long)k * sX + (long)j * ldx + p;
+  const double2 x1 = x[0], x2 = x[Np], x3 = x[2 * Np];
+  const double r2 = 0.70710678118654752440;
+  double2* y = Y + (long)k * Np * 6 * ncol + (long)(6 * j) * Np + p;
+  y[0] = cscale(x1, K[0]);
+  y[Np] = cscale(x2, K[1]);
+  y[2 * Np] = cscale(x3, K[2]);
+  y[3 * Np] = cscale(cadd(cscale(x2, K[2]), cscale(x3, K[1])), r2);
+  y[4 * Np] = cscale(cadd(cscale(x1, K[2]), cscale(x3, K[0])), r2);
+  y[5 * Np] = cscale(cadd(cscale(x1, K[1]), cscale(x2, K[0])), r2);
+  tr[(long)k * Np * ncol + (long)j * Np + p] = cadd(cadd(cscale(x1, K[0]), cscale(x2, K[1])), cscale(x3, K[2]));
+}
+
+// Mandel stress coefficients S = Zy + (Zt / 3) [1,1,1,0,0,0] and the force
+// (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).
+__global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
+                             double2* KX, long ldk, long sK) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (p >= Np) return;
+  const double* K = Kv + ((long)k * Np + p) * 3;
+  const double2* z = Zy + (long)k * Np * 6 * ncol + (long)(6 * j) * Np + p;
+  const double2 t3 = cscale(Zt[(long)k * Np * ncol + (long)j * Np + p], 1.0 / 3.0);
+  const double2 s0 = cadd(z[0], t3), s1 = cadd(z[Np], t3), s2 = cadd(z[2 * Np], t3);
+  const double2 s3 = z[3 * Np], s4 = z[4 * Np], s5 = z[5 * Np];
+  const double r2 = 0.70710678118654752440;
+  double2* o = KX + (long)k * sK + (long)j * ldk + p;
+  o[0] = cscale(cadd(cscale(s0, K[0]), cscale(cadd(cscale(s4, K[2]), cscale(s5, K[1])), r2)), c2);
+  o[Np] = cscale(cadd(cscale(s1, K[1]), cscale(cadd(cscale(s3, K[2]), cscale(s5, K[0])), r2)), c2);
+  o[2 * Np] = cscale(cadd(cscale(s2, K[2]), cscale(cadd(cscale(s3, K[1]), cscale(s4, K[0])), r2)), c2);
+}
+
+// ---------------------------------------------------------------------------
+// Eigensolver helpers.
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(double2* X, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    X[e] = make_double2(0, 0);
+}
+
+__global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* idx, int s) {
+  const int j = threadIdx.x;
+  const int k = blockIdx.x;
+  if (j >= s) return;
+  X[(long)k * sX + (long)j * ldx + idx[k * s + j]] = make_double2(1.0, 0.0);
+}
+
+// R = KX - theta OX per column (one block per (column, k)); writes R into Rp in the
+// preconditioner precision, the residual norm and the relative residual
+// rn = |R| / ((|theta| + sigma) |OX|); columns with rn below act_tol are zeroed in Rp
+// so that converged directions stop feeding the search space.
+template <typename R>
+__global__ __launch_bounds__(256) void residual_kernel(const double2* Big, long n3, long mcols, long sBig,
+                                                       const double* theta, int s, const double* sigma,
+                                                       double act_tol, C_t<R>* Rp, long sR, double* rn,
+                                                       double* rnorm) {
+  const int j = blockIdx.x, k = blockIdx.y;
+  const double2* S = Big + (long)k * sBig;
+  const double2* kx = S + (mcols + j) * n3;      // KS block, column j (X part)
+  const double2* ox = S + (2 * mcols + j) * n3;  // OS block, column j
+  const double th = theta[k * s + j];
+  C_t<R>* r = Rp + (long)k * sR + (long)j * n3;
+  double a = 0, b = 0;
+  for (long i = threadIdx.x; i < n3; i += 256) {
+    const double2 o = ox[i];
+    const double2 v = csub(kx[i], cscale(o, th));
+    r[i] = mk<R>((R)v.x, (R)v.y);
+    a += cabs2(v);
+    b += cabs2(o);
+  }
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  const double rel = sqrt(sa[0]) / ((fabs(th) + sigma[k]) * sqrt(sb[0]) + 1e-300);
+  if (threadIdx.x == 0) {
+    rn[k * s + j] = rel;
+    rnorm[k * s + j] = sqrt(sa[0]);
+  }
+  if (rel < act_tol) {
+    for (long i = threadIdx.x; i < n3; i += 256) r[i] = mk<R>(0, 0);
+  }
+}
+
+template <typename R>
+__global__ void widen_kernel(const C_t<R>* Rp, long sR, long n, double2* W, long sW) {
+  const int k = blockIdx.y;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const C_t<R> v = Rp[(long)k * sR + e];
+    W[(long)k * sW + e] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a8: adjoint.  Coefficients of the displacement (3) and Mandel stress (6)
+// fields of selected Ritz vectors, on the (2M+1)^3 wave grid:
+// Fc[col][f][p], col = k * nsel + j.
+// ---------------------------------------------------------------------------
+__global__ void field_coef_kernel(const double2* X, long ldx, long sX, int nsel, const double2* Zy,
+                                  const double2* Zt, int N, int Np, double2* Fc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (p >= N) return;
+  const double2* x = X + (long)k * sX + (long)j * ldx + p;
+  const double2* z = Zy + (long)k * Np * 6 * nsel + (long)(6 * j) * Np + p;
+  const double2 t3 = cscale(Zt[(long)k * Np * nsel + (long)j * Np + p], 1.0 / 3.0);
+  double2* o = Fc + ((long)k * nsel + j) * 9 * N + p;
+  o[0] = x[0];
+  o[N] = x[Np];
+  o[2 * N] = x[2 * Np];
+  o[3 * N] = cadd(z[0], t3);
+  o[4 * N] = cadd(z[Np], t3);
+  o[5 * N] = cadd(z[2 * Np], t3);
+  o[6 * N] = z[3 * Np];
+  o[7 * N] = z[4 * Np];
+  o[8 * N] = z[5 * Np];
+}
+
+// Synthesis g_e = sum_p c_p exp(-i 2 pi n_p . s_e), first two axes:
+// H1[fc][n1][n2][i3] then H2[fc][n1][i2][i3] (fc = field x column).
+__global__ void synth_pass1(const double2* Fc, int M, int nv, long nfc, double2* H1) {
+  const int L = 2 * M + 1;
+  const long total = nfc * L * L * nv;
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int i3 = (int)(id % nv);
+  const long r = id / nv;  // fc, n1, n2
+  const double2* src = Fc + r * L;
+  double2 acc = make_double2(0, 0);
+  for (int n3 = 0; n3 < L; ++n3) acc = cadd(acc, cmul(voxel_phase(n3 - M, i3, nv, -1), src[n3]));
+  H1[id] = acc;
+}
+
+__global__ void synth_pass2(const double2* H1, int M, int nv, long nfc, double2* H2) {
+  const int L = 2 * M + 1;
+  const long total = nfc * L * nv * nv;
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int i3 = (int)(id % nv);
+  const int i2 = (int)((id / nv) % nv);
+  const long fn1 = id / ((long)nv * nv);  // fc, n1
+  const double2* src = H1 + fn1 * L * nv + i3;
+  double2 acc = make_double2(0, 0);
+  for (int n2 = 0; n2 < L; ++n2) acc = cadd(acc, cmul(voxel_phase(n2 - M, i2, nv, -1), src[(long)n2 * nv]));
+  H2[id] = acc;
+}
+
+// Last axis fused with the field energies:
+//   d lambda / d rho_e = -v w'_e [ lambda Drho |u_e|^2
+//        + (2 pi V)^2 ( Dcvol |tr sigma_e|^2 / 3 + Dcdev (|sigma_e|^2 - |tr sigma_e|^2 / 3) ) ]
+// and d omega / d rho_e = lscale * (d lambda / d rho_e) / (2 omega_SI) (0 at omega = 0).
+__global__ void energy_kernel(const double2* H2, int M, int nv, int ncols, const double* rho, MaterialND mat,
+                              double v, double c2, const double* lam_nd, double lscale, double* out) {
+  const int L = 2 * M + 1;
+  const long nvox = (long)nv * nv * nv;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (e >= nvox) return;
+  const int i1 = (int)(e / ((long)nv * nv));
+  const long i23 = e % ((long)nv * nv);
+  double2 f[9];
+  for (int q = 0; q < 9; ++q) {
+    const double2* src = H2 + ((long)col * 9 + q) * L * nv * nv + i23;
+    double2 acc = make_double2(0, 0);
+    for (int n1 = 0; n1 < L; ++n1) acc = cadd(acc, cmul(voxel_phase(n1 - M, i1, nv, -1), src[(long)n1 * nv * nv]));
+    f[q] = acc;
+  }
+  const double u2 = cabs2(f[0]) + cabs2(f[1]) + cabs2(f[2]);
+  const double2 tr = cadd(cadd(f[3], f[4]), f[5]);
+  double s2 = 0;
+  for (int q = 3; q < 9; ++q) s2 += cabs2(f[q]);
+  const double t2 = cabs2(tr) / 3.0;
+  const double lam = lam_nd[col];
+  const double r = rho[e];
+  const double wp = (mat.p == 1.0) ? 1.0 : mat.p * pow(r, mat.p - 1.0);
+  const double dlam = -v * wp * (lam * mat.ddens * u2 + c2 * (mat.dcvol * t2 + mat.dcdev * (s2 - t2)));
+  const double om = sqrt(fmax(lam, 0.0) * lscale);
+  out[(long)col * nvox + e] = (lam > 0 && om > 0) ? lscale * dlam / (2.0 * om) : 0.0;
+}
+
+// grad_e = sum_col weight[col] * sens[col][e], summed in column order.
+__global__ void weighted_sum_kernel(const double* sens, const double* wgt, int ncols, long nvox, double* grad) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= nvox) return;
+  double acc = grad[e];
+  for (int c = 0; c < ncols; ++c) acc += wgt[c] * sens[(long)c * nvox + e];
+  grad[e] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_fields(const double* rho, int nvox, const MaterialND& mat, double* F, hipStream_t st) {
+  hipLaunchKernelGGL(fields_kernel, dim3(nblk(nvox, 256)), dim3(256), 0, st, rho, nvox, mat, F);
+}
+
+void launch_dft(const double* F, int nv, int M, double v, double2* G1, double2* G2, double2* T, hipStream_t st) {
+  const int M2 = 2 * M, L = 2 * M2 + 1, nf = 3;
+  long n1 = (long)nf * nv * nv * L;
+  hipLaunchKernelGGL(dft_pass1, dim3(nblk(n1, 256)), dim3(256), 0, st, F, nv, M2, G1, nf);
+  long n2 = (long)nf * nv * L * L;
+  hipLaunchKernelGGL(dft_pass2, dim3(nblk(n2, 256)), dim3(256), 0, st, G1, nv, M2, G2, nf);
+  long n3 = (long)nf * L * L * L;
+  hipLaunchKernelGGL(dft_pass3, dim3(nblk(n3, 256)), dim3(256), 0, st, G2, nv, M2, v, T, nf);
+}
+
+void launch_gather(const double2* T, int M, int N, int Np, double2* out, hipStream_t st) {
+  hipLaunchKernelGGL(gather_kernel, dim3(nblk(Np, 256), Np, 3), dim3(256), 0, st, T, M, N, Np, out);
+}
+
+void launch_split_inverse(double2* inv_v, double2* inv_d, long n, hipStream_t st) {
+  hipLaunchKernelGGL(split_inverse_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, inv_v, inv_d, n);
+}
+
+void launch_identity(double2* X, int n, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(identity_kernel, dim3(nblk((long)n * n * batch, 256)), dim3(256), 0, st, X, n, batch);
+}
+
+void launch_kvec(const double* Q, const Recip& T, int M, int N, int Np, int nk, double* Kv, hipStream_t st) {
+  hipLaunchKernelGGL(kvec_kernel, dim3(nblk(Np, 256), nk), dim3(256), 0, st, Q, T, M, N, Np, nk, Kv);
+}
+
+template <typename R>
+void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
+                     int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st) {
+  const long nt = 3L * Np / 64;
+  const long tiles = full ? nt * nt : nt * (nt + 1) / 2;
+  hipLaunchKernelGGL((assemble_kernel<R>), dim3((unsigned)tiles), dim3(256), 0, st, Dm, Bm, Os, Kv, N, Np, nk,
+                     c2, sigma, A, sA, full);
+}
+template void launch_assemble<double>(const double2*, const double2*, const double2*, const double*, int, int, int,
+                                      double, const double*, double2*, long, int, hipStream_t);
+template void launch_assemble<float>(const double2*, const double2*, const double2*, const double*, int, int, int,
+                                     double, const double*, float2*, long, int, hipStream_t);
+
+void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
+                   double2* tr, hipStream_t st) {
+  hipLaunchKernelGGL(strain_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
+                     tr);
+}
+
+void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
+                  double2* KX, long ldk, long sK, hipStream_t st) {
+  hipLaunchKernelGGL(force_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
+                     ldk, sK);
+}
+
+void launch_zero(double2* X, long n, hipStream_t st) {
+  unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 8192);
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, st, X, n);
+}
+
+void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st) {
+  hipLaunchKernelGGL(unit_columns_kernel, dim3(nk), dim3(64), 0, st, X, ldx, sX, idx, s);
+}
+
+template <typename R>
+void launch_residual(const double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
+                     const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((residual_kernel<R>), dim3(s, nk), dim3(256), 0, st, Big, n3, mcols, sBig, theta, s, sigma,
+                     act_tol, Rp, sR, rn, rnorm);
+}
+template void launch_residual<double>(const double2*, long, long, long, const double*, int, int, const double*,
+                                      double, double2*, long, double*, double*, hipStream_t);
+template void launch_residual<float>(const double2*, long, long, long, const double*, int, int, const double*,
+                                     double, float2*, long, double*, double*, hipStream_t);
+
+template <typename R>
+void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st) {
+  unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 4096);
+  hipLaunchKernelGGL((widen_kernel<R>), dim3(nb, nk), dim3(256), 0, st, Rp, sR, n, W, sW);
+}
+template void launch_widen<double>(const double2*, long, long, double2*, long, int, hipStream_t);
+template void launch_widen<float>(const float2*, long, long, double2*, long, int, hipStream_t);
+
+void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
+                       int Np, int nk, double2* Fc, hipStream_t st) {
+  hipLaunchKernelGGL(field_coef_kernel, dim3(nblk(N, 256), nsel, nk), dim3(256), 0, st, X, ldx, sX, nsel, Zy, Zt,
+                     N, Np, Fc);
+}
+
+// Xsel[k][:, j] = X[k][:, sel[j]] for n-row columns.
+__global__ void gather_cols_kernel(const double2* X, long ldx, long sX, const int* sel, int nsel, long n,
+                                   double2* Y, long sY) {
+  const int j = blockIdx.y, k = blockIdx.z;
+  const double2* src = X + (long)k * sX + (long)sel[j] * ldx;
+  double2* dst = Y + (long)k * sY + (long)j * n;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int nsel, long n, int nk, double2* Y,
+                        long sY, hipStream_t st) {
+  unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 64);
+  hipLaunchKernelGGL(gather_cols_kernel, dim3(nb, nsel, nk), dim3(256), 0, st, X, ldx, sX, sel, nsel, n, Y, sY);
+}
+
+void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, double2* H2, hipStream_t st) {
+  const int L = 2 * M + 1;
+  const long nfc = ncols * 9;
+  hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), 0, st, Fc, M, nv, nfc, H1);
+  hipLaunchKernelGGL(synth_pass2, dim3(nblk(nfc * L * nv * nv, 256)), dim3(256), 0, st, H1, M, nv, nfc, H2);
+}
+
+void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rho, const MaterialND& mat, double v,
+                   double c2, const double* lam_nd, double lscale, double* out, hipStream_t st) {
+  const long nvox = (long)nv * nv * nv;
+  hipLaunchKernelGGL(energy_kernel, dim3(nblk(nvox, 256), ncols), dim3(256), 0, st, H2, M, nv, ncols, rho, mat, v,
+                     c2, lam_nd, lscale, out);
+}
+
+void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(weighted_sum_kernel, dim3(nblk(nvox, 256)), dim3(256), 0, st, sens, wgt, ncols, nvox, grad);
+}
+
+}  // namespace phx

@@ -1,0 +1,1054 @@
+// Host runtime and C ABI of the phx library: argument validation,
+// non-dimensionalisation, device workspaces, the per-design precompute and the
+// batched block eigensolver over k-chunks, and the adjoint.
+//
+// Eigensolver (per k-chunk, all k in lock-step, every step a batched kernel):
+//   A(k) = K(k) + sigma Omega is assembled and Cholesky-factored (FP64 or FP32);
+//   X holds s >= nbands + guard search vectors, started from plane-wave unit
+//   vectors of the smallest |K_p|.  Each iteration forms the basis S = [X W P]
+//   (W: preconditioned residuals A^{-1} R, P: previous search direction, LOBPCG),
+//   Omega-orthonormalises it twice (CholQR2 with column dropping), performs
+//   Rayleigh-Ritz with K applied in FP64 without forming it (the k-independent
+//   inverse compliance channels act on all k of the chunk in one GEMM), and
+//   stops when every wanted band's relative residual is below tolerance.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <functional>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/phx.h"
+#include "phx_internal.h"
+#include "phx_physics.h"
+
+using namespace phx;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Opts {
+  double tol[2] = {1e-8, 1e-6};
+  int maxit = 60;
+  int block = 0;
+  double shift = 0.02;
+  double drop = 1e-12;
+  double mem_gb = 64.0;
+};
+
+struct Stats {
+  int iters = 0, chunks = 0, block = 0, kchunk = 0;
+};
+
+}  // namespace
+
+struct phx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = true;
+  std::string err;
+  std::map<std::string, DevBuf> bufs;
+  int* dflag = nullptr;
+  Opts opt;
+  Stats stats;
+};
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
+      throw Fail{e_ == hipErrorOutOfMemory ? PHX_ENOMEM : PHX_EHIP};                   \
+    }                                                                                  \
+  } while (0)
+
+#define KCHK(expr)                                                                     \
+  do {                                                                                 \
+    int e_ = (int)(expr);                                                              \
+    if (e_) {                                                                          \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString((hipError_t)e_);        \
+      throw Fail{PHX_EHIP};                                                            \
+    }                                                                                  \
+  } while (0)
+
+[[noreturn]] void fail(phx_ctx* ctx, int code, const std::string& msg) {
+  ctx->err = msg;
+  throw Fail{code};
+}
+
+template <typename T>
+T* dbuf(phx_ctx* ctx, const std::string& name, size_t count) {
+  DevBuf& b = ctx->bufs[name];
+  const size_t need = std::max<size_t>(count * sizeof(T), 256);
+  if (b.bytes < need) {
+    if (b.p) HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, need);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      ctx->err = "hipMalloc(" + name + ", " + std::to_string(need) + " bytes): " + hipGetErrorString(e);
+      throw Fail{PHX_ENOMEM};
+    }
+    b.bytes = need;
+  }
+  return (T*)b.p;
+}
+
+void prim_rows(int lattice, double A[3][3]) {
+  static const double sc[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  static const double bcc[3][3] = {{-0.5, 0.5, 0.5}, {0.5, -0.5, 0.5}, {0.5, 0.5, -0.5}};
+  static const double fcc[3][3] = {{0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};
+  const double(*s)[3] = lattice == PHX_SC ? sc : (lattice == PHX_BCC ? bcc : fcc);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = s[i][j];
+}
+
+// Reciprocal rows b_j (a_i . b_j = delta_ij) and |det A|.
+double reciprocal(const double A[3][3], double T[3][3]) {
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  // inverse of A, then transpose: T[j][c] = inv(A)[c][j]
+  double inv[3][3];
+  inv[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+  inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+  inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+  inv[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+  inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+  inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+  inv[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+  inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+  inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) T[j][c] = inv[c][j];
+  return fabs(det);
+}
+
+bool material_ok(const phx_material& m) {
+  return isfinite(m.density) && isfinite(m.youngs) && isfinite(m.poisson) && m.density > 0 && m.youngs > 0 &&
+         m.poisson > -1.0 && m.poisson < 0.5;
+}
+
+void check_cell(phx_ctx* ctx, const phx_cell* c) {
+  if (!c) fail(ctx, PHX_EINVAL, "cell is NULL");
+  if (c->lattice < PHX_SC || c->lattice > PHX_FCC) fail(ctx, PHX_EINVAL, "unknown lattice");
+  if (!(c->a > 0) || !isfinite(c->a)) fail(ctx, PHX_EINVAL, "cube edge a must be positive");
+  if (c->M < 1 || c->M > 8) fail(ctx, PHX_EINVAL, "plane-wave order M must be in [1, 8]");
+  if (c->nv < 2 * c->M + 1) fail(ctx, PHX_EINVAL, "nv must be at least 2M+1 (the centroid rule aliases otherwise)");
+  if (c->nv > 256) fail(ctx, PHX_EINVAL, "nv must be at most 256");
+  if (!material_ok(c->phase0) || !material_ok(c->phase1))
+    fail(ctx, PHX_EINVAL, "material needs density > 0, Young's modulus > 0, Poisson ratio in (-1, 1/2)");
+  if (!(c->simp_p >= 1.0) || !isfinite(c->simp_p)) fail(ctx, PHX_EINVAL, "simp_p must be >= 1");
+}
+
+void check_rho(phx_ctx* ctx, const double* rho, long n) {
+  if (!rho) fail(ctx, PHX_EINVAL, "rho is NULL");
+  for (long e = 0; e < n; ++e)
+    if (!isfinite(rho[e]) || rho[e] < 0) fail(ctx, PHX_EINVAL, "rho must be finite and non-negative");
+}
+
+void check_q(phx_ctx* ctx, const double* q, int nk) {
+  if (nk < 1) fail(ctx, PHX_EINVAL, "nk must be positive");
+  if (!q) fail(ctx, PHX_EINVAL, "q is NULL");
+  for (long i = 0; i < 3L * nk; ++i)
+    if (!isfinite(q[i])) fail(ctx, PHX_EINVAL, "q must be finite");
+}
+
+// ---------------------------------------------------------------------------
+// Per-design precompute (k-independent): fields, Fourier tables, Toeplitz
+// gathers, and the inverse compliance channels.
+// ---------------------------------------------------------------------------
+struct Design {
+  phx_cell cell;
+  int M, N, Np, n3, nv;
+  long nvox;
+  double V, v, c2, lscale, sigma, dens_min;
+  MaterialND mat;
+  Recip rec;
+  std::string tag;
+  double* rho_d = nullptr;
+  double2* tab = nullptr;  // 3 x (4M+1)^3
+  double2* Os = nullptr;   // Np x Np
+  double2* Dm = nullptr;   // Pv^{-1} - Pd^{-1}
+  double2* Bm = nullptr;   // Pd^{-1}
+};
+
+MaterialND nondim(const phx_cell& c) {
+  const double E0 = c.phase0.youngs, r0 = c.phase0.density;
+  auto ch = [&](const phx_material& m, double& dens, double& cv, double& cd) {
+    const double E = m.youngs / E0, nu = m.poisson;
+    const double K = E / (3.0 * (1.0 - 2.0 * nu)), G = E / (2.0 * (1.0 + nu));
+    dens = m.density / r0;
+    cv = 1.0 / (3.0 * K);
+    cd = 1.0 / (2.0 * G);
+  };
+  double d0, v0, s0, d1, v1, s1;
+  ch(c.phase0, d0, v0, s0);
+  ch(c.phase1, d1, v1, s1);
+  MaterialND m;
+  m.p = c.simp_p;
+  m.dens0 = d0; m.ddens = d1 - d0;
+  m.cvol0 = v0; m.dcvol = v1 - v0;
+  m.cdev0 = s0; m.dcdev = s1 - s0;
+  return m;
+}
+
+void setup_geometry(const phx_cell& cell, Design& d) {
+  d.cell = cell;
+  d.M = cell.M;
+  const int L = 2 * cell.M + 1;
+  d.N = L * L * L;
+  d.Np = (d.N + 63) / 64 * 64;
+  d.n3 = 3 * d.Np;
+  d.nv = cell.nv;
+  d.nvox = (long)cell.nv * cell.nv * cell.nv;
+  double A[3][3], T[3][3];
+  prim_rows(cell.lattice, A);
+  d.V = reciprocal(A, T);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) d.rec.t[i][j] = T[i][j];
+  d.v = d.V / (double)d.nvox;
+  d.c2 = (2.0 * M_PI * d.V) * (2.0 * M_PI * d.V);
+  d.lscale = cell.phase0.youngs / (cell.phase0.density * cell.a * cell.a);
+  d.mat = nondim(cell);
+}
+
+// rho_host: the design on the host (used for the shift scale and bounds);
+// rho_dev: the same design already on the device, or NULL to upload.
+void setup_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, const double* rho_dev, Design& d,
+                  const std::string& tag) {
+  setup_geometry(cell, d);
+  d.tag = tag;
+  hipStream_t st = ctx->stream;
+  // shift scale and the density lower bound from the host copy
+  double wsum = 0;
+  for (long e = 0; e < d.nvox; ++e) wsum += pow(rho_host[e], cell.simp_p);
+  const double wbar = wsum / d.nvox;
+  double dens_mean = d.mat.dens0 + wbar * d.mat.ddens;
+  double cdev_mean = d.mat.cdev0 + wbar * d.mat.dcdev;
+  double bmin = 1e300;
+  for (int j = 0; j < 3; ++j)
+    bmin = std::min(bmin, d.rec.t[j][0] * d.rec.t[j][0] + d.rec.t[j][1] * d.rec.t[j][1] + d.rec.t[j][2] * d.rec.t[j][2]);
+  const double lam_scale = 4.0 * M_PI * M_PI * bmin * (1.0 / (2.0 * cdev_mean)) / dens_mean;
+  d.sigma = ctx->opt.shift * lam_scale;
+  {
+    double lo = 1e300;
+    for (long e = 0; e < d.nvox; ++e) lo = std::min(lo, d.mat.dens0 + pow(rho_host[e], cell.simp_p) * d.mat.ddens);
+    d.dens_min = lo;
+  }
+
+  if (rho_dev) {
+    d.rho_d = const_cast<double*>(rho_dev);
+  } else {
+    d.rho_d = dbuf<double>(ctx, tag + "rho", d.nvox);
+    HIPCHK(hipMemcpyAsync(d.rho_d, rho_host, d.nvox * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  const int M2 = 2 * d.M, L2 = 2 * M2 + 1;
+  double* F = dbuf<double>(ctx, "F", 3 * d.nvox);
+  double2* G1 = dbuf<double2>(ctx, "G1", 3L * d.nv * d.nv * L2);
+  double2* G2 = dbuf<double2>(ctx, "G2", 3L * d.nv * L2 * L2);
+  d.tab = dbuf<double2>(ctx, tag + "tab", 3L * L2 * L2 * L2);
+  launch_fields(d.rho_d, (int)d.nvox, d.mat, F, st);
+  launch_dft(F, d.nv, d.M, d.v, G1, G2, d.tab, st);
+  KCHK(hipGetLastError());
+
+  const long NN = (long)d.Np * d.Np;
+  double2* ops = dbuf<double2>(ctx, tag + "ops", 3 * NN);  // Os, Pv, Pd -> Os, factors
+  double2* inv = dbuf<double2>(ctx, tag + "inv", 2 * NN);  // Pv^{-1} - Pd^{-1}, Pd^{-1}
+  double2* work = dbuf<double2>(ctx, "phi_work", 2 * NN);
+  double2* dinv = dbuf<double2>(ctx, "phi_dinv", 2L * (d.Np / 64) * 4096);
+  launch_gather(d.tab, d.M, d.N, d.Np, ops, st);
+  KCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
+  KCHK(potrf_batched<double>(ops + NN, d.Np, d.Np, NN, 2, dinv, (long)(d.Np / 64) * 4096, ctx->dflag, st));
+  launch_identity(inv, d.Np, 2, st);
+  KCHK(potrs_batched<double>(ops + NN, d.Np, d.Np, NN, 2, dinv, (long)(d.Np / 64) * 4096, inv, d.Np, NN, work,
+                             d.Np, NN, d.Np, st));
+  launch_split_inverse(inv, inv + NN, NN, st);
+  KCHK(hipGetLastError());
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flag) fail(ctx, PHX_ENOTPD, "compliance Fourier matrix is not positive definite");
+  d.Os = ops;
+  d.Dm = inv;
+  d.Bm = inv + NN;
+}
+
+// ---------------------------------------------------------------------------
+// Eigensolver over one chunk of k-points.
+// ---------------------------------------------------------------------------
+struct ChunkOut {
+  std::vector<double> theta;  // nk x s (non-dimensional lambda)
+  std::vector<double> rnorm;  // nk x s
+  std::vector<double> rn;     // nk x s
+  int iters = 0;
+  bool converged = false;
+};
+
+struct Solver {
+  phx_ctx* ctx;
+  Design* d;
+  int nk, nb, s, m, prec;
+  long n3, sBig;
+  double2 *Big, *Big2;
+  double* Kv;
+  double* sigma_d;
+  double2 *Y, *Tr, *Zy, *Zt;
+  double2 *G, *Gpart, *C0, *Cr;
+  int* keep;
+  double *theta, *rn, *rnorm;
+  void* A;     // nk x n3 x n3 (prec)
+  void* Dinv;  // nk x n3/64 x 4096 (prec)
+  void* Rp;    // nk x n3 x s
+  void* Zp;
+  int ksplit;
+};
+
+template <typename R>
+void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
+          const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
+          int ksplit = 1, C_t<R>* Cpart = nullptr) {
+  GemmArgs<R> g{};
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.A = A; g.lda = lda; g.sA = sA; g.dA = dA;
+  g.B = B; g.ldb = ldb; g.sB = sB; g.dB = dB;
+  g.Cm = Cm; g.ldc = ldc; g.sC = sC; g.dC = 1;
+  g.alpha = alpha; g.beta = beta;
+  g.ksplit = ksplit; g.Cpart = Cpart;
+  KCHK(zgemm<R>(g, opa, opb, ctx->stream));
+}
+
+const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
+
+// K and Omega applied (FP64, matrix-free) to ncol columns of the S block of Big
+// starting at column c0; results to the same columns of the KS and OS blocks.
+void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
+  phx_ctx* ctx = sv.ctx;
+  Design& d = *sv.d;
+  hipStream_t st = ctx->stream;
+  const long n3 = sv.n3, m = sv.m;
+  double2* X = Big + c0 * n3;
+  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st);
+  KCHK(hipGetLastError());
+  const long sy = (long)d.Np * 6 * ncol, st_ = (long)d.Np * ncol;
+  gemm<double>(ctx, 0, 0, d.Np, 6 * ncol, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO);
+  gemm<double>(ctx, 0, 0, d.Np, ncol, d.Np, sv.nk, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, st_, 1, sv.Zt, d.Np, st_, ONE, ZERO);
+  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st);
+  KCHK(hipGetLastError());
+  // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
+  gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
+               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO);
+}
+
+void gram(Solver& sv, double2* Big, int block) {
+  // G_k = S_k^H (block_k), block 1 = KS, 2 = OS
+  const long n3 = sv.n3, m = sv.m;
+  gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
+               m * m, ONE, ZERO, sv.ksplit, sv.Gpart);
+}
+
+void cholqr(Solver& sv) {
+  phx_ctx* ctx = sv.ctx;
+  const long n3 = sv.n3, m = sv.m;
+  gram(sv, sv.Big, 2);
+  launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream);
+  KCHK(hipGetLastError());
+  // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
+  gemm<double>(ctx, 0, 0, n3, m, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.C0, m, m * m, 3, sv.Big2, n3, n3 * m, ONE,
+               ZERO);
+  std::swap(sv.Big, sv.Big2);
+}
+
+void rayleigh_ritz(Solver& sv) {
+  phx_ctx* ctx = sv.ctx;
+  const long n3 = sv.n3, m = sv.m, s = sv.s;
+  gram(sv, sv.Big, 1);
+  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, nullptr, ctx->stream);
+  KCHK(hipGetLastError());
+  // X <- [S] Cr ; P <- [W P] Cr[s:m]
+  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
+               ZERO);
+  gemm<double>(ctx, 0, 0, n3, s, m - s, 3 * sv.nk, sv.Big + s * n3, n3, n3 * m, 1, sv.Cr + s, m, m * s, 3,
+               sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO);
+  std::swap(sv.Big, sv.Big2);
+}
+
+template <typename R>
+void precondition(Solver& sv) {
+  phx_ctx* ctx = sv.ctx;
+  const long n3 = sv.n3;
+  KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
+                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream));
+  launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream);
+  KCHK(hipGetLastError());
+}
+
+int choose_block(phx_ctx* ctx, int nb, int N) {
+  int s = ctx->opt.block > 0 ? ctx->opt.block : std::min(21, nb + std::max(8, nb));
+  s = std::min(s, 3 * N);
+  return s;
+}
+
+long per_k_bytes(const Design& d, int s, int prec) {
+  const long n3 = d.n3, m = 3 * s;
+  const long pc = prec == PHX_FP64 ? 16 : 8;
+  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + 2L * 3 * n3 * m * 16 + 2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
+}
+
+template <typename R>
+void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, ChunkOut& out, Solver& sv) {
+  hipStream_t st = ctx->stream;
+  const int prec = std::is_same<R, double>::value ? PHX_FP64 : PHX_MIXED;
+  const int s = choose_block(ctx, nb, d.N), m = 3 * s;
+  const long n3 = d.n3;
+  sv.ctx = ctx; sv.d = &d; sv.nk = nk; sv.nb = nb; sv.s = s; sv.m = m; sv.prec = prec;
+  sv.n3 = n3;
+  sv.sBig = 3 * n3 * m;
+  sv.Big = dbuf<double2>(ctx, "Big", (long)nk * sv.sBig);
+  sv.Big2 = dbuf<double2>(ctx, "Big2", (long)nk * sv.sBig);
+  sv.Kv = dbuf<double>(ctx, "Kv", (long)nk * d.Np * 3);
+  sv.sigma_d = dbuf<double>(ctx, "sigma", nk);
+  sv.Y = dbuf<double2>(ctx, "Y", (long)nk * d.Np * 6 * s);
+  sv.Tr = dbuf<double2>(ctx, "Tr", (long)nk * d.Np * s);
+  sv.Zy = dbuf<double2>(ctx, "Zy", (long)nk * d.Np * 6 * s);
+  sv.Zt = dbuf<double2>(ctx, "Zt", (long)nk * d.Np * s);
+  sv.ksplit = (int)std::max<long>(1, std::min<long>(16, n3 / 256));
+  sv.G = dbuf<double2>(ctx, "G", (long)nk * m * m);
+  sv.Gpart = dbuf<double2>(ctx, "Gpart", (long)sv.ksplit * nk * m * m);
+  sv.C0 = dbuf<double2>(ctx, "C0", (long)nk * m * m);
+  sv.Cr = dbuf<double2>(ctx, "Cr", (long)nk * m * s);
+  sv.keep = dbuf<int>(ctx, "keep", (long)nk * m);
+  sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
+  sv.rn = dbuf<double>(ctx, "rn", (long)nk * s);
+  sv.rnorm = dbuf<double>(ctx, "rnorm", (long)nk * s);
+  sv.A = dbuf<C_t<R>>(ctx, "A", (long)nk * n3 * n3);
+  sv.Dinv = dbuf<C_t<R>>(ctx, "Dinv", (long)nk * (n3 / 64) * 4096);
+  sv.Rp = dbuf<C_t<R>>(ctx, "Rp", (long)nk * n3 * s);
+  sv.Zp = dbuf<C_t<R>>(ctx, "Zp", (long)nk * n3 * s);
+  double* qd = dbuf<double>(ctx, "q", 3L * nk);
+  int* idx_d = dbuf<int>(ctx, "idx", (long)nk * s);
+
+  // k-vectors, shift, initial plane-wave vectors
+  HIPCHK(hipMemcpyAsync(qd, q, 3L * nk * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_kvec(qd, d.rec, d.M, d.N, d.Np, nk, sv.Kv, st);
+  std::vector<double> sig(nk, d.sigma);
+  HIPCHK(hipMemcpyAsync(sv.sigma_d, sig.data(), nk * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<int> idx((size_t)nk * s);
+  {
+    const int L = 2 * d.M + 1;
+    std::vector<int> ord(d.N);
+    std::vector<double> k2(d.N);
+    for (int k = 0; k < nk; ++k) {
+      for (int p = 0; p < d.N; ++p) {
+        const double n1 = p / (L * L) - d.M, n2 = (p / L) % L - d.M, n3_ = p % L - d.M;
+        const double x[3] = {q[3 * k] + n1, q[3 * k + 1] + n2, q[3 * k + 2] + n3_};
+        double kk = 0;
+        for (int c = 0; c < 3; ++c) {
+          const double kc = x[0] * d.rec.t[0][c] + x[1] * d.rec.t[1][c] + x[2] * d.rec.t[2][c];
+          kk += kc * kc;
+        }
+        k2[p] = kk;
+      }
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return k2[a] < k2[b]; });
+      for (int j = 0; j < s; ++j) idx[(size_t)k * s + j] = (j % 3) * d.Np + ord[j / 3];
+    }
+  }
+  HIPCHK(hipMemcpyAsync(idx_d, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
+
+  // Pencil A = K + sigma Omega and its Cholesky factor.
+  launch_assemble<R>(d.Dm, d.Bm, d.Os, sv.Kv, d.N, d.Np, nk, d.c2, sv.sigma_d, (C_t<R>*)sv.A, n3 * n3, 0, st);
+  KCHK(hipGetLastError());
+  HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
+  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st));
+
+  // Initial block: unit vectors; W = P = 0.
+  launch_zero(sv.Big, (long)nk * sv.sBig, st);
+  launch_unit_columns(sv.Big, n3, sv.sBig, idx_d, s, nk, st);
+  KCHK(hipGetLastError());
+  apply_ops(sv, sv.Big, 0, s);
+
+  const double tol = ctx->opt.tol[prec];
+  std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
+  out.converged = false;
+  int it = 0;
+  for (it = 0; it <= ctx->opt.maxit; ++it) {
+    cholqr(sv);
+    cholqr(sv);
+    rayleigh_ritz(sv);
+    launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, 0.1 * tol, (C_t<R>*)sv.Rp, n3 * s,
+                       sv.rn, sv.rnorm, st);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (it == 0) {
+      int flag = 0;
+      HIPCHK(hipMemcpy(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost));
+      if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
+    }
+    double worst = 0;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < nb; ++j) worst = std::max(worst, rn_h[(size_t)k * s + j]);
+    if (!(worst == worst)) fail(ctx, PHX_EHIP, "eigensolver produced a non-finite residual");
+    if (worst <= tol) {
+      out.converged = true;
+      break;
+    }
+    if (it == ctx->opt.maxit) break;
+    precondition<R>(sv);
+    apply_ops(sv, sv.Big, s, s);
+  }
+  out.iters = it;
+  out.theta.resize((size_t)nk * s);
+  out.rnorm.resize((size_t)nk * s);
+  out.rn = rn_h;
+  HIPCHK(hipMemcpyAsync(out.theta.data(), sv.theta, out.theta.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out.rnorm.data(), sv.rnorm, out.rnorm.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Adjoint of the converged chunk: d omega / d rho_e for bands sel (0-based) of
+// every k of the chunk into out (device, (nk * nsel) x nvox).
+void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
+  phx_ctx* ctx = sv.ctx;
+  Design& d = *sv.d;
+  hipStream_t st = ctx->stream;
+  const int nsel = (int)sel.size(), nk = sv.nk;
+  const long n3 = sv.n3;
+  int* sel_d = dbuf<int>(ctx, "sel", nsel);
+  HIPCHK(hipMemcpyAsync(sel_d, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
+  double2* Xs = dbuf<double2>(ctx, "Xsel", (long)nk * n3 * nsel);
+  launch_gather_cols(sv.Big, n3, sv.sBig, sel_d, nsel, n3, nk, Xs, n3 * nsel, st);
+  double* lam = dbuf<double>(ctx, "lam_sel", (long)nk * nsel);
+  std::vector<double> th((size_t)nk * sv.s), lh((size_t)nk * nsel);
+  HIPCHK(hipMemcpyAsync(th.data(), sv.theta, th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nsel; ++j) lh[(size_t)k * nsel + j] = th[(size_t)k * sv.s + sel[j]];
+  HIPCHK(hipMemcpyAsync(lam, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  double2* Y = dbuf<double2>(ctx, "Ysel", (long)nk * d.Np * 6 * nsel);
+  double2* Tr = dbuf<double2>(ctx, "Trsel", (long)nk * d.Np * nsel);
+  double2* Zy = dbuf<double2>(ctx, "Zysel", (long)nk * d.Np * 6 * nsel);
+  double2* Zt = dbuf<double2>(ctx, "Ztsel", (long)nk * d.Np * nsel);
+  launch_strain(Xs, n3, n3 * nsel, sv.Kv, d.Np, nsel, nk, Y, Tr, st);
+  const long sy = (long)d.Np * 6 * nsel, st_ = (long)d.Np * nsel;
+  gemm<double>(ctx, 0, 0, d.Np, 6 * nsel, d.Np, nk, d.Bm, d.Np, 0, 1, Y, d.Np, sy, 1, Zy, d.Np, sy, ONE, ZERO);
+  gemm<double>(ctx, 0, 0, d.Np, nsel, d.Np, nk, d.Dm, d.Np, 0, 1, Tr, d.Np, st_, 1, Zt, d.Np, st_, ONE, ZERO);
+  const long ncols = (long)nk * nsel;
+  const int L = 2 * d.M + 1;
+  double2* Fc = dbuf<double2>(ctx, "Fc", ncols * 9 * d.N);
+  double2* H1 = dbuf<double2>(ctx, "H1", ncols * 9 * L * L * d.nv);
+  double2* H2 = dbuf<double2>(ctx, "H2", ncols * 9 * L * (long)d.nv * d.nv);
+  launch_field_coef(Xs, n3, n3 * nsel, nsel, Zy, Zt, d.N, d.Np, nk, Fc, st);
+  launch_synth(Fc, d.M, d.nv, ncols, H1, H2, st);
+  launch_energy(H2, d.M, d.nv, (int)ncols, d.rho_d, d.mat, d.v, d.c2, lam, d.lscale, out, st);
+  KCHK(hipGetLastError());
+}
+
+// Runs the eigensolver over k-chunks; fills omega (+ err bounds) and, when sel is
+// non-empty, the per-(k, band) sensitivities into sens_dev (device).
+int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int prec, double* omega, double* ebound,
+               const std::vector<int>& sel, double* sens_dev) {
+  const int s = choose_block(ctx, nb, d.N);
+  const long per = per_k_bytes(d, s, prec);
+  int kc = (int)std::max<long>(1, std::min<long>(nk, (long)(ctx->opt.mem_gb * 1073741824.0) / per));
+  ctx->stats.block = s;
+  ctx->stats.kchunk = kc;
+  ctx->stats.chunks = 0;
+  ctx->stats.iters = 0;
+  bool conv = true;
+  for (int k0 = 0; k0 < nk; k0 += kc) {
+    const int nkc = std::min(kc, nk - k0);
+    ChunkOut co;
+    Solver sv{};
+    if (prec == PHX_FP64) solve_chunk<double>(ctx, d, q + 3L * k0, nkc, nb, co, sv);
+    else solve_chunk<float>(ctx, d, q + 3L * k0, nkc, nb, co, sv);
+    ctx->stats.chunks++;
+    ctx->stats.iters = std::max(ctx->stats.iters, co.iters);
+    conv = conv && co.converged;
+    for (int k = 0; k < nkc; ++k)
+      for (int j = 0; j < nb; ++j) {
+        const double lam = co.theta[(size_t)k * s + j];
+        const double om = sqrt(std::max(lam, 0.0) * d.lscale);
+        if (omega) omega[(size_t)(k0 + k) * nb + j] = om;
+        if (ebound) {
+          const double bl = d.lscale * co.rnorm[(size_t)k * s + j] / sqrt(d.V * d.dens_min);
+          ebound[(size_t)(k0 + k) * nb + j] = om > 0 ? std::min(bl / (2 * om), sqrt(bl)) : sqrt(bl);
+        }
+      }
+    if (!sel.empty()) adjoint_chunk(sv, sel, sens_dev + (long)k0 * sel.size() * d.nvox);
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!conv) {
+    ctx->err = "eigensolver reached maxit before every band met the tolerance";
+    return PHX_ENOCONV;
+  }
+  return PHX_OK;
+}
+
+int guard(phx_ctx* ctx, const std::function<int()>& f) {
+  if (!ctx) return PHX_EINVAL;
+  ctx->err.clear();
+  try {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) {
+      ctx->err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+      return PHX_EHIP;
+    }
+    return f();
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& ex) {
+    ctx->err = ex.what();
+    return PHX_EHIP;
+  }
+}
+
+void check_bands(phx_ctx* ctx, const phx_cell* cell, int nb, int nsens, const int* band_no) {
+  const int L = 2 * cell->M + 1;
+  if (nb < 1 || nb > 16 || nb > 3 * L * L * L) fail(ctx, PHX_EINVAL, "nbands must be in [1, min(16, 3N)]");
+  if (nsens < 0) fail(ctx, PHX_EINVAL, "nsens must be non-negative");
+  if (nsens > 0 && !band_no) fail(ctx, PHX_EINVAL, "band_no is NULL");
+  for (int j = 0; j < nsens; ++j)
+    if (band_no[j] < 1 || band_no[j] > nb) fail(ctx, PHX_EINVAL, "band_no entries must be in [1, nbands]");
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int phx_create(phx_ctx** out, int hip_device) {
+  if (!out) return PHX_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return PHX_EHIP;
+  if (hip_device < 0 || hip_device >= n) return PHX_EINVAL;
+  phx_ctx* c = new phx_ctx();
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
+      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) {
+    delete c;
+    return PHX_EHIP;
+  }
+  *out = c;
+  return PHX_OK;
+}
+
+int phx_destroy(phx_ctx* ctx) {
+  if (!ctx) return PHX_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (ctx->dflag) (void)hipFree(ctx->dflag);
+  if (ctx->stream && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return PHX_OK;
+}
+
+const char* phx_last_error(const phx_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+int phx_set_option(phx_ctx* ctx, const char* key, double v) {
+  if (!ctx || !key) return PHX_EINVAL;
+  std::string k(key);
+  auto bad = [&]() {
+    ctx->err = "bad value for option " + k;
+    return PHX_EINVAL;
+  };
+  if (k == "tol_fp64") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.tol[0] = v; }
+  else if (k == "tol_mixed") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.tol[1] = v; }
+  else if (k == "maxit") { if (!(v >= 1 && v <= 10000)) return bad(); ctx->opt.maxit = (int)v; }
+  else if (k == "block") { if (!(v == 0 || (v >= 2 && v <= 21))) return bad(); ctx->opt.block = (int)v; }
+  else if (k == "shift") { if (!(v > 0 && v < 1e6)) return bad(); ctx->opt.shift = v; }
+  else if (k == "drop") { if (!(v > 0 && v < 1e-2)) return bad(); ctx->opt.drop = v; }
+  else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
+  else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
+  return PHX_OK;
+}
+
+int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
+  if (!ctx || !key || !value) return PHX_EINVAL;
+  std::string k(key);
+  if (k == "iters") *value = ctx->stats.iters;
+  else if (k == "chunks") *value = ctx->stats.chunks;
+  else if (k == "block") *value = ctx->stats.block;
+  else if (k == "kchunk") *value = ctx->stats.kchunk;
+  else return PHX_EINVAL;
+  return PHX_OK;
+}
+
+int phx_validate(const phx_cell* cell, const double* rho, int nk, const double* q, int nbands, int nsens,
+                 const int* band_no, char* msg, int msglen) {
+  phx_ctx tmp;
+  phx_ctx* ctx = &tmp;
+  int rc = PHX_OK;
+  try {
+    check_cell(ctx, cell);
+    if (rho) check_rho(ctx, rho, (long)cell->nv * cell->nv * cell->nv);
+    if (q || nk) check_q(ctx, q, nk);
+    if (nbands || nsens) check_bands(ctx, cell, nbands, nsens, band_no);
+  } catch (const Fail& f) {
+    rc = f.code;
+  }
+  if (msg && msglen > 0) {
+    strncpy(msg, ctx->err.c_str(), (size_t)msglen - 1);
+    msg[msglen - 1] = 0;
+  }
+  return rc;
+}
+
+int phx_kpath(phx_lattice lattice, const char* path, int nk, double* q_out) {
+  if (!q_out || lattice < PHX_SC || lattice > PHX_FCC) return PHX_EINVAL;
+  struct Pt { char c; double x, y, z; };
+  static const Pt sc[] = {{'G', 0, 0, 0}, {'X', 0, 0.5, 0}, {'M', 0.5, 0.5, 0}, {'R', 0.5, 0.5, 0.5}};
+  static const Pt bcc[] = {{'G', 0, 0, 0}, {'H', 0, 0, 1}, {'N', 0.5, 0.5, 0}, {'P', 0.5, 0.5, 0.5}};
+  static const Pt fcc[] = {{'G', 0, 0, 0}, {'X', 0, 1, 0}, {'W', 0.5, 1, 0}, {'K', 0.75, 0.75, 0}, {'L', 0.5, 0.5, 0.5},
+                           {'U', 0.25, 1, 0.25}};
+  const Pt* tab = lattice == PHX_SC ? sc : (lattice == PHX_BCC ? bcc : fcc);
+  const int ntab = lattice == PHX_FCC ? 6 : 4;
+  const char* def = lattice == PHX_SC ? "GXMGRX|MR" : (lattice == PHX_BCC ? "GHNGPH|PN" : "GXWKGLUWLK|UX");
+  std::string p = path ? path : def;
+  // branches of vertices
+  std::vector<std::vector<const Pt*>> br(1);
+  for (char ch : p) {
+    if (ch == '|') { br.emplace_back(); continue; }
+    const Pt* f = nullptr;
+    for (int i = 0; i < ntab; ++i)
+      if (tab[i].c == ch) f = &tab[i];
+    if (!f) return PHX_EINVAL;
+    br.back().push_back(f);
+  }
+  br.erase(std::remove_if(br.begin(), br.end(), [](const std::vector<const Pt*>& b) { return b.empty(); }), br.end());
+  int nvert = 0;
+  for (auto& b : br) nvert += (int)b.size();
+  if (nvert == 0 || nk < nvert) return PHX_EINVAL;
+  std::vector<double> len;
+  for (auto& b : br)
+    for (size_t i = 0; i + 1 < b.size(); ++i) {
+      const double dx = b[i + 1]->x - b[i]->x, dy = b[i + 1]->y - b[i]->y, dz = b[i + 1]->z - b[i]->z;
+      len.push_back(sqrt(dx * dx + dy * dy + dz * dz));
+    }
+  const int extra = nk - nvert;
+  std::vector<int> cnt(len.size(), 0);
+  const double tot = std::accumulate(len.begin(), len.end(), 0.0);
+  if (!len.empty() && tot > 0) {
+    std::vector<double> share(len.size());
+    int used = 0;
+    for (size_t i = 0; i < len.size(); ++i) {
+      share[i] = extra * len[i] / tot;
+      cnt[i] = (int)floor(share[i]);
+      used += cnt[i];
+    }
+    std::vector<size_t> ord(len.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](size_t a, size_t b) { return (share[a] - cnt[a]) > (share[b] - cnt[b]); });
+    for (int r = 0; r < extra - used; ++r) cnt[ord[r]]++;
+  } else if (extra > 0) {
+    return PHX_EINVAL;
+  }
+  double A[3][3];
+  prim_rows(lattice, A);
+  int o = 0;
+  size_t si = 0;
+  auto emit = [&](double x, double y, double z) {
+    for (int j = 0; j < 3; ++j) q_out[3 * o + j] = A[j][0] * x + A[j][1] * y + A[j][2] * z;
+    ++o;
+  };
+  for (auto& b : br) {
+    emit(b[0]->x, b[0]->y, b[0]->z);
+    for (size_t i = 0; i + 1 < b.size(); ++i, ++si) {
+      const Pt *u = b[i], *v = b[i + 1];
+      const int c = cnt[si];
+      for (int j = 1; j <= c; ++j) {
+        const double t = (double)j / (c + 1);
+        emit(u->x + (v->x - u->x) * t, u->y + (v->y - u->y) * t, u->z + (v->z - u->z) * t);
+      }
+      emit(v->x, v->y, v->z);
+    }
+  }
+  return o == nk ? PHX_OK : PHX_EINVAL;
+}
+
+int phx_fourier(phx_ctx* ctx, const phx_cell* cell, const double* rho, double* out) {
+  return guard(ctx, [&]() {
+    check_cell(ctx, cell);
+    if (!out) fail(ctx, PHX_EINVAL, "out is NULL");
+    const long nvox = (long)cell->nv * cell->nv * cell->nv;
+    check_rho(ctx, rho, nvox);
+    Design d;
+    setup_geometry(*cell, d);
+    double* rd = dbuf<double>(ctx, "rho", nvox);
+    HIPCHK(hipMemcpyAsync(rd, rho, nvox * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const int L2 = 4 * d.M + 1;
+    const long nt = (long)L2 * L2 * L2;
+    double* F = dbuf<double>(ctx, "F", 3 * nvox);
+    double2* G1 = dbuf<double2>(ctx, "G1", 3L * d.nv * d.nv * L2);
+    double2* G2 = dbuf<double2>(ctx, "G2", 3L * d.nv * L2 * L2);
+    double2* T = dbuf<double2>(ctx, "tab", 3 * nt);
+    launch_fields(rd, (int)nvox, d.mat, F, ctx->stream);
+    launch_dft(F, d.nv, d.M, d.v, G1, G2, T, ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, T, 3 * nt * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double a = cell->a;
+    const double sc[3] = {a * a * a * cell->phase0.density, a * a * a / cell->phase0.youngs,
+                          a * a * a / cell->phase0.youngs};
+    for (int f = 0; f < 3; ++f)
+      for (long i = 0; i < 2 * nt; ++i) out[f * 2 * nt + i] *= sc[f];
+    return PHX_OK;
+  });
+}
+
+int phx_schur(phx_ctx* ctx, const phx_cell* cell, const double* rho, const double* q, double* out) {
+  return guard(ctx, [&]() {
+    check_cell(ctx, cell);
+    if (!out) fail(ctx, PHX_EINVAL, "out is NULL");
+    const long nvox = (long)cell->nv * cell->nv * cell->nv;
+    check_rho(ctx, rho, nvox);
+    check_q(ctx, q, 1);
+    Design d;
+    setup_design(ctx, *cell, rho, nullptr, d, "d0:");
+    hipStream_t st = ctx->stream;
+    double* qd = dbuf<double>(ctx, "q", 3);
+    double* Kv = dbuf<double>(ctx, "Kv", (long)d.Np * 3);
+    double* sg = dbuf<double>(ctx, "sigma", 1);
+    const long n3 = d.n3;
+    double2* A = dbuf<double2>(ctx, "A", n3 * n3);
+    HIPCHK(hipMemcpyAsync(qd, q, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(sg, 0, sizeof(double), st));
+    launch_kvec(qd, d.rec, d.M, d.N, d.Np, 1, Kv, st);
+    launch_assemble<double>(d.Dm, d.Bm, d.Os, Kv, d.N, d.Np, 1, d.c2, sg, A, n3 * n3, 1, st);
+    KCHK(hipGetLastError());
+    std::vector<double2> h(n3 * n3);
+    HIPCHK(hipMemcpyAsync(h.data(), A, h.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const long n = 3L * d.N;
+    const double sc = cell->a * cell->phase0.youngs;
+    for (int cj = 0; cj < 3; ++cj)
+      for (int qq = 0; qq < d.N; ++qq)
+        for (int ci = 0; ci < 3; ++ci)
+          for (int p = 0; p < d.N; ++p) {
+            const double2 v = h[(ci * d.Np + p) + (long)(cj * d.Np + qq) * n3];
+            const long o = (3L * p + ci) + (3L * qq + cj) * n;
+            out[2 * o] = v.x * sc;
+            out[2 * o + 1] = v.y * sc;
+          }
+    return PHX_OK;
+  });
+}
+
+static int bands_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+                      phx_precision prec, int nsens, const int* band_no, double* omega, double* ebound,
+                      double* domega, const double* weight, double* grad) {
+  check_cell(ctx, cell);
+  const long nvox = (long)cell->nv * cell->nv * cell->nv;
+  check_rho(ctx, rho, nvox);
+  check_q(ctx, q, nk);
+  check_bands(ctx, cell, nbands, nsens, band_no);
+  if (prec != PHX_FP64 && prec != PHX_MIXED) fail(ctx, PHX_EINVAL, "unknown precision");
+  Design d;
+  setup_design(ctx, *cell, rho, nullptr, d, "d0:");
+  std::vector<int> sel;
+  for (int j = 0; j < nsens; ++j) sel.push_back(band_no[j] - 1);
+  double* sens = nullptr;
+  if (nsens > 0) sens = dbuf<double>(ctx, "sens", (long)nk * nsens * nvox);
+  std::vector<double> om_tmp;
+  if (!omega) {
+    om_tmp.resize((size_t)nk * nbands);
+    omega = om_tmp.data();
+  }
+  int rc = run_design(ctx, d, q, nk, nbands, prec, omega, ebound, sel, sens);
+  if (rc != PHX_OK && rc != PHX_ENOCONV) return rc;
+  hipStream_t st = ctx->stream;
+  if (nsens > 0 && domega) {
+    HIPCHK(hipMemcpyAsync(domega, sens, (long)nk * nsens * nvox * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  if (nsens > 0 && grad) {
+    double* w = dbuf<double>(ctx, "wgt", (long)nk * nsens);
+    double* g = dbuf<double>(ctx, "grad", nvox);
+    HIPCHK(hipMemcpyAsync(w, weight, (long)nk * nsens * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(g, 0, nvox * sizeof(double), st));
+    launch_weighted_sum(sens, w, nk * nsens, nvox, g, st);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(grad, g, nvox * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return rc;
+}
+
+int phx_bands(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+              phx_precision prec, double* omega, double* err_bound) {
+  return guard(ctx, [&]() {
+    if (!omega) fail(ctx, PHX_EINVAL, "omega is NULL");
+    return bands_impl(ctx, cell, rho, nk, q, nbands, prec, 0, nullptr, omega, err_bound, nullptr, nullptr, nullptr);
+  });
+}
+
+int phx_sens(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+             phx_precision prec, int nsens, const int* band_no, double* omega, double* domega_drho) {
+  return guard(ctx, [&]() {
+    if (!omega || !domega_drho) fail(ctx, PHX_EINVAL, "omega or domega_drho is NULL");
+    if (nsens < 1) fail(ctx, PHX_EINVAL, "nsens must be at least 1");
+    return bands_impl(ctx, cell, rho, nk, q, nbands, prec, nsens, band_no, omega, nullptr, domega_drho, nullptr,
+                      nullptr);
+  });
+}
+
+int phx_adjoint(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
+                phx_precision prec, int nsens, const int* band_no, const double* weight, double* omega,
+                double* grad) {
+  return guard(ctx, [&]() {
+    if (!weight || !grad) fail(ctx, PHX_EINVAL, "weight or grad is NULL");
+    if (nsens < 1) fail(ctx, PHX_EINVAL, "nsens must be at least 1");
+    for (long i = 0; i < (long)nk * nsens; ++i)
+      if (!isfinite(weight[i])) fail(ctx, PHX_EINVAL, "weights must be finite");
+    return bands_impl(ctx, cell, rho, nk, q, nbands, prec, nsens, band_no, omega, nullptr, nullptr, weight, grad);
+  });
+}
+
+int phx_bands_batch(phx_ctx* ctx, int ndesign, const phx_cell* cells, const double* const* rho, int nk,
+                    const double* q, int nbands, phx_precision prec, int nsens, const int* band_no,
+                    double* const* omega, double* const* domega) {
+  return guard(ctx, [&]() {
+    if (ndesign < 1 || !cells || !rho || !omega) fail(ctx, PHX_EINVAL, "ndesign, cells, rho and omega are required");
+    int worst = PHX_OK;
+    for (int i = 0; i < ndesign; ++i) {
+      if (!omega[i]) fail(ctx, PHX_EINVAL, "omega[d] is NULL");
+      const int rc = bands_impl(ctx, &cells[i], rho[i], nk, q, nbands, prec, (domega && domega[i]) ? nsens : 0,
+                                band_no, omega[i], nullptr, domega ? domega[i] : nullptr, nullptr, nullptr);
+      if (rc < 0 && rc != PHX_ENOCONV) return rc;
+      if (rc == PHX_ENOCONV) worst = rc;
+    }
+    return worst;
+  });
+}
+
+int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host, int nbands,
+                 phx_precision prec, int nsens, const int* band_no, double* omega_dev, double* domega_dev,
+                 void* stream) {
+  return guard(ctx, [&]() {
+    check_cell(ctx, cell);
+    if (!rho_dev || !omega_dev) fail(ctx, PHX_EINVAL, "rho_dev and omega_dev are required");
+    check_q(ctx, q_host, nk);
+    check_bands(ctx, cell, nbands, nsens, band_no);
+    if (nsens > 0 && !domega_dev) fail(ctx, PHX_EINVAL, "domega_dev is NULL");
+    if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const long nvox = (long)cell->nv * cell->nv * cell->nv;
+    std::vector<double> rh(nvox);
+    HIPCHK(hipMemcpyAsync(rh.data(), rho_dev, nvox * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    check_rho(ctx, rh.data(), nvox);
+    Design d;
+    setup_design(ctx, *cell, rh.data(), rho_dev, d, "d0:");
+    std::vector<int> sel;
+    for (int j = 0; j < nsens; ++j) sel.push_back(band_no[j] - 1);
+    std::vector<double> om((size_t)nk * nbands);
+    const int rc = run_design(ctx, d, q_host, nk, nbands, prec, om.data(), nullptr, sel, domega_dev);
+    HIPCHK(hipMemcpyAsync(omega_dev, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return rc;
+  });
+}
+
+int phx_zgemm(phx_ctx* ctx, phx_precision prec, char opa, char opb, int m, int n, int k, const double* alpha,
+              const double* A, long lda, long strideA, const double* B, long ldb, long strideB, const double* beta,
+              double* C, long ldc, long strideC, int batch) {
+  return guard(ctx, [&]() {
+    if (m < 0 || n < 0 || k < 0 || batch < 1 || !alpha || !beta || !A || !B || !C)
+      fail(ctx, PHX_EINVAL, "bad zgemm arguments");
+    const int oa = (opa == 'C' || opa == 'c') ? 1 : 0, ob = (opb == 'C' || opb == 'c') ? 1 : 0;
+    if ((opa != 'N' && opa != 'n' && !oa) || (opb != 'N' && opb != 'n' && !ob)) fail(ctx, PHX_EINVAL, "op must be N or C");
+    const long ra = oa ? k : m, ca = oa ? m : k, rb = ob ? n : k, cb = ob ? k : n;
+    if (lda < std::max<long>(1, ra) || ldb < std::max<long>(1, rb) || ldc < std::max<long>(1, m))
+      fail(ctx, PHX_EINVAL, "leading dimension too small");
+    const long na = strideA * (batch - 1) + lda * (ca - 1) + ra;
+    const long nbb = strideB * (batch - 1) + ldb * (cb - 1) + rb;
+    const long nc = strideC * (batch - 1) + ldc * (n - 1) + m;
+    hipStream_t st = ctx->stream;
+    auto run = [&](auto tag) {
+      typedef decltype(tag) R;
+      typedef C_t<R> Cx;
+      std::vector<Cx> ha(na), hb(nbb), hc(nc);
+      for (long i = 0; i < na; ++i) ha[i] = mk<R>((R)A[2 * i], (R)A[2 * i + 1]);
+      for (long i = 0; i < nbb; ++i) hb[i] = mk<R>((R)B[2 * i], (R)B[2 * i + 1]);
+      for (long i = 0; i < nc; ++i) hc[i] = mk<R>((R)C[2 * i], (R)C[2 * i + 1]);
+      Cx* da = dbuf<Cx>(ctx, "tA", na);
+      Cx* db = dbuf<Cx>(ctx, "tB", nbb);
+      Cx* dc = dbuf<Cx>(ctx, "tC", nc);
+      HIPCHK(hipMemcpyAsync(da, ha.data(), na * sizeof(Cx), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(db, hb.data(), nbb * sizeof(Cx), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dc, hc.data(), nc * sizeof(Cx), hipMemcpyHostToDevice, st));
+      gemm<R>(ctx, oa, ob, m, n, k, batch, da, lda, strideA, 1, db, ldb, strideB, 1, dc, ldc, strideC,
+              mk<R>((R)alpha[0], (R)alpha[1]), mk<R>((R)beta[0], (R)beta[1]));
+      HIPCHK(hipMemcpyAsync(hc.data(), dc, nc * sizeof(Cx), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (long i = 0; i < nc; ++i) {
+        C[2 * i] = hc[i].x;
+        C[2 * i + 1] = hc[i].y;
+      }
+    };
+    if (prec == PHX_FP64) run(double());
+    else run(float());
+    return PHX_OK;
+  });
+}
+
+int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, const double* A, double* B) {
+  return guard(ctx, [&]() {
+    if (n < 64 || n % 64 || nrhs < 1 || batch < 1 || !A || !B) fail(ctx, PHX_EINVAL, "bad zposv arguments");
+    hipStream_t st = ctx->stream;
+    const long na = (long)n * n * batch, nb = (long)n * nrhs * batch;
+    auto run = [&](auto tag) {
+      typedef decltype(tag) R;
+      typedef C_t<R> Cx;
+      std::vector<Cx> ha(na), hb(nb);
+      for (long i = 0; i < na; ++i) ha[i] = mk<R>((R)A[2 * i], (R)A[2 * i + 1]);
+      for (long i = 0; i < nb; ++i) hb[i] = mk<R>((R)B[2 * i], (R)B[2 * i + 1]);
+      Cx* da = dbuf<Cx>(ctx, "tA", na);
+      Cx* db = dbuf<Cx>(ctx, "tB", nb);
+      Cx* dz = dbuf<Cx>(ctx, "tC", nb);
+      Cx* dinv = dbuf<Cx>(ctx, "tD", (long)batch * (n / 64) * 4096);
+      HIPCHK(hipMemcpyAsync(da, ha.data(), na * sizeof(Cx), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(db, hb.data(), nb * sizeof(Cx), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
+      KCHK(potrf_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, ctx->dflag, st));
+      KCHK(potrs_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, db, n, (long)n * nrhs, dz, n,
+                            (long)n * nrhs, nrhs, st));
+      int flag = 0;
+      HIPCHK(hipMemcpyAsync(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb.data(), db, nb * sizeof(Cx), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (flag) fail(ctx, PHX_ENOTPD, "matrix is not positive definite");
+      for (long i = 0; i < nb; ++i) {
+        B[2 * i] = hb[i].x;
+        B[2 * i + 1] = hb[i].y;
+      }
+    };
+    if (prec == PHX_FP64) run(double());
+    else run(float());
+    return PHX_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+"""ctypes binding of libphx.so (argument marshalling only; every step runs in the HIP library).
+
+The C ABI is declared in ``include/phx.h``.  Loading fails loudly when the
+library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char, c_char_p, c_double, c_int, c_long, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphx.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENOTPD = 0, -1, -2, -3, -4, -5
+LATTICE = {"SC": 0, "BCC": 1, "FCC": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class PhxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"phx error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("density", c_double), ("youngs", c_double), ("poisson", c_double)]
+
+
+class Cell(ctypes.Structure):
+    _fields_ = [("lattice", c_int), ("a", c_double), ("nv", c_int), ("M", c_int),
+                ("phase0", Material), ("phase1", Material), ("simp_p", c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libphx.so (raises if it is missing: no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m "
+                          "paper_1603_06855_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    D = POINTER(c_double)
+    I = POINTER(c_int)
+    P = c_void_p
+    sig = {
+        "phx_create": (c_int, [POINTER(c_void_p), c_int]),
+        "phx_destroy": (c_int, [P]),
+        "phx_last_error": (c_char_p, [P]),
+        "phx_set_option": (c_int, [P, c_char_p, c_double]),
+        "phx_get_stat": (c_int, [P, c_char_p, D]),
+        "phx_kpath": (c_int, [c_int, c_char_p, c_int, D]),
+        "phx_validate": (c_int, [POINTER(Cell), D, c_int, D, c_int, c_int, I, POINTER(c_char), c_int]),
+        "phx_fourier": (c_int, [P, POINTER(Cell), D, D]),
+        "phx_schur": (c_int, [P, POINTER(Cell), D, D, D]),
+        "phx_bands": (c_int, [P, POINTER(Cell), D, c_int, D, c_int, c_int, D, D]),
+        "phx_sens": (c_int, [P, POINTER(Cell), D, c_int, D, c_int, c_int, c_int, I, D, D]),
+        "phx_adjoint": (c_int, [P, POINTER(Cell), D, c_int, D, c_int, c_int, c_int, I, D, D, D]),
+        "phx_bands_batch": (c_int, [P, c_int, POINTER(Cell), POINTER(D), c_int, D, c_int, c_int, c_int, I,
+                                    POINTER(D), POINTER(D)]),
+        "phx_sens_dev": (c_int, [P, POINTER(Cell), c_void_p, c_int, D, c_int, c_int, c_int, I, c_void_p,
+                                 c_void_p, c_void_p]),
+        "phx_zgemm": (c_int, [P, c_int, c_char, c_char, c_int, c_int, c_int, D, D, c_long, c_long, D, c_long,
+                              c_long, D, D, c_long, c_long, c_int]),
+        "phx_zposv": (c_int, [P, c_int, c_int, c_int, c_int, D, D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_int))
+
+
+def make_cell(cell) -> Cell:
+    """Convert a ``synth.Cell``-like object (lattice name, a, nv, M, phase0/1, simp_p)."""
+    lat = cell.lattice if isinstance(cell.lattice, int) else LATTICE[cell.lattice]
+    m0, m1 = cell.phase0, cell.phase1
+    return Cell(lat, float(cell.a), int(cell.nv), int(cell.M),
+                Material(m0.density, m0.youngs, m0.poisson), Material(m1.density, m1.youngs, m1.poisson),
+                float(cell.simp_p))
+
+
+def kpath(lattice: str, nk: int, path: Optional[str] = None) -> np.ndarray:
+    lib = load()
+    q = np.zeros((nk, 3))
+    rc = lib.phx_kpath(LATTICE[lattice], path.encode() if path else None, nk, _dptr(q))
+    if rc != OK:
+        raise PhxError(rc, "phx_kpath rejected its arguments")
+    return q
+
+
+def validate(cell, rho=None, q=None, nbands=0, band_no=()):
+    lib = load()
+    c = make_cell(cell)
+    msg = ctypes.create_string_buffer(256)
+    r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    nk = 0 if q is None else qq.size // 3
+    b = np.ascontiguousarray(band_no, dtype=np.int32)
+    rc = lib.phx_validate(byref(c), _dptr(r) if r is not None else None, nk, _dptr(qq) if qq is not None else None,
+                          int(nbands), len(b), _iptr(b) if len(b) else None, msg, 256)
+    return rc, msg.value.decode()
+
+
+class Context:
+    """One HIP device, one stream, grow-only device workspaces."""
+
+    def __init__(self, device: int = 0, **options):
+        self.lib = load()
+        h = c_void_p()
+        rc = self.lib.phx_create(byref(h), device)
+        if rc != OK:
+            raise PhxError(rc, "phx_create failed (no HIP device?)")
+        self.h = h
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.phx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int, allow=()):
+        if rc != OK and rc not in allow:
+            raise PhxError(rc, self.lib.phx_last_error(self.h).decode())
+        return rc
+
+    def set_option(self, key: str, value: float):
+        self._check(self.lib.phx_set_option(self.h, key.encode(), float(value)))
+
+    def stat(self, key: str) -> float:
+        v = c_double()
+        self._check(self.lib.phx_get_stat(self.h, key.encode(), byref(v)))
+        return v.value
+
+    # -------------------------------------------------------------- stages
+    def fourier(self, cell, rho) -> np.ndarray:
+        c = make_cell(cell)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        L2 = 4 * c.M + 1
+        out = np.zeros(3 * L2 ** 3 * 2)
+        self._check(self.lib.phx_fourier(self.h, byref(c), _dptr(r), _dptr(out)))
+        return out.view(np.complex128).reshape(3, L2, L2, L2)
+
+    def schur(self, cell, rho, q) -> np.ndarray:
+        c = make_cell(cell)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(3)
+        n = 3 * (2 * c.M + 1) ** 3
+        out = np.zeros(2 * n * n)
+        self._check(self.lib.phx_schur(self.h, byref(c), _dptr(r), _dptr(qq), _dptr(out)))
+        return out.view(np.complex128).reshape(n, n, order="F")
+
+    # -------------------------------------------------------------- band structure
+    def bands(self, cell, rho, q, nbands: int, precision: str = "fp64", bounds: bool = False,
+              allow_noconv: bool = False):
+        c = make_cell(cell)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        om = np.zeros((nk, nbands))
+        eb = np.zeros((nk, nbands))
+        rc = self.lib.phx_bands(self.h, byref(c), _dptr(r), nk, _dptr(qq), nbands, PRECISION[precision],
+                                _dptr(om), _dptr(eb))
+        self._check(rc, (ENOCONV,) if allow_noconv else ())
+        return (om, eb) if bounds else om
+
+    def sens(self, cell, rho, q, nbands: int, band_no: Sequence[int], precision: str = "fp64",
+             allow_noconv: bool = False):
+        c = make_cell(cell)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        om = np.zeros((nk, nbands))
+        dw = np.zeros((nk, len(b), r.size))
+        rc = self.lib.phx_sens(self.h, byref(c), _dptr(r), nk, _dptr(qq), nbands, PRECISION[precision], len(b),
+                               _iptr(b), _dptr(om), _dptr(dw))
+        self._check(rc, (ENOCONV,) if allow_noconv else ())
+        return om, dw
+
+    def adjoint(self, cell, rho, q, nbands: int, band_no: Sequence[int], weight, precision: str = "fp64"):
+        c = make_cell(cell)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        w = np.ascontiguousarray(weight, dtype=np.float64).reshape(nk, len(b))
+        om = np.zeros((nk, nbands))
+        g = np.zeros(r.size)
+        self._check(self.lib.phx_adjoint(self.h, byref(c), _dptr(r), nk, _dptr(qq), nbands, PRECISION[precision],
+                                         len(b), _iptr(b), _dptr(w), _dptr(om), _dptr(g)))
+        return om, g
+
+    def bands_batch(self, cells, rhos, q, nbands: int, precision: str = "fp64", band_no: Sequence[int] = ()):
+        nd = len(cells)
+        carr = (Cell * nd)(*[make_cell(c) for c in cells])
+        rs = [np.ascontiguousarray(r, dtype=np.float64).reshape(-1) for r in rhos]
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        oms = [np.zeros((nk, nbands)) for _ in range(nd)]
+        dws = [np.zeros((nk, len(b), r.size)) for r in rs] if len(b) else None
+        DP = POINTER(c_double)
+        rp = (DP * nd)(*[_dptr(r) for r in rs])
+        op = (DP * nd)(*[_dptr(o) for o in oms])
+        dp = (DP * nd)(*[_dptr(d) for d in dws]) if dws is not None else None
+        self._check(self.lib.phx_bands_batch(self.h, nd, carr, rp, nk, _dptr(qq), nbands, PRECISION[precision],
+                                             len(b), _iptr(b) if len(b) else None, op, dp))
+        return (oms, dws) if dws is not None else oms
+
+    def sens_dev(self, cell, rho_t, q, nbands: int, band_no: Sequence[int], precision: str = "fp64"):
+        """torch CUDA tensors in and out: rho_t (nv^3 float64 on the device)."""
+        import torch
+        c = make_cell(cell)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        rho_t = rho_t.contiguous().to(torch.float64)
+        om = torch.empty((nk, nbands), dtype=torch.float64, device=rho_t.device)
+        dw = torch.empty((nk, len(b), rho_t.numel()), dtype=torch.float64, device=rho_t.device)
+        stream = torch.cuda.current_stream(rho_t.device).cuda_stream
+        self._check(self.lib.phx_sens_dev(self.h, byref(c), c_void_p(rho_t.data_ptr()), nk, _dptr(qq), nbands,
+                                          PRECISION[precision], len(b), _iptr(b), c_void_p(om.data_ptr()),
+                                          c_void_p(dw.data_ptr()), c_void_p(stream)))
+        return om, dw
+
+    # -------------------------------------------------------------- dense building blocks
+    def zgemm(self, opa: str, opb: str, A, B, C=None, alpha=1.0, beta=0.0, precision: str = "fp64"):
+        """Batched: A (batch, ., .) etc. complex arrays (column-major semantics via Fortran order)."""
+        A = np.asarray(A, dtype=np.complex128)
+        B = np.asarray(B, dtype=np.complex128)
+        if A.ndim == 2:
+            A, B = A[None], B[None]
+            C = None if C is None else np.asarray(C)[None]
+            squeeze = True
+        else:
+            squeeze = False
+        batch = A.shape[0]
+        m = A.shape[1] if opa == "N" else A.shape[2]
+        k = A.shape[2] if opa == "N" else A.shape[1]
+        n = B.shape[2] if opb == "N" else B.shape[1]
+        Af = np.concatenate([np.asfortranarray(a).reshape(-1, order="F") for a in A])
+        Bf = np.concatenate([np.asfortranarray(b).reshape(-1, order="F") for b in B])
+        if C is None:
+            C = np.zeros((batch, m, n), dtype=np.complex128)
+        Cf = np.concatenate([np.asfortranarray(c).reshape(-1, order="F") for c in np.asarray(C, np.complex128)])
+        Ad, Bd, Cd = Af.view(np.float64), Bf.view(np.float64), Cf.view(np.float64).copy()
+        al = np.array([np.real(alpha), np.imag(alpha)], dtype=np.float64)
+        be = np.array([np.real(beta), np.imag(beta)], dtype=np.float64)
+        self._check(self.lib.phx_zgemm(self.h, PRECISION[precision], opa.encode(), opb.encode(), m, n, k, _dptr(al),
+                                       _dptr(np.ascontiguousarray(Ad)), A.shape[1], A.shape[1] * A.shape[2],
+                                       _dptr(np.ascontiguousarray(Bd)), B.shape[1], B.shape[1] * B.shape[2],
+                                       _dptr(be), _dptr(Cd), m, m * n, batch))
+        out = Cd.view(np.complex128).reshape(batch, n, m).transpose(0, 2, 1)
+        return out[0] if squeeze else out
+
+    def zposv(self, A, B, precision: str = "fp64"):
+        A = np.asarray(A, dtype=np.complex128)
+        B = np.asarray(B, dtype=np.complex128)
+        batch, n, _ = A.shape
+        nrhs = B.shape[2]
+        Af = np.concatenate([np.asfortranarray(a).reshape(-1, order="F") for a in A]).view(np.float64)
+        Bf = np.concatenate([np.asfortranarray(b).reshape(-1, order="F") for b in B]).view(np.float64).copy()
+        self._check(self.lib.phx_zposv(self.h, PRECISION[precision], n, nrhs, batch, _dptr(np.ascontiguousarray(Af)),
+                                       _dptr(Bf)))
+        return Bf.view(np.complex128).reshape(batch, nrhs, n).transpose(0, 2, 1)
