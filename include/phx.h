@@ -189,6 +189,19 @@ int phx_zgemm(phx_ctx* ctx, phx_precision prec, char opa, char opb, int m, int n
  * n must be a multiple of 64.  PHX_ENOTPD if a pivot is not positive. */
 int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, const double* A, double* B);
 
+/* Small dense kernels of the block eigensolver (one workgroup per batch item,
+ * order m <= 64, FP64, column-major (re, im) pairs).
+ * phx_small_orth: from a Hermitian Gram matrix G = S^H W S of a basis S, the
+ * coefficients C0 (m x m, upper triangular) with (S C0)^H W (S C0) = I on the
+ * kept columns; columns are first scaled to unit norm and a column whose
+ * Cholesky pivot falls below `drop` is dropped (keep = 0, its C0 column zero).
+ * phx_small_eig: the s lowest eigenpairs of the Hermitian G (m x m) restricted
+ * to the columns with keep != 0, by cyclic Jacobi: C (m x s) eigenvectors,
+ * theta (s) ascending. */
+int phx_small_orth(phx_ctx* ctx, int m, int batch, const double* G, double drop, double* C0, int* keep);
+int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const int* keep, double* C,
+                  double* theta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,8 +9,8 @@
 //
 // Complex products are built from four real MFMA products.  The MFMA is fed the
 // B tile as its first operand and the A tile as its second, so the 16x16 result
-// it returns is C transposed: each lane then holds four consecutive *columns* of
-// one row, and lanes 0..15 cover 16 consecutive rows, which makes the stores to
+// it returns is C transposed: each lane then holds four *columns* of one row,
+// and lanes 0..15 cover 16 consecutive rows, which makes the stores to
 // column-major C contiguous.
 #include "phx_common.h"
 #include "phx_internal.h"
@@ -139,7 +139,9 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wr * 32 + x * 16 + (lane & 15);
-        const int col = col0 + wc * 32 + y * 16 + ((lane >> 4) << 2) + r;
+        // MFMA result layout (lane l, register r): FP32 holds row 4(l/16)+r, FP64 holds
+        // row l/16 + 4r of the 16x16 block, column l%16 in both (here rows are C columns).
+        const int col = col0 + wc * 32 + y * 16 + (sizeof(R) == 8 ? ((lane >> 4) + 4 * r) : (((lane >> 4) << 2) + r));
         if (row < g.M && col < g.N) {
           C acc = mk<R>(cr[x][y][r], ci[x][y][r]);
           C v = cmul(g.alpha, acc);

@@ -12,6 +12,7 @@
 //   inverse compliance channels act on all k of the chunk in one GEMM), and
 //   stops when every wanted band's relative residual is below tolerance.
 #include <math.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -60,6 +61,7 @@ struct phx_ctx {
   int* dflag = nullptr;
   Opts opt;
   Stats stats;
+  bool trace = false;
 };
 
 namespace {
@@ -506,6 +508,21 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     double worst = 0;
     for (int k = 0; k < nk; ++k)
       for (int j = 0; j < nb; ++j) worst = std::max(worst, rn_h[(size_t)k * s + j]);
+    if (ctx->trace) {
+      std::vector<int> kh((size_t)nk * m);
+      std::vector<double> th((size_t)nk * s);
+      HIPCHK(hipMemcpy(kh.data(), sv.keep, kh.size() * sizeof(int), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(th.data(), sv.theta, th.size() * sizeof(double), hipMemcpyDeviceToHost));
+      int kept = 0;
+      for (int j = 0; j < m; ++j) kept += kh[j];
+      double wall = 0;
+      for (double v : rn_h) wall = std::max(wall, v);
+      fprintf(stderr, "[phx] it %d worst(wanted) %.3e worst(all) %.3e kept(k0) %d theta(k0)", it, worst, wall, kept);
+      for (int j = 0; j < std::min(s, 6); ++j) fprintf(stderr, " %.6g", th[j]);
+      fprintf(stderr, " rn(k0)");
+      for (int j = 0; j < std::min(s, 6); ++j) fprintf(stderr, " %.2e", rn_h[j]);
+      fprintf(stderr, "\n");
+    }
     if (!(worst == worst)) fail(ctx, PHX_EHIP, "eigensolver produced a non-finite residual");
     if (worst <= tol) {
       out.converged = true;
@@ -645,6 +662,8 @@ int phx_create(phx_ctx** out, int hip_device) {
   if (hip_device < 0 || hip_device >= n) return PHX_EINVAL;
   phx_ctx* c = new phx_ctx();
   c->device = hip_device;
+  const char* tr = getenv("PHX_TRACE");
+  c->trace = tr && tr[0] && tr[0] != '0';
   if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
       hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) {
     delete c;
@@ -1010,6 +1029,46 @@ int phx_zgemm(phx_ctx* ctx, phx_precision prec, char opa, char opb, int m, int n
     };
     if (prec == PHX_FP64) run(double());
     else run(float());
+    return PHX_OK;
+  });
+}
+
+int phx_small_orth(phx_ctx* ctx, int m, int batch, const double* G, double drop, double* C0, int* keep) {
+  return guard(ctx, [&]() {
+    if (m < 1 || m > 64 || batch < 1 || !G || !C0 || !keep || !(drop > 0)) fail(ctx, PHX_EINVAL, "bad arguments");
+    hipStream_t st = ctx->stream;
+    const long n = (long)m * m * batch;
+    double2* dg = dbuf<double2>(ctx, "tA", n);
+    double2* dc = dbuf<double2>(ctx, "tB", n);
+    int* dk = dbuf<int>(ctx, "tK", (long)m * batch);
+    HIPCHK(hipMemcpyAsync(dg, G, n * sizeof(double2), hipMemcpyHostToDevice, st));
+    launch_chol_drop(dg, m, batch, drop, dc, dk, st);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(C0, dc, n * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(keep, dk, (long)m * batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PHX_OK;
+  });
+}
+
+int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const int* keep, double* C,
+                  double* theta) {
+  return guard(ctx, [&]() {
+    if (m < 1 || m > 64 || s < 1 || s > m || batch < 1 || !G || !keep || !C || !theta)
+      fail(ctx, PHX_EINVAL, "bad arguments");
+    hipStream_t st = ctx->stream;
+    const long n = (long)m * m * batch;
+    double2* dg = dbuf<double2>(ctx, "tA", n);
+    double2* dc = dbuf<double2>(ctx, "tB", (long)m * s * batch);
+    int* dk = dbuf<int>(ctx, "tK", (long)m * batch);
+    double* dt = dbuf<double>(ctx, "tT", (long)s * batch);
+    HIPCHK(hipMemcpyAsync(dg, G, n * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dk, keep, (long)m * batch * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_rr_eig(dg, dk, m, s, batch, dc, dt, nullptr, st);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(C, dc, (long)m * s * batch * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(theta, dt, (long)s * batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return PHX_OK;
   });
 }

@@ -9,7 +9,9 @@
 // rr_eig: Rayleigh-Ritz on an Omega-orthonormal basis: eigen-decomposition of the
 //   Hermitian G = S^H K S by cyclic parallel Jacobi (round-robin pair ordering),
 //   returning the s lowest eigenpairs.  Dropped columns get a large diagonal so they
-//   are never selected.
+//   are never selected.  An off-diagonal entry below 1e-18 of its two diagonal
+//   entries is set to zero instead of rotated, and the sweeps stop once a sweep
+//   performs no rotation (or the off-diagonal mass is negligible).
 #include "phx_common.h"
 #include "phx_physics.h"
 
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
   __shared__ int order[64];
   __shared__ int used[64];
   __shared__ int stop;
+  __shared__ int rotated;
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
   const double2* Gk = G + (long)k * m * m;
@@ -157,7 +160,10 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
       }
       __syncthreads();
     }
-    if (tid == 0) stop = (red[0] <= 1e-32 * red2[0]) ? 1 : 0;
+    if (tid == 0) {
+      stop = (red[0] <= 1e-32 * red2[0] || (sw > 0 && !rotated)) ? 1 : 0;
+      rotated = 0;
+    }
     __syncthreads();
     if (stop) break;
     for (int r = 0; r < mm - 1; ++r) {
@@ -167,10 +173,21 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
         else { p = (r + tid) % (mm - 1); q = (r - tid + mm - 1) % (mm - 1); }
         const double a = As[p][p].x, b = As[q][q].x;
         const double2 c = As[q][p];  // row p, col q
-        const double ac = sqrt(cabs2(c));
+        // |c| scaled so that its square cannot underflow into subnormals.
+        const double cm = fmax(fabs(c.x), fabs(c.y));
+        double ac = 0.0;
+        if (cm > 0) {
+          const double xr = c.x / cm, yr = c.y / cm;
+          ac = cm * sqrt(xr * xr + yr * yr);
+        }
         double cs = 1.0, sn = 0.0;
         double2 ph = make_double2(1.0, 0.0);
-        if (ac > 1e-300) {
+        if (!(ac > 1e-300 && ac > 1e-18 * (fabs(a) + fabs(b)))) {
+          // below the rounding floor of its diagonal: set to zero (this pair owns both entries)
+          As[q][p] = make_double2(0.0, 0.0);
+          As[p][q] = make_double2(0.0, 0.0);
+        } else {
+          rotated = 1;
           ph = make_double2(c.x / ac, -c.y / ac);
           const double tau = (b - a) / (2.0 * ac);
           double t;

@@ -71,6 +71,8 @@ def load():
         "phx_zgemm": (c_int, [P, c_int, c_char, c_char, c_int, c_int, c_int, D, D, c_long, c_long, D, c_long,
                               c_long, D, D, c_long, c_long, c_int]),
         "phx_zposv": (c_int, [P, c_int, c_int, c_int, c_int, D, D]),
+        "phx_small_orth": (c_int, [P, c_int, c_int, D, c_double, D, I]),
+        "phx_small_eig": (c_int, [P, c_int, c_int, c_int, D, I, D, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -294,3 +296,24 @@ class Context:
         self._check(self.lib.phx_zposv(self.h, PRECISION[precision], n, nrhs, batch, _dptr(np.ascontiguousarray(Af)),
                                        _dptr(Bf)))
         return Bf.view(np.complex128).reshape(batch, nrhs, n).transpose(0, 2, 1)
+
+    def small_orth(self, G, drop: float = 1e-12):
+        G = np.asarray(G, dtype=np.complex128)
+        batch, m, _ = G.shape
+        Gf = np.concatenate([np.asfortranarray(g).reshape(-1, order="F") for g in G]).view(np.float64)
+        C0 = np.zeros(2 * m * m * batch)
+        keep = np.zeros(m * batch, dtype=np.int32)
+        self._check(self.lib.phx_small_orth(self.h, m, batch, _dptr(np.ascontiguousarray(Gf)), drop, _dptr(C0),
+                                            _iptr(keep)))
+        return C0.view(np.complex128).reshape(batch, m, m).transpose(0, 2, 1), keep.reshape(batch, m)
+
+    def small_eig(self, G, keep, s: int):
+        G = np.asarray(G, dtype=np.complex128)
+        batch, m, _ = G.shape
+        Gf = np.concatenate([np.asfortranarray(g).reshape(-1, order="F") for g in G]).view(np.float64)
+        k = np.ascontiguousarray(keep, dtype=np.int32).reshape(-1)
+        C = np.zeros(2 * m * s * batch)
+        th = np.zeros(s * batch)
+        self._check(self.lib.phx_small_eig(self.h, m, s, batch, _dptr(np.ascontiguousarray(Gf)), _iptr(k), _dptr(C),
+                                           _dptr(th)))
+        return C.view(np.complex128).reshape(batch, s, m).transpose(0, 2, 1), th.reshape(batch, s)
