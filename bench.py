@@ -1,0 +1,175 @@
+"""Throughput of k-point band solves + adjoint on one MI355X.
+
+Workload (FCC M=5 headline): 16 seeded designs, FCC primitive cell, 32^3 voxels
+(uniform[0,1] then periodic 3x3x3 box mean, seeds 400-415), plane-wave order
+M=5 (N=1331: 3993 displacement / 7986 stress unknowns), 60 k-points on the
+IBZ boundary G-X-W-K-G-L-U-W-L-K|U-X, lowest 12 bands, d omega / d rho_e for
+bands 6 and 7 at every k, mixed precision (FP32 pencil factorisation and
+preconditioner, FP64 residuals and Rayleigh-Ritz).  One step = all 16 designs
+x 60 k-points.  Inputs are resident on the device (torch tensors) when the
+timed region starts; outputs stay on the device.
+
+Prints one JSON line (rank 0) with the metric, a roofline entry for the
+dominant kernel class measured with HIP events on the library stream over the
+timed region, the mixed-vs-FP64 accuracy gate and a CPU-oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--designs", type=int, default=16)
+    ap.add_argument("--nk", type=int, default=60)
+    ap.add_argument("--M", type=int, default=5)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-gate", action="store_true", help="skip the mixed-vs-FP64 accuracy gate")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "design-only, see DESIGN.md)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1603_06855_amd import phx, synth
+
+    dev = torch.device("cuda:0")
+    ctx = phx.Context(0)
+    wl = synth.config4(all_m5=True, ndesign=args.designs)
+    cells = [synth.Cell(c.lattice, c.a, c.nv, args.M, c.phase0, c.phase1, c.simp_p) for c in wl.cells]
+    q = phx.kpath("FCC", args.nk) if args.nk >= 12 else phx.kpath("FCC", 12)[: args.nk]
+    bands = (6, 7)
+    nb = 12
+    rho_dev = [torch.from_numpy(np.ascontiguousarray(d.reshape(-1))).to(dev) for d in wl.designs]
+    torch.cuda.synchronize()
+
+    def step():
+        outs = []
+        for c, r in zip(cells, rho_dev):
+            outs.append(ctx.sens_dev(c, r, q, nb, bands, args.precision))
+        return outs
+
+    # Accuracy gate (untimed): mixed vs FP64 on design 0 at a k-subset.
+    gate = None
+    if not args.no_gate:
+        sub = q[:: max(1, args.nk // 8)]
+        ctx.set_option("tol_fp64", 1e-10)
+        om64, dw64 = ctx.sens(cells[0], wl.designs[0], sub, nb, bands, "fp64")
+        om32, dw32 = ctx.sens(cells[0], wl.designs[0], sub, nb, bands, "mixed")
+        ctx.set_option("tol_fp64", 1e-8)
+        scale = om64.max()
+        rel = np.where(om64 > 1e-3 * scale, np.abs(om32 - om64) / np.maximum(om64, 1e-300), 0.0)
+        sens_err = float(max(np.abs(dw32[k, j] - dw64[k, j]).max() / max(np.abs(dw64[k, j]).max(), 1e-300)
+                             for k in range(len(sub)) for j in range(len(bands)) if om64[k, bands[j] - 1] > 0))
+        gate = {"k_points": int(len(sub)), "max_rel_omega_err": float(rel.max()), "max_sens_err": sens_err,
+                "pass": bool(rel.max() <= 1e-6)}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.set_option("profile_reset", 1)
+    ctx.set_option("profile", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        step()
+        iters = max(iters, ctx.stat("iters"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_option("profile", 0)
+
+    elapsed = t1 - t0
+    units = args.designs * args.nk * args.steps
+    value = units / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble", "apply", "gram", "small",
+               "update", "residual", "adjoint"]
+    prof = {c: {k: ctx.stat(f"prof.{c}.{k}") for k in ("ms", "flops", "bytes", "count")} for c in classes}
+    dom = max(classes, key=lambda c: prof[c]["ms"])
+    p = prof[dom]
+    mfma_classes = {"herk", "panel", "trsm_update", "trsm_diag", "apply", "gram", "update", "potrf_diag"}
+    if dom in mfma_classes:
+        fp = "fp32" if (args.precision == "mixed" and dom in {"herk", "panel", "trsm_update", "trsm_diag",
+                                                                  "potrf_diag"}) else "fp64"
+        achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[fp] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / (PEAK[fp] / 1e12), "traffic": None, "kernel": dom, "dtype": fp,
+                "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1)}
+    else:
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": achieved / (PEAK["hbm"] / 1e9), "traffic": None, "kernel": dom,
+                "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1)}
+    breakdown = {c: round(prof[c]["ms"] / args.steps, 3) for c in classes}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.M)
+
+    line = {
+        "metric": "k-point band solves+adjoint/sec, FCC M=5; mixed vs FP64 at <=1e-6 rel omega err",
+        "value": value,
+        "unit": "k-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64" if args.precision == "mixed" else "fp64",
+        "data": "synthetic",
+        "config": {"workload": f"FCC 32^3, M={args.M} (3N={3 * (2 * args.M + 1) ** 3}), {args.designs} designs x "
+                               f"{args.nk} k, 12 bands, adjoint bands 6/7, {args.precision}",
+                   "designs": args.designs, "k_points": args.nk, "nbands": nb, "sens_bands": list(bands),
+                   "M": args.M, "precision": args.precision, "parallelism": "single GPU",
+                   "eigensolver_iters_max": iters},
+        "roofline": roof,
+        "stage_ms_per_step": breakdown,
+        "accuracy_gate": gate,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(M: int):
+    """The FP64 oracle on one design x one k-point (+ adjoint of bands 6 and 7), FCC 32^3."""
+    from oracle import adjoint, geometry
+    from paper_1603_06855_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    cell = synth.Cell("FCC", 1.0, 32, M)
+    rho = synth.box_smoothed_uniform(32, 400)
+    Q = geometry.kpath("FCC", 60)[[7]]
+    t = time.perf_counter()
+    adjoint.sensitivities(cell, rho, Q, 12, (6, 7))
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "k-solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 design x 1 k-point (FCC 32^3, M={M}, 12 bands, adjoint bands 6/7), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

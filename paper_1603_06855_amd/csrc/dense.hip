@@ -275,14 +275,22 @@ template int potrf_diag<float>(float2*, long, long, int, int, float2*, long, int
 // multiple of 64; lower triangle used and overwritten by L), keeping the
 // inverted diagonal blocks of L in Dinv (batch x n/64 blocks of 64x64).
 // ---------------------------------------------------------------------------
+#define PHX_HOOK_BEGIN(c) \
+  if (hook) hook->begin(hook->user, (c))
+#define PHX_HOOK_END(c, f, b) \
+  if (hook) hook->end(hook->user, (c), (f), (b))
+
 template <typename R>
 int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
-                  hipStream_t st) {
+                  hipStream_t st, const ProfHook* hook) {
   typedef C_t<R> C;
   const int T = n / 64;
+  const double cb = (double)sizeof(C);
   for (int j = 0; j < T; ++j) {
     const int j0 = j * 64;
+    PHX_HOOK_BEGIN(PROF_POTRF_DIAG);
     int e = potrf_diag<R>(A, lda, sA, batch, j0, Dinv, sD, flag, st);
+    PHX_HOOK_END(PROF_POTRF_DIAG, batch * 8.0 * 64 * 64 * 64 / 3.0, batch * cb * (64.0 * 64 * 2));
     if (e) return e;
     const int rem = n - j0 - 64;
     if (rem <= 0) break;
@@ -294,7 +302,9 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
       g.B = Dinv + (long)j * 4096; g.ldb = 64; g.sB = sD;
       g.Cm = panel; g.ldc = lda; g.sC = sA;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      PHX_HOOK_BEGIN(PROF_PANEL);
       e = zgemm<R>(g, 0, 1, st);
+      PHX_HOOK_END(PROF_PANEL, batch * 8.0 * rem * 64 * 64, batch * cb * (2.0 * rem * 64));
       if (e) return e;
     }
     {  // trailing lower tiles -= panel panel^H
@@ -304,14 +314,20 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
       g.B = panel; g.ldb = lda; g.sB = sA;
       g.Cm = A + (j0 + 64) + (long)(j0 + 64) * lda; g.ldc = lda; g.sC = sA;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      PHX_HOOK_BEGIN(PROF_HERK);
       e = zgemm<R>(g, 0, 1, st);
+      // algorithmic: rank-64 update of the lower triangle (rem(rem+1)/2 entries), read+write once
+      PHX_HOOK_END(PROF_HERK, batch * 8.0 * 64 * (double)rem * (rem + 1) / 2.0,
+                   batch * cb * ((double)rem * (rem + 1) + rem * 64.0));
       if (e) return e;
     }
   }
   return 0;
 }
-template int potrf_batched<double>(double2*, int, long, long, int, double2*, long, int*, hipStream_t);
-template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, int*, hipStream_t);
+template int potrf_batched<double>(double2*, int, long, long, int, double2*, long, int*, hipStream_t,
+                                   const ProfHook*);
+template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, int*, hipStream_t,
+                                  const ProfHook*);
 
 // ---------------------------------------------------------------------------
 // Solve (L L^H) Y = B for a batch of factors from potrf_batched; B is n x nc
@@ -320,8 +336,10 @@ template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, 
 // ---------------------------------------------------------------------------
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
-                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st) {
+                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
+                  const ProfHook* hook) {
   const int T = n / 64;
+  const double cb = (double)sizeof(C_t<R>);
   int e;
   for (int j = 0; j < T; ++j) {  // forward: L Z = B
     const int j0 = j * 64;
@@ -332,7 +350,10 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
       g.B = B + j0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z + j0; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      if ((e = zgemm<R>(g, 0, 0, st))) return e;
+      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * 64 * 64 * nc / 2, batch * cb * (64.0 * 64 / 2 + 2.0 * 64 * nc));
+      if (e) return e;
     }
     if (j0 + 64 < n) {
       GemmArgs<R> g{};
@@ -341,7 +362,10 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
       g.B = Z + j0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + j0 + 64; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      if ((e = zgemm<R>(g, 0, 0, st))) return e;
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * g.M * 64 * nc, batch * cb * ((double)g.M * 64 + 2.0 * g.M * nc));
+      if (e) return e;
     }
   }
   for (int j = T - 1; j >= 0; --j) {  // backward: L^H Y = Z, Y into B
@@ -353,7 +377,10 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
       g.B = Z + j0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + j0; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      if ((e = zgemm<R>(g, 1, 0, st))) return e;
+      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      e = zgemm<R>(g, 1, 0, st);
+      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * 64 * 64 * nc / 2, batch * cb * (64.0 * 64 / 2 + 2.0 * 64 * nc));
+      if (e) return e;
     }
     if (j0 > 0) {
       GemmArgs<R> g{};
@@ -362,14 +389,17 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
       g.B = B + j0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      if ((e = zgemm<R>(g, 1, 0, st))) return e;
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 1, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * g.M * 64 * nc, batch * cb * ((double)g.M * 64 + 2.0 * g.M * nc));
+      if (e) return e;
     }
   }
   return 0;
 }
 template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
-                                   long, double2*, long, long, int, hipStream_t);
+                                   long, double2*, long, long, int, hipStream_t, const ProfHook*);
 template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
-                                  long, float2*, long, long, int, hipStream_t);
+                                  long, float2*, long, long, int, hipStream_t, const ProfHook*);
 
 }  // namespace phx

@@ -27,16 +27,32 @@ struct GemmArgs {
 template <typename R>
 int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);
 
+// Optional timing hook around kernel launches (class id, algorithmic flops/bytes).
+enum ProfClass {
+  PROF_POTRF_DIAG = 0,
+  PROF_PANEL,
+  PROF_HERK,
+  PROF_TRSM_DIAG,
+  PROF_TRSM_UPDATE,
+  PROF_NCLASS_DENSE
+};
+struct ProfHook {
+  void (*begin)(void* user, int cls);
+  void (*end)(void* user, int cls, double flops, double bytes);
+  void* user;
+};
+
 template <typename R>
 int potrf_diag(C_t<R>* A, long lda, long sA, int batch, int j0, C_t<R>* Dinv, long sD, int* flag,
                hipStream_t st);
 
 template <typename R>
 int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
-                  hipStream_t st);
+                  hipStream_t st, const ProfHook* hook = nullptr);
 
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
-                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st);
+                  C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
+                  const ProfHook* hook = nullptr);
 
 }  // namespace phx

@@ -34,7 +34,7 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
 void launch_zero(double2* X, long n, hipStream_t st);
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
 template <typename R>
-void launch_residual(const double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
+void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
                      hipStream_t st);
 template <typename R>

@@ -267,15 +267,15 @@ __global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* id
 
 // R = KX - theta OX per column (one block per (column, k)); writes R into Rp in the
 // preconditioner precision, the residual norm and the relative residual
-// rn = |R| / ((|theta| + sigma) |OX|); columns with rn below act_tol are zeroed in Rp
-// so that converged directions stop feeding the search space.
+// rn = |R| / ((|theta| + sigma) |OX|).  Columns with rn below act_tol are locked: their
+// residual and their previous-direction (P) column are zeroed.
 template <typename R>
-__global__ __launch_bounds__(256) void residual_kernel(const double2* Big, long n3, long mcols, long sBig,
+__global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, long mcols, long sBig,
                                                        const double* theta, int s, const double* sigma,
                                                        double act_tol, C_t<R>* Rp, long sR, double* rn,
                                                        double* rnorm) {
   const int j = blockIdx.x, k = blockIdx.y;
-  const double2* S = Big + (long)k * sBig;
+  double2* S = Big + (long)k * sBig;
   const double2* kx = S + (mcols + j) * n3;      // KS block, column j (X part)
   const double2* ox = S + (2 * mcols + j) * n3;  // OS block, column j
   const double th = theta[k * s + j];
@@ -305,7 +305,16 @@ __global__ __launch_bounds__(256) void residual_kernel(const double2* Big, long 
     rnorm[k * s + j] = sqrt(sa[0]);
   }
   if (rel < act_tol) {
-    for (long i = threadIdx.x; i < n3; i += 256) r[i] = mk<R>(0, 0);
+    // Converged column: it stops feeding the search space (soft locking).  Its
+    // preconditioned residual and its previous-direction column are zeroed, so the
+    // next orthonormalisation drops them instead of amplifying rounding noise.
+    double2* pc = S + (2L * s + j) * n3;
+    for (long i = threadIdx.x; i < n3; i += 256) {
+      r[i] = mk<R>(0, 0);
+      pc[i] = make_double2(0, 0);
+      pc[mcols * n3 + i] = make_double2(0, 0);
+      pc[2 * mcols * n3 + i] = make_double2(0, 0);
+    }
   }
 }
 
@@ -485,16 +494,16 @@ void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, i
 }
 
 template <typename R>
-void launch_residual(const double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
+void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
                      hipStream_t st) {
   hipLaunchKernelGGL((residual_kernel<R>), dim3(s, nk), dim3(256), 0, st, Big, n3, mcols, sBig, theta, s, sigma,
                      act_tol, Rp, sR, rn, rnorm);
 }
-template void launch_residual<double>(const double2*, long, long, long, const double*, int, int, const double*,
-                                      double, double2*, long, double*, double*, hipStream_t);
-template void launch_residual<float>(const double2*, long, long, long, const double*, int, int, const double*,
-                                     double, float2*, long, double*, double*, hipStream_t);
+template void launch_residual<double>(double2*, long, long, long, const double*, int, int, const double*, double,
+                                      double2*, long, double*, double*, hipStream_t);
+template void launch_residual<float>(double2*, long, long, long, const double*, int, int, const double*, double,
+                                     float2*, long, double*, double*, hipStream_t);
 
 template <typename R>
 void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st) {

@@ -50,6 +50,90 @@ struct Stats {
   int iters = 0, chunks = 0, block = 0, kchunk = 0;
 };
 
+// Kernel-class timing with HIP events recorded on the context stream.
+enum RtClass {
+  PROF_ASSEMBLE = phx::PROF_NCLASS_DENSE,
+  PROF_APPLY,
+  PROF_GRAM,
+  PROF_SMALL,
+  PROF_UPDATE,
+  PROF_RESIDUAL,
+  PROF_ADJOINT,
+  PROF_NCLASS
+};
+const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble",
+                                             "apply", "gram", "small", "update", "residual", "adjoint"};
+
+struct ProfAcc {
+  double ms = 0, flops = 0, bytes = 0;
+  long count = 0;
+};
+
+struct Profiler {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  struct Pend {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pend> pend;
+  hipEvent_t open = nullptr;
+  ProfAcc acc[PROF_NCLASS];
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void begin(int cls) {
+    if (!on) return;
+    open = get();
+    if (open) (void)hipEventRecord(open, st);
+  }
+  void end(int cls, double flops, double bytes) {
+    if (!on || !open) return;
+    hipEvent_t b = get();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    pend.push_back({cls, open, b, flops, bytes});
+    open = nullptr;
+  }
+  // Call after the stream has been synchronised.
+  void flush() {
+    for (auto& p : pend) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        acc[p.cls].ms += ms;
+        acc[p.cls].flops += p.flops;
+        acc[p.cls].bytes += p.bytes;
+        acc[p.cls].count += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pend.clear();
+  }
+  void reset() {
+    for (auto& a : acc) a = ProfAcc();
+  }
+  ~Profiler() {
+    for (auto& p : pend) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+void hook_begin(void* u, int cls) { ((Profiler*)u)->begin(cls); }
+void hook_end(void* u, int cls, double f, double b) { ((Profiler*)u)->end(cls, f, b); }
+
 }  // namespace
 
 struct phx_ctx {
@@ -62,7 +146,17 @@ struct phx_ctx {
   Opts opt;
   Stats stats;
   bool trace = false;
+  Profiler prof;
+  phx::ProfHook hook{hook_begin, hook_end, nullptr};
+  const phx::ProfHook* hk() {
+    hook.user = &prof;
+    prof.st = stream;
+    return prof.on ? &hook : nullptr;
+  }
 };
+
+#define PROF_BEGIN(c) ctx->prof.begin(c)
+#define PROF_END(c, f, b) ctx->prof.end((c), (f), (b))
 
 namespace {
 
@@ -347,6 +441,8 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   hipStream_t st = ctx->stream;
   const long n3 = sv.n3, m = sv.m;
   double2* X = Big + c0 * n3;
+  const double NN = (double)d.N * d.N, nk = sv.nk;
+  PROF_BEGIN(PROF_APPLY);
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st);
   KCHK(hipGetLastError());
   const long sy = (long)d.Np * 6 * ncol, st_ = (long)d.Np * ncol;
@@ -357,24 +453,33 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
   gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
                Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO);
+  // algorithmic: 10 N^2 complex MACs per column per k; the three N x N operators read once
+  PROF_END(PROF_APPLY, 8.0 * 10 * NN * ncol * nk, 16.0 * (3 * NN + nk * ncol * 3.0 * d.N * 4));
 }
 
 void gram(Solver& sv, double2* Big, int block) {
   // G_k = S_k^H (block_k), block 1 = KS, 2 = OS
+  phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
+  PROF_BEGIN(PROF_GRAM);
   gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
                m * m, ONE, ZERO, sv.ksplit, sv.Gpart);
+  PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nk, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nk);
 }
 
 void cholqr(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
   gram(sv, sv.Big, 2);
+  PROF_BEGIN(PROF_SMALL);
   launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream);
+  PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
+  PROF_BEGIN(PROF_UPDATE);
   gemm<double>(ctx, 0, 0, n3, m, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.C0, m, m * m, 3, sv.Big2, n3, n3 * m, ONE,
                ZERO);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nk, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nk);
   std::swap(sv.Big, sv.Big2);
 }
 
@@ -382,13 +487,18 @@ void rayleigh_ritz(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   gram(sv, sv.Big, 1);
+  PROF_BEGIN(PROF_SMALL);
   launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, nullptr, ctx->stream);
+  PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // X <- [S] Cr ; P <- [W P] Cr[s:m]
+  PROF_BEGIN(PROF_UPDATE);
   gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
                ZERO);
   gemm<double>(ctx, 0, 0, n3, s, m - s, 3 * sv.nk, sv.Big + s * n3, n3, n3 * m, 1, sv.Cr + s, m, m * s, 3,
                sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nk,
+           16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
   std::swap(sv.Big, sv.Big2);
 }
 
@@ -397,7 +507,7 @@ void precondition(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3;
   KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
-                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream));
+                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk()));
   launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream);
   KCHK(hipGetLastError());
 }
@@ -476,10 +586,14 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   HIPCHK(hipMemcpyAsync(idx_d, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
 
   // Pencil A = K + sigma Omega and its Cholesky factor.
+  PROF_BEGIN(PROF_ASSEMBLE);
   launch_assemble<R>(d.Dm, d.Bm, d.Os, sv.Kv, d.N, d.Np, nk, d.c2, sv.sigma_d, (C_t<R>*)sv.A, n3 * n3, 0, st);
+  // algorithmic bytes: the lower triangle of every A(k) written once, the three N x N operators read once
+  PROF_END(PROF_ASSEMBLE, 0, (double)sizeof(C_t<R>) * nk * (3.0 * d.N) * (3.0 * d.N + 1) / 2 + 48.0 * d.N * d.N);
   KCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
-  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st));
+  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st,
+                        ctx->hk()));
 
   // Initial block: unit vectors; W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
@@ -491,15 +605,28 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
   out.converged = false;
   int it = 0;
+  bool near = false;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
     cholqr(sv);
     cholqr(sv);
     rayleigh_ritz(sv);
-    launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, 0.1 * tol, (C_t<R>*)sv.Rp, n3 * s,
+    // K X and Omega X afresh from the Ritz vectors: the residual then never inherits the
+    // rounding drift that the implicit recurrences KX <- KS C accumulate over iterations.
+    // Near convergence the previous direction P is a small difference of nearly equal
+    // vectors, so its recurrence-built images lose accuracy relative to P itself; they
+    // are recomputed too.
+    if (it > 0) {
+      apply_ops(sv, sv.Big, 0, s);
+      if (near) apply_ops(sv, sv.Big, 2 * s, s);
+    }
+    PROF_BEGIN(PROF_RESIDUAL);
+    launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
                        sv.rn, sv.rnorm, st);
+    PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * nk + (double)sizeof(C_t<R>) * 3.0 * d.N * s * nk);
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ctx->prof.flush();
     if (it == 0) {
       int flag = 0;
       HIPCHK(hipMemcpy(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost));
@@ -528,6 +655,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       out.converged = true;
       break;
     }
+    near = near || worst < 1e-5;
     if (it == ctx->opt.maxit) break;
     precondition<R>(sv);
     apply_ops(sv, sv.Big, s, s);
@@ -573,9 +701,11 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
   double2* Fc = dbuf<double2>(ctx, "Fc", ncols * 9 * d.N);
   double2* H1 = dbuf<double2>(ctx, "H1", ncols * 9 * L * L * d.nv);
   double2* H2 = dbuf<double2>(ctx, "H2", ncols * 9 * L * (long)d.nv * d.nv);
+  PROF_BEGIN(PROF_ADJOINT);
   launch_field_coef(Xs, n3, n3 * nsel, nsel, Zy, Zt, d.N, d.Np, nk, Fc, st);
   launch_synth(Fc, d.M, d.nv, ncols, H1, H2, st);
   launch_energy(H2, d.M, d.nv, (int)ncols, d.rho_d, d.mat, d.v, d.c2, lam, d.lscale, out, st);
+  PROF_END(PROF_ADJOINT, 0, 8.0 * ncols * d.nvox + 16.0 * ncols * 9 * d.N);
   KCHK(hipGetLastError());
 }
 
@@ -613,6 +743,7 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
     if (!sel.empty()) adjoint_chunk(sv, sel, sens_dev + (long)k0 * sel.size() * d.nvox);
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->prof.flush();
   if (!conv) {
     ctx->err = "eigensolver reached maxit before every band met the tolerance";
     return PHX_ENOCONV;
@@ -701,6 +832,8 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "shift") { if (!(v > 0 && v < 1e6)) return bad(); ctx->opt.shift = v; }
   else if (k == "drop") { if (!(v > 0 && v < 1e-2)) return bad(); ctx->opt.drop = v; }
   else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
+  else if (k == "profile") { ctx->prof.on = (v != 0); }
+  else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
   return PHX_OK;
 }
@@ -712,6 +845,20 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "chunks") *value = ctx->stats.chunks;
   else if (k == "block") *value = ctx->stats.block;
   else if (k == "kchunk") *value = ctx->stats.kchunk;
+  else if (k.rfind("prof.", 0) == 0) {
+    const size_t dot = k.rfind('.');
+    const std::string cls = k.substr(5, dot - 5), f = k.substr(dot + 1);
+    int c = -1;
+    for (int i = 0; i < PROF_NCLASS; ++i)
+      if (cls == PROF_NAMES[i]) c = i;
+    if (c < 0) return PHX_EINVAL;
+    const ProfAcc& a = ctx->prof.acc[c];
+    if (f == "ms") *value = a.ms;
+    else if (f == "flops") *value = a.flops;
+    else if (f == "bytes") *value = a.bytes;
+    else if (f == "count") *value = (double)a.count;
+    else return PHX_EINVAL;
+  }
   else return PHX_EINVAL;
   return PHX_OK;
 }
