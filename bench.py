@@ -102,24 +102,27 @@ def main():
     value = units / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble", "apply", "gram", "small",
-               "update", "residual", "adjoint"]
+    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble", "apply", "op_gemm", "gram",
+               "small", "update", "residual", "adjoint"]
     prof = {c: {k: ctx.stat(f"prof.{c}.{k}") for k in ("ms", "flops", "bytes", "count")} for c in classes}
-    dom = max(classes, key=lambda c: prof[c]["ms"])
+    # Classes that are exactly one kernel (one instantiation, each launch timed on its own
+    # by HIP events on the library stream): the roofline entry is the one of them that took
+    # the most time in the timed region.
+    fp_chol = "float" if args.precision == "mixed" else "double"
+    single = {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", "fp32" if fp_chol == "float" else "fp64"),
+              "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 2>", "fp64")}
+    dom = max(single, key=lambda c: prof[c]["ms"])
     p = prof[dom]
-    mfma_classes = {"herk", "panel", "trsm_update", "trsm_diag", "apply", "gram", "update", "potrf_diag"}
-    if dom in mfma_classes:
-        fp = "fp32" if (args.precision == "mixed" and dom in {"herk", "panel", "trsm_update", "trsm_diag",
-                                                                  "potrf_diag"}) else "fp64"
-        achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[fp] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / (PEAK[fp] / 1e12), "traffic": None, "kernel": dom, "dtype": fp,
-                "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1)}
-    else:
-        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-                "frac": achieved / (PEAK["hbm"] / 1e9), "traffic": None, "kernel": dom,
-                "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1)}
+    name, fp = single[dom]
+    achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[fp] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / (PEAK[fp] / 1e12), "traffic": None, "kernel": name, "dtype": fp,
+            "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1),
+            "flops_per_launch": p["flops"] / max(p["count"], 1)}
+    other = [c for c in single if c != dom][0]
+    po = prof[other]
+    roof["next"] = {"kernel": single[other][0], "achieved": po["flops"] / max(po["ms"], 1e-9) / 1e9,
+                    "avg_launch_us": 1e3 * po["ms"] / max(po["count"], 1), "launches": int(po["count"])}
     breakdown = {c: round(prof[c]["ms"] / args.steps, 3) for c in classes}
 
     cpu = None
@@ -153,7 +156,7 @@ def main():
 
 
 def cpu_baseline(M: int):
-    """The FP64 oracle on one design x one k-point (+ adjoint of bands 6 and 7), FCC 32^3."""
+    """The FP64 oracle on one design x two k-points (+ adjoint of bands 6 and 7), FCC 32^3."""
     from oracle import adjoint, geometry
     from paper_1603_06855_amd import synth
     try:
@@ -163,12 +166,13 @@ def cpu_baseline(M: int):
         threads = os.cpu_count()
     cell = synth.Cell("FCC", 1.0, 32, M)
     rho = synth.box_smoothed_uniform(32, 400)
-    Q = geometry.kpath("FCC", 60)[[7]]
+    Q = geometry.kpath("FCC", 60)[[7, 23]]
     t = time.perf_counter()
     adjoint.sensitivities(cell, rho, Q, 12, (6, 7))
     dt = time.perf_counter() - t
-    return {"value": 1.0 / dt, "unit": "k-solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 design x 1 k-point (FCC 32^3, M={M}, 12 bands, adjoint bands 6/7), {dt:.1f} s"}
+    return {"value": len(Q) / dt, "unit": "k-solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 design x {len(Q)} k-points (FCC 32^3, M={M}, 12 bands, adjoint bands 6/7, "
+                      f"per-design compliance factorisation included), {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -166,12 +166,23 @@ int phx_bands_batch(phx_ctx* ctx, int ndesign, const phx_cell* cells, const doub
                     const double* q, int nbands, phx_precision prec, int nsens, const int* band_no,
                     double* const* omega, double* const* domega);
 
-/* Device-pointer variants: rho, q, omega, domega_drho point to device memory
- * and the call is ordered on `stream` (a hipStream_t) and synchronises it
- * before returning; used by the PyTorch binding. */
+/* Device-pointer variants, used by the PyTorch binding.  rho_dev (nv^3),
+ * omega_dev (nk * nbands), domega_dev (nk * nsens * nv^3), weight_dev
+ * (nk * nsens) and grad_dev (nv^3) are device arrays; q_host and band_no stay
+ * on the host.  Work already queued on `stream` (a hipStream_t, may be NULL)
+ * is waited for first; the call then runs on the context's stream and returns
+ * after its results are in place.  Same errors as the host calls; a non-finite
+ * or negative rho is detected after copying the design to the host. */
+int phx_bands_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                  int nbands, phx_precision prec, double* omega_dev, void* stream);
 int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
                  int nbands, phx_precision prec, int nsens, const int* band_no, double* omega_dev,
                  double* domega_dev, void* stream);
+/* grad_dev = sum_{k, j} weight_dev[k * nsens + j] d omega_{band_no[j]}(k) / d rho_e
+ * (the backward of any objective of the band frequencies); omega_dev may be NULL. */
+int phx_adjoint_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                    int nbands, phx_precision prec, int nsens, const int* band_no, const double* weight_dev,
+                    double* omega_dev, double* grad_dev, void* stream);
 
 /* ------------------------------------------------------------------ dense building blocks */
 

@@ -17,17 +17,31 @@
 
 namespace phx {
 
-template <typename R, int OPA, int OPB>
+// One workgroup (4 waves) computes a BM x BN tile of C; wave w covers rows
+// (w % WM) * 32 .. +32 and columns (w / WM) * 32 .. +32 with 2 x 2 MFMA blocks.
+// Shapes: 64 x 64 (WM = 2) for square work, 128 x 32 (WM = 4) for the narrow
+// right-hand-side blocks of the triangular solves and subspace updates.
+// MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update), 2 k-shared
+// operator times a block (same code as 0; a separate instantiation so that profilers
+// report the matrix-free operator products on their own).
+template <typename R, int OPA, int OPB, int BM, int BN, int MODE>
 __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
-  __shared__ R Asr[16][64 + 4], Asi[16][64 + 4], Bsr[16][64 + 4], Bsi[16][64 + 4];
+  constexpr int WM = BM / 32;
+  static_assert(WM * (BN / 32) == 4, "four waves per tile");
+  // per-thread staging: A holds BM*16 elements, B holds 16*BN, in groups of VA / VB
+  // consecutive elements along the operand's contiguous dimension
+  constexpr int NA = BM * 16 / 256, NB = BN * 16 / 256;
+  constexpr int VA = NA < 4 ? NA : 4, VB = NB < 4 ? NB : 4;
+  constexpr int GA = NA / VA, GB = NB / VB;
+  __shared__ R Asr[16][BM + 4], Asi[16][BM + 4], Bsr[16][BN + 4], Bsi[16][BN + 4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave % WM, wc = wave / WM;
   int ti, tj;
-  if (g.tri) {
+  if (MODE == 1) {
     const long t = blockIdx.x;
     long r = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
@@ -35,11 +49,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
     ti = (int)r;
     tj = (int)(t - r * (r + 1) / 2);
   } else {
-    const int tm = (g.M + 63) >> 6;
+    const int tm = (g.M + BM - 1) / BM;
     ti = blockIdx.x % tm;
     tj = blockIdx.x / tm;
   }
-  const int row0 = ti * 64, col0 = tj * 64;
+  const int row0 = ti * BM, col0 = tj * BN;
   const int b = blockIdx.y;
   const int sp = blockIdx.z;
   const C* A = g.A + (long)(b / g.dA) * g.sA;
@@ -59,40 +73,60 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
       ci[i][j] = (ACC){0, 0, 0, 0};
     }
 
-  C ra[4], rb[4];
+  // Group index gi = tid + 256 * r.  OPA = 0 (A column-major, contiguous in i): group
+  // (i-block, k) with i-block fastest; OPA = 1 (A^H, contiguous in k): (k-block, i).
+  C ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int i, k;
-      if (OPA == 0) { k = k0 + (tid >> 4); i = row0 + ((tid & 15) << 2) + q; }
-      else { i = row0 + (tid >> 2); k = k0 + ((tid & 3) << 2) + q; }
-      C v = mk<R>(0, 0);
-      if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
-      ra[q] = v;
-      int j, kb;
-      if (OPB == 0) { j = col0 + (tid >> 2); kb = k0 + ((tid & 3) << 2) + q; }
-      else { kb = k0 + (tid >> 4); j = col0 + ((tid & 15) << 2) + q; }
-      C w = mk<R>(0, 0);
-      if (j < g.N && kb < kend) w = (OPB == 0) ? B[kb + (long)j * g.ldb] : B[j + (long)kb * g.ldb];
-      rb[q] = w;
+    for (int r = 0; r < GA; ++r) {
+      const int gi = tid + 256 * r;
+#pragma unroll
+      for (int q = 0; q < VA; ++q) {
+        int i, k;
+        if (OPA == 0) { i = row0 + (gi % (BM / VA)) * VA + q; k = k0 + gi / (BM / VA); }
+        else { k = k0 + (gi % (16 / VA)) * VA + q; i = row0 + gi / (16 / VA); }
+        C v = mk<R>(0, 0);
+        if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+        ra[r * VA + q] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < GB; ++r) {
+      const int gi = tid + 256 * r;
+#pragma unroll
+      for (int q = 0; q < VB; ++q) {
+        int j, k;
+        if (OPB == 0) { k = k0 + (gi % (16 / VB)) * VB + q; j = col0 + gi / (16 / VB); }
+        else { j = col0 + (gi % (BN / VB)) * VB + q; k = k0 + gi / (BN / VB); }
+        C w = mk<R>(0, 0);
+        if (j < g.N && k < kend) w = (OPB == 0) ? B[k + (long)j * g.ldb] : B[j + (long)k * g.ldb];
+        rb[r * VB + q] = w;
+      }
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (OPA == 0) {
-        const int kk = tid >> 4, ii = ((tid & 15) << 2) + q;
-        Asr[kk][ii] = ra[q].x; Asi[kk][ii] = ra[q].y;
-      } else {
-        const int ii = tid >> 2, kk = ((tid & 3) << 2) + q;
-        Asr[kk][ii] = ra[q].x; Asi[kk][ii] = -ra[q].y;
+    for (int r = 0; r < GA; ++r) {
+      const int gi = tid + 256 * r;
+#pragma unroll
+      for (int q = 0; q < VA; ++q) {
+        int ii, kk;
+        if (OPA == 0) { ii = (gi % (BM / VA)) * VA + q; kk = gi / (BM / VA); }
+        else { kk = (gi % (16 / VA)) * VA + q; ii = gi / (16 / VA); }
+        Asr[kk][ii] = ra[r * VA + q].x;
+        Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
       }
-      if (OPB == 0) {
-        const int jj = tid >> 2, kk = ((tid & 3) << 2) + q;
-        Bsr[kk][jj] = rb[q].x; Bsi[kk][jj] = rb[q].y;
-      } else {
-        const int kk = tid >> 4, jj = ((tid & 15) << 2) + q;
-        Bsr[kk][jj] = rb[q].x; Bsi[kk][jj] = -rb[q].y;
+    }
+#pragma unroll
+    for (int r = 0; r < GB; ++r) {
+      const int gi = tid + 256 * r;
+#pragma unroll
+      for (int q = 0; q < VB; ++q) {
+        int jj, kk;
+        if (OPB == 0) { kk = (gi % (16 / VB)) * VB + q; jj = gi / (16 / VB); }
+        else { jj = (gi % (BN / VB)) * VB + q; kk = gi / (BN / VB); }
+        Bsr[kk][jj] = rb[r * VB + q].x;
+        Bsi[kk][jj] = OPB == 0 ? rb[r * VB + q].y : -rb[r * VB + q].y;
       }
     }
   };
@@ -178,15 +212,36 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.K <= 0) {  // C = beta C
     g.ksplit = 1;
   }
+  // Narrow outputs (N <= 32: triangular solves and updates with the s search
+  // vectors) use 128 x 32 tiles; everything else 64 x 64.
+  const bool narrow = !g.tri && !g.op && g.N <= 32;
+  const int BM = narrow ? 128 : 64, BN = narrow ? 32 : 64;
   long ntiles;
-  const long tm = (g.M + 63) / 64, tn = (g.N + 63) / 64;
+  const long tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   if (g.tri) ntiles = tm * (tm + 1) / 2;
   else ntiles = tm * tn;
   dim3 grid((unsigned)ntiles, (unsigned)g.batch, (unsigned)g.ksplit);
-  if (opa == 0 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 0, 0>), grid, dim3(256), 0, st, g);
-  else if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1>), grid, dim3(256), 0, st, g);
-  else if (opa == 1 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 1, 0>), grid, dim3(256), 0, st, g);
-  else hipLaunchKernelGGL((zgemm_kernel<R, 1, 1>), grid, dim3(256), 0, st, g);
+#define PHX_GEMM_LAUNCH(BMv, BNv, T)                                                                     \
+  do {                                                                                                    \
+    if (opa == 0 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 0, 0, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
+    else if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
+    else if (opa == 1 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 1, 0, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
+    else hipLaunchKernelGGL((zgemm_kernel<R, 1, 1, BMv, BNv, T>), grid, dim3(256), 0, st, g);             \
+  } while (0)
+  // The lower-triangular tile grid (Hermitian rank-k update of the Cholesky trailing
+  // matrix) and the k-shared operator products are their own instantiations.
+  if (g.tri) {
+    if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid, dim3(256), 0, st, g);
+    else return (int)hipErrorInvalidValue;
+  } else if (g.op) {
+    if (opa != 0 || opb != 0) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((zgemm_kernel<R, 0, 0, 64, 64, 2>), grid, dim3(256), 0, st, g);
+  } else if (narrow) {
+    PHX_GEMM_LAUNCH(128, 32, 0);
+  } else {
+    PHX_GEMM_LAUNCH(64, 64, 0);
+  }
+#undef PHX_GEMM_LAUNCH
   if (g.ksplit > 1) {
     long MN = (long)g.M * g.N;
     unsigned nb = (unsigned)std::min<long>((MN + 255) / 256, 1024);

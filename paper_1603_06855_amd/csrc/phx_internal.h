@@ -20,6 +20,7 @@ struct GemmArgs {
   C_t<R>* Cm; long ldc, sC; int dC;
   C_t<R> alpha, beta;
   int tri;
+  int op;  // 1: A is a k-shared operator (stride 0); selects a separately named kernel
   int ksplit;
   C_t<R>* Cpart;
 };

@@ -53,7 +53,8 @@ struct Stats {
 // Kernel-class timing with HIP events recorded on the context stream.
 enum RtClass {
   PROF_ASSEMBLE = phx::PROF_NCLASS_DENSE,
-  PROF_APPLY,
+  PROF_APPLY,     // strain and force (pointwise parts of the matrix-free K X)
+  PROF_OP_GEMM,   // the k-shared operator products Bm Y, Dm t, Omega_s X
   PROF_GRAM,
   PROF_SMALL,
   PROF_UPDATE,
@@ -62,7 +63,7 @@ enum RtClass {
   PROF_NCLASS
 };
 const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble",
-                                             "apply", "gram", "small", "update", "residual", "adjoint"};
+                                             "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"};
 
 struct ProfAcc {
   double ms = 0, flops = 0, bytes = 0;
@@ -420,8 +421,9 @@ struct Solver {
 template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
-          int ksplit = 1, C_t<R>* Cpart = nullptr) {
+          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0) {
   GemmArgs<R> g{};
+  g.op = op;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.lda = lda; g.sA = sA; g.dA = dA;
   g.B = B; g.ldb = ldb; g.sB = sB; g.dB = dB;
@@ -435,26 +437,39 @@ const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
 
 // K and Omega applied (FP64, matrix-free) to ncol columns of the S block of Big
 // starting at column c0; results to the same columns of the KS and OS blocks.
+// The strain blocks Y (Np x 6 ncol per k) and traces t (Np x ncol per k) of all k
+// are contiguous, so the two compliance products are single GEMMs over every k.
 void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   phx_ctx* ctx = sv.ctx;
   Design& d = *sv.d;
   hipStream_t st = ctx->stream;
   const long n3 = sv.n3, m = sv.m;
   double2* X = Big + c0 * n3;
-  const double NN = (double)d.N * d.N, nk = sv.nk;
+  const double Np = d.Np, nk = sv.nk;
   PROF_BEGIN(PROF_APPLY);
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st);
+  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
-  const long sy = (long)d.Np * 6 * ncol, st_ = (long)d.Np * ncol;
-  gemm<double>(ctx, 0, 0, d.Np, 6 * ncol, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO);
-  gemm<double>(ctx, 0, 0, d.Np, ncol, d.Np, sv.nk, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, st_, 1, sv.Zt, d.Np, st_, ONE, ZERO);
+  const int ny = 6 * ncol * sv.nk, nt = ncol * sv.nk;
+  // algorithmic flops of an operator product: 8 Np^2 per column; the operator is read
+  // once and the block read and written once
+  PROF_BEGIN(PROF_OP_GEMM);
+  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, 1, d.Bm, d.Np, 0, 1, sv.Y, d.Np, 0, 1, sv.Zy, d.Np, 0, ONE, ZERO, 1,
+               nullptr, 1);
+  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * ny, 16.0 * (Np * Np + 2.0 * Np * ny));
+  PROF_BEGIN(PROF_OP_GEMM);
+  gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
+               nullptr, 1);
+  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
+  PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st);
+  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
+  PROF_BEGIN(PROF_OP_GEMM);
   gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
-               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO);
-  // algorithmic: 10 N^2 complex MACs per column per k; the three N x N operators read once
-  PROF_END(PROF_APPLY, 8.0 * 10 * NN * ncol * nk, 16.0 * (3 * NN + nk * ncol * 3.0 * d.N * 4));
+               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1);
+  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
 }
 
 void gram(Solver& sv, double2* Big, int block) {
@@ -737,7 +752,7 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
         if (omega) omega[(size_t)(k0 + k) * nb + j] = om;
         if (ebound) {
           const double bl = d.lscale * co.rnorm[(size_t)k * s + j] / sqrt(d.V * d.dens_min);
-          ebound[(size_t)(k0 + k) * nb + j] = om > 0 ? std::min(bl / (2 * om), sqrt(bl)) : sqrt(bl);
+          ebound[(size_t)(k0 + k) * nb + j] = om > 0 ? std::min(bl / om, sqrt(bl)) : sqrt(bl);
         }
       }
     if (!sel.empty()) adjoint_chunk(sv, sel, sens_dev + (long)k0 * sel.size() * d.nvox);
@@ -1110,30 +1125,70 @@ int phx_bands_batch(phx_ctx* ctx, int ndesign, const phx_cell* cells, const doub
   });
 }
 
+// Device-pointer path shared by the *_dev calls: rho on the device, q on the host,
+// omega / domega / grad on the device (each may be NULL when not wanted).
+static int dev_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                    int nbands, phx_precision prec, int nsens, const int* band_no, double* omega_dev,
+                    double* domega_dev, const double* weight_dev, double* grad_dev, void* stream) {
+  check_cell(ctx, cell);
+  if (!rho_dev) fail(ctx, PHX_EINVAL, "rho_dev is NULL");
+  check_q(ctx, q_host, nk);
+  check_bands(ctx, cell, nbands, nsens, band_no);
+  if (prec != PHX_FP64 && prec != PHX_MIXED) fail(ctx, PHX_EINVAL, "unknown precision");
+  if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  const long nvox = (long)cell->nv * cell->nv * cell->nv;
+  hipStream_t st = ctx->stream;
+  std::vector<double> rh(nvox);
+  HIPCHK(hipMemcpyAsync(rh.data(), rho_dev, nvox * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  check_rho(ctx, rh.data(), nvox);
+  Design d;
+  setup_design(ctx, *cell, rh.data(), rho_dev, d, "d0:");
+  std::vector<int> sel;
+  for (int j = 0; j < nsens; ++j) sel.push_back(band_no[j] - 1);
+  double* sens = domega_dev;
+  if (nsens > 0 && !sens) sens = dbuf<double>(ctx, "sens", (long)nk * nsens * nvox);
+  std::vector<double> om((size_t)nk * nbands);
+  const int rc = run_design(ctx, d, q_host, nk, nbands, prec, om.data(), nullptr, sel, sens);
+  if (omega_dev)
+    HIPCHK(hipMemcpyAsync(omega_dev, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  if (grad_dev) {
+    HIPCHK(hipMemsetAsync(grad_dev, 0, nvox * sizeof(double), st));
+    launch_weighted_sum(sens, weight_dev, nk * nsens, nvox, grad_dev, st);
+    KCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return rc;
+}
+
+int phx_bands_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                  int nbands, phx_precision prec, double* omega_dev, void* stream) {
+  return guard(ctx, [&]() {
+    if (!omega_dev) fail(ctx, PHX_EINVAL, "omega_dev is NULL");
+    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, 0, nullptr, omega_dev, nullptr, nullptr, nullptr,
+                    stream);
+  });
+}
+
 int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host, int nbands,
                  phx_precision prec, int nsens, const int* band_no, double* omega_dev, double* domega_dev,
                  void* stream) {
   return guard(ctx, [&]() {
-    check_cell(ctx, cell);
-    if (!rho_dev || !omega_dev) fail(ctx, PHX_EINVAL, "rho_dev and omega_dev are required");
-    check_q(ctx, q_host, nk);
-    check_bands(ctx, cell, nbands, nsens, band_no);
+    if (!omega_dev) fail(ctx, PHX_EINVAL, "omega_dev is NULL");
     if (nsens > 0 && !domega_dev) fail(ctx, PHX_EINVAL, "domega_dev is NULL");
-    if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-    const long nvox = (long)cell->nv * cell->nv * cell->nv;
-    std::vector<double> rh(nvox);
-    HIPCHK(hipMemcpyAsync(rh.data(), rho_dev, nvox * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    check_rho(ctx, rh.data(), nvox);
-    Design d;
-    setup_design(ctx, *cell, rh.data(), rho_dev, d, "d0:");
-    std::vector<int> sel;
-    for (int j = 0; j < nsens; ++j) sel.push_back(band_no[j] - 1);
-    std::vector<double> om((size_t)nk * nbands);
-    const int rc = run_design(ctx, d, q_host, nk, nbands, prec, om.data(), nullptr, sel, domega_dev);
-    HIPCHK(hipMemcpyAsync(omega_dev, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    return rc;
+    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, domega_dev, nullptr,
+                    nullptr, stream);
+  });
+}
+
+int phx_adjoint_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                    int nbands, phx_precision prec, int nsens, const int* band_no, const double* weight_dev,
+                    double* omega_dev, double* grad_dev, void* stream) {
+  return guard(ctx, [&]() {
+    if (!weight_dev || !grad_dev) fail(ctx, PHX_EINVAL, "weight_dev or grad_dev is NULL");
+    if (nsens < 1) fail(ctx, PHX_EINVAL, "nsens must be at least 1");
+    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, nullptr, weight_dev,
+                    grad_dev, stream);
   });
 }
 

@@ -66,8 +66,11 @@ def load():
         "phx_adjoint": (c_int, [P, POINTER(Cell), D, c_int, D, c_int, c_int, c_int, I, D, D, D]),
         "phx_bands_batch": (c_int, [P, c_int, POINTER(Cell), POINTER(D), c_int, D, c_int, c_int, c_int, I,
                                     POINTER(D), POINTER(D)]),
+        "phx_bands_dev": (c_int, [P, POINTER(Cell), c_void_p, c_int, D, c_int, c_int, c_void_p, c_void_p]),
         "phx_sens_dev": (c_int, [P, POINTER(Cell), c_void_p, c_int, D, c_int, c_int, c_int, I, c_void_p,
                                  c_void_p, c_void_p]),
+        "phx_adjoint_dev": (c_int, [P, POINTER(Cell), c_void_p, c_int, D, c_int, c_int, c_int, I, c_void_p,
+                                    c_void_p, c_void_p, c_void_p]),
         "phx_zgemm": (c_int, [P, c_int, c_char, c_char, c_int, c_int, c_int, D, D, c_long, c_long, D, c_long,
                               c_long, D, D, c_long, c_long, c_int]),
         "phx_zposv": (c_int, [P, c_int, c_int, c_int, c_int, D, D]),
@@ -247,7 +250,7 @@ class Context:
         qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
         nk = qq.shape[0]
         b = np.ascontiguousarray(band_no, dtype=np.int32)
-        rho_t = rho_t.contiguous().to(torch.float64)
+        rho_t = rho_t.detach().contiguous().to(torch.float64)
         om = torch.empty((nk, nbands), dtype=torch.float64, device=rho_t.device)
         dw = torch.empty((nk, len(b), rho_t.numel()), dtype=torch.float64, device=rho_t.device)
         stream = torch.cuda.current_stream(rho_t.device).cuda_stream
@@ -255,6 +258,35 @@ class Context:
                                           PRECISION[precision], len(b), _iptr(b), c_void_p(om.data_ptr()),
                                           c_void_p(dw.data_ptr()), c_void_p(stream)))
         return om, dw
+
+    def bands_dev(self, cell, rho_t, q, nbands: int, precision: str = "fp64"):
+        """torch CUDA tensors in and out: rho_t (nv^3 float64 on the device) -> omega (nk, nbands)."""
+        import torch
+        c = make_cell(cell)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        rho_t = rho_t.detach().contiguous().to(torch.float64)
+        om = torch.empty((nk, nbands), dtype=torch.float64, device=rho_t.device)
+        stream = torch.cuda.current_stream(rho_t.device).cuda_stream
+        self._check(self.lib.phx_bands_dev(self.h, byref(c), c_void_p(rho_t.data_ptr()), nk, _dptr(qq), nbands,
+                                           PRECISION[precision], c_void_p(om.data_ptr()), c_void_p(stream)))
+        return om
+
+    def adjoint_dev(self, cell, rho_t, q, nbands: int, band_no: Sequence[int], weight_t, precision: str = "fp64"):
+        """grad (nv^3, device) = sum_{k,j} weight_t[k, j] d omega_{band_no[j]}(k) / d rho."""
+        import torch
+        c = make_cell(cell)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        rho_t = rho_t.detach().contiguous().to(torch.float64)
+        w = weight_t.detach().to(device=rho_t.device, dtype=torch.float64).contiguous().reshape(nk, len(b))
+        g = torch.empty(rho_t.numel(), dtype=torch.float64, device=rho_t.device)
+        stream = torch.cuda.current_stream(rho_t.device).cuda_stream
+        self._check(self.lib.phx_adjoint_dev(self.h, byref(c), c_void_p(rho_t.data_ptr()), nk, _dptr(qq), nbands,
+                                             PRECISION[precision], len(b), _iptr(b), c_void_p(w.data_ptr()), None,
+                                             c_void_p(g.data_ptr()), c_void_p(stream)))
+        return g
 
     # -------------------------------------------------------------- dense building blocks
     def zgemm(self, opa: str, opb: str, A, B, C=None, alpha=1.0, beta=0.0, precision: str = "fp64"):

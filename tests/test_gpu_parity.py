@@ -32,7 +32,8 @@ def _rand(rng, *shape):
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-5)])
 @pytest.mark.parametrize("opa", ["N", "C"])
 @pytest.mark.parametrize("opb", ["N", "C"])
-@pytest.mark.parametrize("m,n,k,batch", [(1, 1, 1, 1), (70, 45, 33, 3), (130, 64, 200, 2), (64, 128, 16, 1)])
+@pytest.mark.parametrize("m,n,k,batch", [(1, 1, 1, 1), (70, 45, 33, 3), (130, 64, 200, 2), (64, 128, 16, 1),
+                                           (200, 21, 64, 2), (129, 32, 17, 1), (300, 7, 130, 3)])
 def test_zgemm(ctx, prec, tol, opa, opb, m, n, k, batch):
     log("zgemm", prec, opa, opb, m, n, k, batch)
     rng = np.random.default_rng(m * 7 + n + k)
@@ -134,7 +135,13 @@ def test_bands_fp64_config1(ctx, config1_ref):
     err = _om_err(om, ref)
     log("max rel err", err.max())
     assert err.max() <= 1e-9
-    assert np.all(np.abs(om - ref) <= eb + 1e-9 * ref.max())
+    # the acoustic bands at Gamma: the oracle's own value is the square root of a
+    # rounding-level lambda, so they get the same absolute 1e-6 omega_max as in _om_err
+    acoustic = ref < 1e-3 * ref.max()
+    slack = eb + np.where(acoustic, 1e-6, 1e-9) * ref.max() - np.abs(om - ref)
+    i = np.unravel_index(np.argmin(slack), slack.shape)
+    log("tightest bound: k, band", i, "omega", om[i], "ref", ref[i], "bound", eb[i])
+    assert np.all(slack >= 0)
 
 
 def test_bands_mixed_config1(ctx, config1_ref):
