@@ -90,9 +90,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
+    sweeps = 0
+    coarse_iters = 0
     for _ in range(args.steps):
         step()
         iters = max(iters, ctx.stat("iters"))
+        sweeps = max(sweeps, ctx.stat("rr_sweeps"))
+        coarse_iters = max(coarse_iters, ctx.stat("coarse_iters"))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_option("profile", 0)
@@ -146,7 +150,8 @@ def main():
                                f"{args.nk} k, 12 bands, adjoint bands 6/7, {args.precision}",
                    "designs": args.designs, "k_points": args.nk, "nbands": nb, "sens_bands": list(bands),
                    "M": args.M, "precision": args.precision, "parallelism": "single GPU",
-                   "eigensolver_iters_max": iters},
+                   "eigensolver_iters_max": iters, "jacobi_sweeps_max": sweeps,
+                   "coarse_start_iters_max": coarse_iters},
         "roofline": roof,
         "stage_ms_per_step": breakdown,
         "accuracy_gate": gate,

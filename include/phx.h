@@ -87,11 +87,18 @@ const char* phx_last_error(const phx_ctx* ctx);
  * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
  * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
  * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
- * "mem_gb" (device memory budget for one k-chunk, default 64).
+ * "mem_gb" (device memory budget for one k-chunk, default 64), "coarse" (1:
+ * for M >= 4 every k-chunk is first solved at order M-2 to the residual
+ * "coarse_tol", default 1e-3, and its Ritz vectors, embedded in the order-M
+ * plane-wave set, start the order-M solve; 0: start from plane-wave unit
+ * vectors; default 1).
  * Returns PHX_EINVAL for an unknown key or an out-of-range value. */
 int phx_set_option(phx_ctx* ctx, const char* key, double value);
 /* Statistics of the last solve: "iters" (eigensolver iterations of the
- * slowest chunk), "chunks", "block", "kchunk". */
+ * slowest chunk), "chunks", "block", "kchunk", "rr_sweeps" (most Jacobi sweeps
+ * one Rayleigh-Ritz step needed at any k), "coarse_iters" (iterations of the
+ * coarse start).  "prof.<class>.<ms|flops|bytes|count>"
+ * reads the kernel-class timers (enabled with the option "profile"). */
 int phx_get_stat(const phx_ctx* ctx, const char* key, double* value);
 
 /* ------------------------------------------------------------------ helpers */

@@ -335,45 +335,68 @@ template int potrf_diag<float>(float2*, long, long, int, int, float2*, long, int
 #define PHX_HOOK_END(c, f, b) \
   if (hook) hook->end(hook->user, (c), (f), (b))
 
+// Two-level blocking: 64-wide panels inside 256-wide column blocks.  Inside a
+// column block each panel updates only the block's remaining columns; the rest of
+// the trailing matrix receives one rank-256 Hermitian update per block, which
+// reads and writes the trailing matrix a quarter as often as rank-64 updates.
 template <typename R>
 int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
                   hipStream_t st, const ProfHook* hook) {
   typedef C_t<R> C;
-  const int T = n / 64;
+  constexpr int NB = 256;
   const double cb = (double)sizeof(C);
-  for (int j = 0; j < T; ++j) {
-    const int j0 = j * 64;
-    PHX_HOOK_BEGIN(PROF_POTRF_DIAG);
-    int e = potrf_diag<R>(A, lda, sA, batch, j0, Dinv, sD, flag, st);
-    PHX_HOOK_END(PROF_POTRF_DIAG, batch * 8.0 * 64 * 64 * 64 / 3.0, batch * cb * (64.0 * 64 * 2));
-    if (e) return e;
-    const int rem = n - j0 - 64;
-    if (rem <= 0) break;
-    C* panel = A + (j0 + 64) + (long)j0 * lda;
-    {  // panel <- panel * Dinv_j^H   (in place: one 64-wide column tile per row tile)
-      GemmArgs<R> g{};
-      g.M = rem; g.N = 64; g.K = 64; g.batch = batch;
-      g.A = panel; g.lda = lda; g.sA = sA;
-      g.B = Dinv + (long)j * 4096; g.ldb = 64; g.sB = sD;
-      g.Cm = panel; g.ldc = lda; g.sC = sA;
-      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      PHX_HOOK_BEGIN(PROF_PANEL);
-      e = zgemm<R>(g, 0, 1, st);
-      PHX_HOOK_END(PROF_PANEL, batch * 8.0 * rem * 64 * 64, batch * cb * (2.0 * rem * 64));
+  for (int J = 0; J < n; J += NB) {
+    const int w = std::min(NB, n - J);
+    for (int j0 = J; j0 < J + w; j0 += 64) {
+      const int j = j0 / 64;
+      PHX_HOOK_BEGIN(PROF_POTRF_DIAG);
+      int e = potrf_diag<R>(A, lda, sA, batch, j0, Dinv, sD, flag, st);
+      PHX_HOOK_END(PROF_POTRF_DIAG, batch * 8.0 * 64 * 64 * 64 / 6.0, batch * cb * (64.0 * 64 * 2));
       if (e) return e;
+      const int rem = n - j0 - 64;
+      if (rem <= 0) break;
+      C* panel = A + (j0 + 64) + (long)j0 * lda;
+      {  // panel <- panel * Dinv_j^H   (in place: one 64-wide column tile per row tile)
+        GemmArgs<R> g{};
+        g.M = rem; g.N = 64; g.K = 64; g.batch = batch;
+        g.A = panel; g.lda = lda; g.sA = sA;
+        g.B = Dinv + (long)j * 4096; g.ldb = 64; g.sB = sD;
+        g.Cm = panel; g.ldc = lda; g.sC = sA;
+        g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+        PHX_HOOK_BEGIN(PROF_PANEL);
+        e = zgemm<R>(g, 0, 1, st);
+        PHX_HOOK_END(PROF_PANEL, batch * 8.0 * rem * 64 * 64 / 2.0, batch * cb * (2.0 * rem * 64));
+        if (e) return e;
+      }
+      const int nin = J + w - j0 - 64;  // columns of this block right of the panel
+      if (nin > 0) {  // block columns j0+64 .. J+w, every row below the panel's diagonal tile
+        GemmArgs<R> g{};
+        g.M = rem; g.N = nin; g.K = 64; g.batch = batch;
+        g.A = panel; g.lda = lda; g.sA = sA;
+        g.B = panel; g.ldb = lda; g.sB = sA;
+        g.Cm = A + (j0 + 64) + (long)(j0 + 64) * lda; g.ldc = lda; g.sC = sA;
+        g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+        PHX_HOOK_BEGIN(PROF_PANEL);
+        e = zgemm<R>(g, 0, 1, st);
+        PHX_HOOK_END(PROF_PANEL, batch * 8.0 * 64 * ((double)rem * nin - nin * (nin - 1) / 2.0),
+                     batch * cb * (2.0 * rem * nin + rem * 64.0));
+        if (e) return e;
+      }
     }
-    {  // trailing lower tiles -= panel panel^H
+    const int rem2 = n - J - w;
+    if (rem2 > 0) {  // trailing lower tiles -= block block^H (rank w)
+      C* blk = A + (J + w) + (long)J * lda;
       GemmArgs<R> g{};
-      g.M = rem; g.N = rem; g.K = 64; g.batch = batch; g.tri = 1;
-      g.A = panel; g.lda = lda; g.sA = sA;
-      g.B = panel; g.ldb = lda; g.sB = sA;
-      g.Cm = A + (j0 + 64) + (long)(j0 + 64) * lda; g.ldc = lda; g.sC = sA;
+      g.M = rem2; g.N = rem2; g.K = w; g.batch = batch; g.tri = 1;
+      g.A = blk; g.lda = lda; g.sA = sA;
+      g.B = blk; g.ldb = lda; g.sB = sA;
+      g.Cm = A + (J + w) + (long)(J + w) * lda; g.ldc = lda; g.sC = sA;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
       PHX_HOOK_BEGIN(PROF_HERK);
-      e = zgemm<R>(g, 0, 1, st);
-      // algorithmic: rank-64 update of the lower triangle (rem(rem+1)/2 entries), read+write once
-      PHX_HOOK_END(PROF_HERK, batch * 8.0 * 64 * (double)rem * (rem + 1) / 2.0,
-                   batch * cb * ((double)rem * (rem + 1) + rem * 64.0));
+      const int e = zgemm<R>(g, 0, 1, st);
+      // algorithmic: rank-w update of the lower triangle (rem2(rem2+1)/2 entries), read+write once
+      PHX_HOOK_END(PROF_HERK, batch * 8.0 * w * (double)rem2 * (rem2 + 1) / 2.0,
+                   batch * cb * ((double)rem2 * (rem2 + 1) + (double)rem2 * w));
       if (e) return e;
     }
   }
@@ -385,6 +408,184 @@ template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, 
                                   const ProfHook*);
 
 // ---------------------------------------------------------------------------
+// Triangular solves with few right-hand sides (nc <= 32), one diagonal
+// super-block of T <= WS/64 tiles per launch, one workgroup per matrix:
+//   LOWER (L Z = B):    for t = 0..T-1:  Z_t = Dinv_t B_t;    B_u -= L_ut Z_t  (u > t)
+//   UPPER (L^H Y = Z):  for t = T-1..0:  Y_t = Dinv_t^H Z_t;  Z_u -= L_tu^H Y_t (u < t)
+// The super-block's right-hand side (rows J0 .. J0 + 64T of Bin) is held in LDS;
+// the solution rows go to X.  The rest of the solve is a GEMM per super-block.
+// Wave w computes 16-row stripes; MFMA k-index mapping: k = 4 ks + lane/16 when
+// the operand is read down columns (coalesced over rows), k = 16 (lane/16) + ks
+// when it is read along columns of L (each lane walks contiguous memory).
+// ---------------------------------------------------------------------------
+template <typename R, bool LOWER, int WS>
+__global__ __launch_bounds__(256) void trsv_block_kernel(const C_t<R>* L, long lda, long sL, const C_t<R>* Dinv,
+                                                         long sD, const C_t<R>* Bin, long ldb, long sB, C_t<R>* X,
+                                                         long ldx, long sX, int J0, int T, int nc) {
+  typedef C_t<R> C;
+  typedef typename acc_t<R>::type ACC;
+  __shared__ R Sr[WS][32], Si[WS][32];
+  // column swizzle by row parity: the four rows one MFMA operand read touches fall
+  // in two different bank halves
+#define SW(row, col) ((col) ^ (((row) & 1) << 4))
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const long b = blockIdx.x;
+  const C* Lb = L + b * sL;
+  const C* Db = Dinv + b * sD;
+  const C* Bb = Bin + b * sB;
+  C* Xb = X + b * sX;
+  const int rows = 64 * T;
+  for (int e = tid; e < rows * 32; e += 256) {
+    const int r = e % rows, c = e / rows;
+    C v = mk<R>(0, 0);
+    if (c < nc) v = Bb[(J0 + r) + (long)c * ldb];
+    Sr[r][SW(r, c)] = v.x;
+    Si[r][SW(r, c)] = v.y;
+  }
+  __syncthreads();
+  auto colmap = [&](int r) { return sizeof(R) == 8 ? (lg + 4 * r) : (4 * lg + r); };
+  for (int step = 0; step < T; ++step) {
+    const int t = LOWER ? step : T - 1 - step;
+    const int tb = 64 * t;
+    ACC cr[2], ci[2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      cr[y] = (ACC){0, 0, 0, 0};
+      ci[y] = (ACC){0, 0, 0, 0};
+    }
+    {  // diagonal tile: rows 16 wave .. +16 of Dinv_t (or Dinv_t^H) times the tile's rhs
+      const C* Dt = Db + (long)((J0 >> 6) + t) * 4096;
+      const int i = 16 * wave + li;
+      C av[16];  // all 16 operand loads in flight before the first product
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int k = LOWER ? 4 * ks + lg : 16 * lg + ks;
+        av[ks] = LOWER ? Dt[i + 64 * k] : cconj(Dt[k + 64 * i]);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int k = LOWER ? 4 * ks + lg : 16 * lg + ks;
+        const C a = av[ks];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int col = 16 * y + li, row = tb + k;
+          const R br = Sr[row][SW(row, col)], bi = Si[row][SW(row, col)];
+          cr[y] = mfma16(br, a.x, cr[y]);
+          ci[y] = mfma16(bi, a.x, ci[y]);
+          cr[y] = mfma16(-bi, a.y, cr[y]);
+          ci[y] = mfma16(br, a.y, ci[y]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tb + 16 * wave + li, col = 16 * y + colmap(r);
+        Sr[row][SW(row, col)] = cr[y][r];
+        Si[row][SW(row, col)] = ci[y][r];
+        if (col < nc) Xb[(J0 + row) + (long)col * ldx] = mk<R>(cr[y][r], ci[y][r]);
+      }
+    __syncthreads();
+    const int nu = LOWER ? T - 1 - t : t;
+    for (int q = wave; q < 4 * nu; q += 4) {
+      const int u = LOWER ? t + 1 + q / 4 : q / 4;
+      const int r0 = 64 * u + 16 * (q % 4);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        cr[y] = (ACC){0, 0, 0, 0};
+        ci[y] = (ACC){0, 0, 0, 0};
+      }
+      C av[16];
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int k = LOWER ? 4 * ks + lg : 16 * lg + ks;
+        av[ks] = LOWER ? Lb[(J0 + r0 + li) + (long)(J0 + tb + k) * lda]
+                       : cconj(Lb[(J0 + tb + k) + (long)(J0 + r0 + li) * lda]);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int k = LOWER ? 4 * ks + lg : 16 * lg + ks;
+        const C a = av[ks];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int col = 16 * y + li, row = tb + k;
+          const R br = Sr[row][SW(row, col)], bi = Si[row][SW(row, col)];
+          cr[y] = mfma16(br, a.x, cr[y]);
+          ci[y] = mfma16(bi, a.x, ci[y]);
+          cr[y] = mfma16(-bi, a.y, cr[y]);
+          ci[y] = mfma16(br, a.y, ci[y]);
+        }
+      }
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + li, col = 16 * y + colmap(r);
+          Sr[row][SW(row, col)] -= cr[y][r];
+          Si[row][SW(row, col)] -= ci[y][r];
+        }
+    }
+    __syncthreads();
+  }
+#undef SW
+}
+
+// Narrow solve (nc <= 32): super-block kernels plus one GEMM per super-block.
+template <typename R>
+int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD, C_t<R>* B,
+                 long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook) {
+  constexpr int WS = sizeof(R) == 4 ? 256 : 128;
+  const double cb = (double)sizeof(C_t<R>);
+  const int nsb = (n + WS - 1) / WS;
+  int e;
+  for (int sbi = 0; sbi < nsb; ++sbi) {  // forward: L Z = B
+    const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
+    PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+    hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch), dim3(256), 0, st, L, lda, sL, Dinv, sD, B,
+                       ldb, sB, Z, ldz, sZ, J0, T, nc);
+    PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
+    if ((e = (int)hipGetLastError())) return e;
+    const int rem = n - J0 - w;
+    if (rem > 0) {
+      GemmArgs<R> g{};
+      g.M = rem; g.N = nc; g.K = w; g.batch = batch;
+      g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL;
+      g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
+      g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * rem * w * nc, batch * cb * ((double)rem * w + 2.0 * rem * nc));
+      if (e) return e;
+    }
+  }
+  for (int sbi = nsb - 1; sbi >= 0; --sbi) {  // backward: L^H Y = Z, Y into B
+    const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
+    PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+    hipLaunchKernelGGL((trsv_block_kernel<R, false, WS>), dim3(batch), dim3(256), 0, st, L, lda, sL, Dinv, sD, Z,
+                       ldz, sZ, B, ldb, sB, J0, T, nc);
+    PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
+    if ((e = (int)hipGetLastError())) return e;
+    if (J0 > 0) {
+      GemmArgs<R> g{};
+      g.M = J0; g.N = nc; g.K = w; g.batch = batch;
+      g.A = L + J0; g.lda = lda; g.sA = sL;  // rows J0..J0+w, cols 0..J0-1; op = C
+      g.B = B + J0; g.ldb = ldb; g.sB = sB;
+      g.Cm = Z; g.ldc = ldz; g.sC = sZ;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 1, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * J0 * w * nc, batch * cb * ((double)J0 * w + 2.0 * J0 * nc));
+      if (e) return e;
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Solve (L L^H) Y = B for a batch of factors from potrf_batched; B is n x nc
 // (ld ldb, batch stride sB), Z is a work buffer of the same shape.  The result
 // overwrites B.  Every block step is a GEMM with an inverted diagonal block.
@@ -393,6 +594,7 @@ template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
                   const ProfHook* hook) {
+  if (nc <= 32) return potrs_narrow<R>(L, n, lda, sL, batch, Dinv, sD, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   const int T = n / 64;
   const double cb = (double)sizeof(C_t<R>);
   int e;

@@ -33,6 +33,8 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
                   double2* KX, long ldk, long sK, hipStream_t st);
 void launch_zero(double2* X, long n, hipStream_t st);
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
+void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,
+                    int Np, int s, int nk, hipStream_t st);
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,

@@ -519,6 +519,29 @@ void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const doub
                      N, Np, Fc);
 }
 
+// Coarse-to-fine embedding of displacement coefficient blocks: the plane wave n of
+// order Mc keeps its coefficients at the same n in the order-M set (M > Mc); every
+// other fine coefficient is zero (the destination is zeroed first).
+__global__ void prolong_kernel(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX,
+                               int M, int Np) {
+  const int Lc = 2 * Mc + 1, L = 2 * M + 1, Nc = Lc * Lc * Lc;
+  const int pc = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (pc >= Nc) return;
+  const int n1 = pc / (Lc * Lc) - Mc, n2 = (pc / Lc) % Lc - Mc, n3 = pc % Lc - Mc;
+  const int p = ((n1 + M) * L + (n2 + M)) * L + (n3 + M);
+  const double2* src = Xc + (long)k * sXc + (long)j * ldc + pc;
+  double2* dst = X + (long)k * sX + (long)j * ldx + p;
+  for (int c = 0; c < 3; ++c) dst[(long)c * Np] = src[(long)c * Npc];
+}
+
+void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,
+                    int Np, int s, int nk, hipStream_t st) {
+  const int Lc = 2 * Mc + 1, Nc = Lc * Lc * Lc;
+  hipLaunchKernelGGL(prolong_kernel, dim3(nblk(Nc, 256), s, nk), dim3(256), 0, st, Xc, ldc, sXc, Mc, Npc, X, ldx,
+                     sX, M, Np);
+}
+
 // Xsel[k][:, j] = X[k][:, sel[j]] for n-row columns.
 __global__ void gather_cols_kernel(const double2* X, long ldx, long sX, const int* sel, int nsel, long n,
                                    double2* Y, long sY) {

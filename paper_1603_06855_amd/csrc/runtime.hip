@@ -44,10 +44,14 @@ struct Opts {
   double shift = 0.02;
   double drop = 1e-12;
   double mem_gb = 64.0;
+  int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
+  double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
 };
 
 struct Stats {
   int iters = 0, chunks = 0, block = 0, kchunk = 0;
+  int rr_sweeps = 0;  // most Jacobi sweeps any k needed in a Rayleigh-Ritz step of the last solve
+  int coarse_iters = 0;  // eigensolver iterations of the coarse start (slowest chunk)
 };
 
 // Kernel-class timing with HIP events recorded on the context stream.
@@ -410,6 +414,7 @@ struct Solver {
   double2 *Y, *Tr, *Zy, *Zt;
   double2 *G, *Gpart, *C0, *Cr;
   int* keep;
+  int* sweeps;
   double *theta, *rn, *rnorm;
   void* A;     // nk x n3 x n3 (prec)
   void* Dinv;  // nk x n3/64 x 4096 (prec)
@@ -503,7 +508,7 @@ void rayleigh_ritz(Solver& sv) {
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   gram(sv, sv.Big, 1);
   PROF_BEGIN(PROF_SMALL);
-  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, nullptr, ctx->stream);
+  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // X <- [S] Cr ; P <- [W P] Cr[s:m]
@@ -539,8 +544,11 @@ long per_k_bytes(const Design& d, int s, int prec) {
   return n3 * n3 * pc + (n3 / 64) * 4096 * pc + 2L * 3 * n3 * m * 16 + 2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
 }
 
+// init (may be NULL): nk blocks of s start vectors (n3 x s, k-stride n3 s) replacing
+// the plane-wave unit vectors; tol_override > 0 replaces the precision's tolerance.
 template <typename R>
-void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, ChunkOut& out, Solver& sv) {
+void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, ChunkOut& out, Solver& sv,
+                 const double2* init = nullptr, double tol_override = 0) {
   hipStream_t st = ctx->stream;
   const int prec = std::is_same<R, double>::value ? PHX_FP64 : PHX_MIXED;
   const int s = choose_block(ctx, nb, d.N), m = 3 * s;
@@ -562,6 +570,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.C0 = dbuf<double2>(ctx, "C0", (long)nk * m * m);
   sv.Cr = dbuf<double2>(ctx, "Cr", (long)nk * m * s);
   sv.keep = dbuf<int>(ctx, "keep", (long)nk * m);
+  sv.sweeps = dbuf<int>(ctx, "sweeps", nk);
   sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
   sv.rn = dbuf<double>(ctx, "rn", (long)nk * s);
   sv.rnorm = dbuf<double>(ctx, "rnorm", (long)nk * s);
@@ -610,14 +619,20 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st,
                         ctx->hk()));
 
-  // Initial block: unit vectors; W = P = 0.
+  // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
-  launch_unit_columns(sv.Big, n3, sv.sBig, idx_d, s, nk, st);
+  if (init) {
+    HIPCHK(hipMemcpy2DAsync(sv.Big, sv.sBig * sizeof(double2), init, n3 * s * sizeof(double2), n3 * s * sizeof(double2),
+                            nk, hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_unit_columns(sv.Big, n3, sv.sBig, idx_d, s, nk, st);
+  }
   KCHK(hipGetLastError());
   apply_ops(sv, sv.Big, 0, s);
 
-  const double tol = ctx->opt.tol[prec];
+  const double tol = tol_override > 0 ? tol_override : ctx->opt.tol[prec];
   std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
+  std::vector<int> sw_h(nk);
   out.converged = false;
   int it = 0;
   bool near = false;
@@ -640,7 +655,9 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * nk + (double)sizeof(C_t<R>) * 3.0 * d.N * s * nk);
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sw_h.data(), sv.sweeps, sw_h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    for (int v : sw_h) ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, v);
     ctx->prof.flush();
     if (it == 0) {
       int flag = 0;
@@ -726,8 +743,10 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
 
 // Runs the eigensolver over k-chunks; fills omega (+ err bounds) and, when sel is
 // non-empty, the per-(k, band) sensitivities into sens_dev (device).
+// dc (may be NULL): the same design at a lower plane-wave order; each chunk is then
+// first solved there to a loose tolerance and its Ritz vectors start the full solve.
 int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int prec, double* omega, double* ebound,
-               const std::vector<int>& sel, double* sens_dev) {
+               const std::vector<int>& sel, double* sens_dev, Design* dc = nullptr) {
   const int s = choose_block(ctx, nb, d.N);
   const long per = per_k_bytes(d, s, prec);
   int kc = (int)std::max<long>(1, std::min<long>(nk, (long)(ctx->opt.mem_gb * 1073741824.0) / per));
@@ -735,13 +754,28 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
   ctx->stats.kchunk = kc;
   ctx->stats.chunks = 0;
   ctx->stats.iters = 0;
+  ctx->stats.rr_sweeps = 0;
+  ctx->stats.coarse_iters = 0;
   bool conv = true;
   for (int k0 = 0; k0 < nk; k0 += kc) {
     const int nkc = std::min(kc, nk - k0);
     ChunkOut co;
     Solver sv{};
-    if (prec == PHX_FP64) solve_chunk<double>(ctx, d, q + 3L * k0, nkc, nb, co, sv);
-    else solve_chunk<float>(ctx, d, q + 3L * k0, nkc, nb, co, sv);
+    const double2* init = nullptr;
+    if (dc) {
+      ChunkOut cc;
+      Solver svc{};
+      if (prec == PHX_FP64) solve_chunk<double>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
+      else solve_chunk<float>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
+      ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, cc.iters);
+      double2* xi = dbuf<double2>(ctx, "Xinit", (long)nkc * d.n3 * s);
+      launch_zero(xi, (long)nkc * d.n3 * s, ctx->stream);
+      launch_prolong(svc.Big, dc->n3, svc.sBig, dc->M, dc->Np, xi, d.n3, d.n3 * s, d.M, d.Np, s, nkc, ctx->stream);
+      KCHK(hipGetLastError());
+      init = xi;
+    }
+    if (prec == PHX_FP64) solve_chunk<double>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
+    else solve_chunk<float>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
     ctx->stats.chunks++;
     ctx->stats.iters = std::max(ctx->stats.iters, co.iters);
     conv = conv && co.converged;
@@ -764,6 +798,16 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
     return PHX_ENOCONV;
   }
   return PHX_OK;
+}
+
+// The same design at plane-wave order M-2, used to start the order-M eigensolver
+// (enabled by the option "coarse" for M >= 4), or NULL.
+Design* coarse_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, const double* rho_dev, Design& dc) {
+  if (!ctx->opt.coarse || cell.M < 4) return nullptr;
+  phx_cell cc = cell;
+  cc.M = cell.M - 2;
+  setup_design(ctx, cc, rho_host, rho_dev, dc, "c0:");
+  return &dc;
 }
 
 int guard(phx_ctx* ctx, const std::function<int()>& f) {
@@ -847,6 +891,8 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "shift") { if (!(v > 0 && v < 1e6)) return bad(); ctx->opt.shift = v; }
   else if (k == "drop") { if (!(v > 0 && v < 1e-2)) return bad(); ctx->opt.drop = v; }
   else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
+  else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
+  else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -860,6 +906,8 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "chunks") *value = ctx->stats.chunks;
   else if (k == "block") *value = ctx->stats.block;
   else if (k == "kchunk") *value = ctx->stats.kchunk;
+  else if (k == "rr_sweeps") *value = ctx->stats.rr_sweeps;
+  else if (k == "coarse_iters") *value = ctx->stats.coarse_iters;
   else if (k.rfind("prof.", 0) == 0) {
     const size_t dot = k.rfind('.');
     const std::string cls = k.substr(5, dot - 5), f = k.substr(dot + 1);
@@ -1059,7 +1107,9 @@ static int bands_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho, int
     om_tmp.resize((size_t)nk * nbands);
     omega = om_tmp.data();
   }
-  int rc = run_design(ctx, d, q, nk, nbands, prec, omega, ebound, sel, sens);
+  Design dcs;
+  Design* dc = coarse_design(ctx, *cell, rho, nullptr, dcs);
+  int rc = run_design(ctx, d, q, nk, nbands, prec, omega, ebound, sel, sens, dc);
   if (rc != PHX_OK && rc != PHX_ENOCONV) return rc;
   hipStream_t st = ctx->stream;
   if (nsens > 0 && domega) {
@@ -1149,7 +1199,9 @@ static int dev_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, i
   double* sens = domega_dev;
   if (nsens > 0 && !sens) sens = dbuf<double>(ctx, "sens", (long)nk * nsens * nvox);
   std::vector<double> om((size_t)nk * nbands);
-  const int rc = run_design(ctx, d, q_host, nk, nbands, prec, om.data(), nullptr, sel, sens);
+  Design dcs;
+  Design* dc = coarse_design(ctx, *cell, rh.data(), rho_dev, dcs);
+  const int rc = run_design(ctx, d, q_host, nk, nbands, prec, om.data(), nullptr, sel, sens, dc);
   if (omega_dev)
     HIPCHK(hipMemcpyAsync(omega_dev, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, st));
   if (grad_dev) {

@@ -9,15 +9,19 @@
 // rr_eig: Rayleigh-Ritz on an Omega-orthonormal basis: eigen-decomposition of the
 //   Hermitian G = S^H K S by cyclic parallel Jacobi (round-robin pair ordering),
 //   returning the s lowest eigenpairs.  Dropped columns get a large diagonal so they
-//   are never selected.  An off-diagonal entry below 1e-18 of its two diagonal
-//   entries is set to zero instead of rotated, and the sweeps stop once a sweep
-//   performs no rotation (or the off-diagonal mass is negligible).
+//   are never selected.  A pair (p, q) is rotated only while |a_pq| exceeds both
+//   1e-15 sqrt(|a_pp a_qq|) (relative accuracy of the small eigenvalues) and
+//   1e-18 of the largest kept diagonal entry (the zero modes at Gamma); a rotated
+//   pair's off-diagonal entries are then set to zero exactly rather than left at
+//   rounding level, so a sweep without rotations is reached and ends the loop.
 #include "phx_common.h"
 #include "phx_physics.h"
 
 namespace phx {
 
-__global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m, double drop, double2* C0,
+constexpr int SMALL_NT = 1024;  // threads per workgroup of the small kernels (latency bound)
+
+__global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, int m, double drop, double2* C0,
                                                         int* keep) {
   __shared__ double2 Ls[64][65];  // [col][row]
   __shared__ double2 Xs[64][65];
@@ -27,7 +31,7 @@ __global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m,
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
   const double2* Gk = G + (long)k * m * m;
-  for (int e = tid; e < m * m; e += 256) {
+  for (int e = tid; e < m * m; e += SMALL_NT) {
     const int i = e % m, j = e / m;
     const double2 a = Gk[i + j * m], b = Gk[j + i * m];
     Ls[j][i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m,
     kp[tid] = ok ? 1 : 0;
   }
   __syncthreads();
-  for (int e = tid; e < m * m; e += 256) {
+  for (int e = tid; e < m * m; e += SMALL_NT) {
     const int i = e % m, j = e / m;
     Ls[j][i] = cscale(Ls[j][i], D[i] * D[j]);
   }
@@ -63,7 +67,7 @@ __global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m,
     }
     __syncthreads();
     if (pc > 0) {
-      for (int e = tid; e < m * m; e += 256) {
+      for (int e = tid; e < m * m; e += SMALL_NT) {
         const int i = e % m, j = e / m;
         if (j > c && i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(Ls[c][i], Ls[c][j]));
       }
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m,
     __syncthreads();
   }
   double2* Ck = C0 + (long)k * m * m;
-  for (int e = tid; e < m * m; e += 256) {
+  for (int e = tid; e < m * m; e += SMALL_NT) {
     const int r = e % m, c = e / m;
     // C0[r][c] = D_r conj(Linv[c][r]), Linv[c][r] = Xs[r][c]
     double2 v = make_double2(0, 0);
@@ -95,16 +99,15 @@ __global__ __launch_bounds__(256) void chol_drop_kernel(const double2* G, int m,
   if (tid < m) keep[k * m + tid] = kp[tid];
 }
 
-__global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int* keep, int m, int s, double2* C,
+__global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, const int* keep, int m, int s, double2* C,
                                                      double* theta, int* sweeps_out) {
   __shared__ double2 As[64][65];  // [col][row]
   __shared__ double2 Vs[64][65];
   __shared__ int pp[32], qq[32];
   __shared__ double cs_[32], sn_[32];
   __shared__ double2 ph_[32];
-  __shared__ double red[256], red2[256];
+  __shared__ double red[SMALL_NT], red2[SMALL_NT];
   __shared__ int order[64];
-  __shared__ int used[64];
   __shared__ int stop;
   __shared__ int rotated;
   const int tid = threadIdx.x;
@@ -114,16 +117,28 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
   const int mm = (m + 1) & ~1;
   // Hermitian part restricted to kept columns; a scale for the large diagonal.
   double amax = 0;
-  for (int e = tid; e < m * m; e += 256) amax = fmax(amax, sqrt(cabs2(Gk[e])));
+  for (int e = tid; e < m * m; e += SMALL_NT) amax = fmax(amax, sqrt(cabs2(Gk[e])));
   red[tid] = amax;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = SMALL_NT / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
     __syncthreads();
   }
   const double big = 1e3 * red[0] + 1.0;
   __syncthreads();
-  for (int e = tid; e < mm * mm; e += 256) {
+  // largest kept diagonal entry: the absolute floor of the rotation threshold
+  double dmax = 0;
+  for (int i = tid; i < m; i += SMALL_NT)
+    if (kk[i]) dmax = fmax(dmax, fabs(Gk[i + i * m].x));
+  red[tid] = dmax;
+  __syncthreads();
+  for (int w = SMALL_NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double floor_abs = 1e-18 * red[0] + 1e-300;
+  __syncthreads();
+  for (int e = tid; e < mm * mm; e += SMALL_NT) {
     const int i = e % mm, j = e / mm;
     double2 v = make_double2(0, 0);
     if (i < m && j < m) {
@@ -145,7 +160,7 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
   const int half = mm / 2;
   for (sw = 0; sw < 40; ++sw) {
     double off = 0, dg = 0;
-    for (int e = tid; e < mm * mm; e += 256) {
+    for (int e = tid; e < mm * mm; e += SMALL_NT) {
       const int i = e % mm, j = e / mm;
       const double a2 = cabs2(As[j][i]);
       if (i == j) dg += a2; else off += a2;
@@ -153,7 +168,7 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
     red[tid] = off;
     red2[tid] = dg;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = SMALL_NT / 2; w > 0; w >>= 1) {
       if (tid < w) {
         red[tid] += red[tid + w];
         red2[tid] += red2[tid + w];
@@ -182,8 +197,8 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
         }
         double cs = 1.0, sn = 0.0;
         double2 ph = make_double2(1.0, 0.0);
-        if (!(ac > 1e-300 && ac > 1e-18 * (fabs(a) + fabs(b)))) {
-          // below the rounding floor of its diagonal: set to zero (this pair owns both entries)
+        if (!(ac > floor_abs && ac > 1e-15 * sqrt(fabs(a) * fabs(b)))) {
+          // below the thresholds: set to zero (this pair owns both entries)
           As[q][p] = make_double2(0.0, 0.0);
           As[p][q] = make_double2(0.0, 0.0);
         } else {
@@ -200,7 +215,7 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int e = tid; e < half * mm; e += 256) {
+      for (int e = tid; e < half * mm; e += SMALL_NT) {
         const int i = e / mm, row = e % mm;
         const int p = pp[i], q = qq[i];
         const double cs = cs_[i], sn = sn_[i];
@@ -216,7 +231,7 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
       }
       __syncthreads();
       // rows: A <- J^H A
-      for (int e = tid; e < half * mm; e += 256) {
+      for (int e = tid; e < half * mm; e += SMALL_NT) {
         const int i = e / mm, col = e % mm;
         const int p = pp[i], q = qq[i];
         const double cs = cs_[i], sn = sn_[i];
@@ -227,26 +242,29 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
         As[col][q] = cadd(cscale(ap, sn), cscale(phaq, cs));
       }
       __syncthreads();
-    }
-  }
-  if (tid == 0) {
-    // selection of the s lowest diagonal entries (stable in index order)
-    for (int i = 0; i < mm; ++i) used[i] = 0;
-    for (int j = 0; j < s; ++j) {
-      int best = -1;
-      double bv = 0;
-      for (int i = 0; i < m; ++i) {
-        if (used[i]) continue;
-        const double d = As[i][i].x;
-        if (best < 0 || d < bv) { best = i; bv = d; }
+      if (tid < half && sn_[tid] != 0.0) {
+        const int p = pp[tid], q = qq[tid];
+        As[q][p] = make_double2(0.0, 0.0);
+        As[p][q] = make_double2(0.0, 0.0);
+        As[p][p].y = 0.0;
+        As[q][q].y = 0.0;
       }
-      used[best] = 1;
-      order[j] = best;
+      __syncthreads();
     }
-    if (sweeps_out) sweeps_out[k] = sw;
   }
+  // selection of the s lowest diagonal entries (ties in index order): each entry's rank
+  if (tid < m) {
+    const double d = As[tid][tid].x;
+    int rank = 0;
+    for (int i = 0; i < m; ++i) {
+      const double di = As[i][i].x;
+      rank += (di < d || (di == d && i < tid)) ? 1 : 0;
+    }
+    if (rank < s) order[rank] = tid;
+  }
+  if (tid == 0 && sweeps_out) sweeps_out[k] = sw;
   __syncthreads();
-  for (int e = tid; e < m * s; e += 256) {
+  for (int e = tid; e < m * s; e += SMALL_NT) {
     const int r = e % m, j = e / m;
     C[(long)k * m * s + r + (long)j * m] = Vs[order[j]][r];
   }
@@ -254,12 +272,12 @@ __global__ __launch_bounds__(256) void rr_eig_kernel(const double2* G, const int
 }
 
 void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st) {
-  hipLaunchKernelGGL(chol_drop_kernel, dim3(nk), dim3(256), 0, st, G, m, drop, C0, keep);
+  hipLaunchKernelGGL(chol_drop_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, m, drop, C0, keep);
 }
 
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta, int* sweeps,
                    hipStream_t st) {
-  hipLaunchKernelGGL(rr_eig_kernel, dim3(nk), dim3(256), 0, st, G, keep, m, s, C, theta, sweeps);
+  hipLaunchKernelGGL(rr_eig_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, keep, m, s, C, theta, sweeps);
 }
 
 }  // namespace phx

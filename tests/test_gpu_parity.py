@@ -284,3 +284,25 @@ def test_small_eig(ctx, m, s):
         R = G[b][np.ix_(k, k)] @ Ck[k] - Ck[k] * th[b][None, :]
         assert np.abs(R).max() < 1e-11 * np.abs(G[b]).max()
         assert np.abs(np.conj(Ck.T) @ Ck - np.eye(s)).max() < 1e-12
+
+
+@pytest.mark.parametrize("m,s,nzero", [(63, 21, 3), (63, 21, 0), (45, 16, 0)])
+def test_small_eig_graded_near_diagonal(ctx, m, s, nzero):
+    """Rayleigh-Ritz matrices near convergence: a graded diagonal (exact zeros for the
+    Gamma acoustic modes, then five decades) plus a Hermitian coupling scaled like
+    sqrt(d_i d_j); eigenvalues to 1e-12 relative (1e-15 of the largest for the zeros)."""
+    rng = np.random.default_rng(m + s + nzero)
+    d = np.sort(10.0 ** rng.uniform(-2, 3, m))
+    d[:nzero] = 0.0
+    E = _rand(rng, 2, m, m)
+    E = 0.5 * (E + np.conj(np.transpose(E, (0, 2, 1))))
+    sc = np.sqrt(np.outer(d, d))
+    G = np.stack([np.diag(d) + 1e-4 * E[b] * sc for b in range(2)])
+    keep = np.ones((2, m), dtype=np.int32)
+    C, th = ctx.small_eig(G, keep, s)
+    for b in range(2):
+        ref = np.linalg.eigvalsh(G[b])[:s]
+        tol = np.maximum(1e-12 * np.abs(ref), 1e-15 * d.max())
+        assert np.all(np.abs(th[b] - ref) <= tol), np.abs(th[b] - ref) / np.maximum(np.abs(ref), 1e-300)
+        R = G[b] @ C[b] - C[b] * th[b][None, :]
+        assert np.abs(R).max() < 1e-12 * d.max()
