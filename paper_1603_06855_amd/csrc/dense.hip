@@ -260,66 +260,63 @@ template int zgemm<float>(const GemmArgs<float>&, int, int, hipStream_t);
 // factorisation stays finite; the host turns the flag into an error.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void potrf_diag_kernel(C_t<R>* A, long lda, long sA, int j0,
-                                                         C_t<R>* Dinv, long sD, int* flag) {
+__global__ __launch_bounds__(1024) void potrf_diag_kernel(C_t<R>* A, long lda, long sA, int j0,
+                                                          C_t<R>* Dinv, long sD, int* flag) {
   typedef C_t<R> C;
   __shared__ C Ls[64][65];  // Ls[col][row]
-  __shared__ C Xs[64][65];
-  __shared__ R piv;
+  __shared__ C Xs[64][65];  // L^{-1}, Xs[col][row]
+  __shared__ R pivs[64];
   const int tid = threadIdx.x;
   C* Ab = A + (long)blockIdx.x * sA + j0 + (long)j0 * lda;
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += 1024) {
     const int i = e & 63, j = e >> 6;
     Ls[j][i] = (i >= j) ? Ab[i + (long)j * lda] : mk<R>(0, 0);
+    Xs[j][i] = mk<R>(i == j ? (R)1 : (R)0, 0);
   }
   __syncthreads();
+  // Right-looking: the pivot is read by every thread, column k is scaled, then the
+  // trailing lower triangle takes the rank-1 update.  The factor's diagonal is kept
+  // in pivs (the unscaled Ls[k][k] stays in place until the end).
   for (int k = 0; k < 64; ++k) {
+    R d = Ls[k][k].x;
+    const bool bad = !(d > 0) || !isfinite((double)d);
+    if (bad) d = 1;
+    const R piv = sqrt(d);
     if (tid == 0) {
-      R d = Ls[k][k].x;
-      if (!(d > 0) || !isfinite((double)d)) {
-        atomicOr(flag, isfinite((double)d) ? PHX_FLAG_NOTPD : PHX_FLAG_NONFINITE);
-        d = 1;
-      }
-      d = sqrt(d);
-      Ls[k][k] = mk<R>(d, 0);
-      piv = d;
+      if (bad) atomicOr(flag, isfinite((double)Ls[k][k].x) ? PHX_FLAG_NOTPD : PHX_FLAG_NONFINITE);
+      pivs[k] = piv;
     }
+    if (tid > k && tid < 64) Ls[k][tid] = cscale(Ls[k][tid], (R)1 / piv);
     __syncthreads();
-    const R inv = (R)1 / piv;
-    if (tid > k && tid < 64) Ls[k][tid] = cscale(Ls[k][tid], inv);
-    __syncthreads();
-    for (int e = tid; e < 4096; e += 256) {
+    for (int e = tid; e < 4096; e += 1024) {
       const int i = e & 63, j = e >> 6;
       if (j > k && i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(Ls[k][i], Ls[k][j]));
     }
     __syncthreads();
   }
-  // Inverse of the lower factor, one row at a time; thread t owns column t.
+  if (tid < 64) Ls[tid][tid] = mk<R>(pivs[tid], 0);
+  // Inverse of the lower factor by right-looking substitution on the identity:
+  // row i of X is final once divided by the pivot; it then updates the rows below.
   for (int i = 0; i < 64; ++i) {
-    if (tid < 64) {
-      const int t = tid;
-      C v = mk<R>(0, 0);
-      if (t <= i) {
-        C s = mk<R>(t == i ? (R)1 : (R)0, 0);
-        for (int l = t; l < i; ++l) s = csub(s, cmul(Ls[l][i], Xs[t][l]));
-        const R d = Ls[i][i].x;
-        v = cscale(s, (R)1 / d);
-      }
-      Xs[t][i] = v;
+    if (tid <= i) Xs[tid][i] = cscale(Xs[tid][i], (R)1 / pivs[i]);
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 1024) {
+      const int r = e & 63, t = e >> 6;
+      if (r > i && t <= i) Xs[t][r] = csub(Xs[t][r], cmul(Ls[i][r], Xs[t][i]));
     }
     __syncthreads();
   }
-  for (int e = tid; e < 4096; e += 256) {
+  for (int e = tid; e < 4096; e += 1024) {
     const int i = e & 63, j = e >> 6;
     if (i >= j) Ab[i + (long)j * lda] = Ls[j][i];
-    Dinv[(long)blockIdx.x * sD + (long)(j0 >> 6) * 4096 + i + 64 * j] = Xs[j][i];
+    Dinv[(long)blockIdx.x * sD + (long)(j0 >> 6) * 4096 + i + 64 * j] = (i >= j) ? Xs[j][i] : mk<R>(0, 0);
   }
 }
 
 template <typename R>
 int potrf_diag(C_t<R>* A, long lda, long sA, int batch, int j0, C_t<R>* Dinv, long sD, int* flag,
                hipStream_t st) {
-  hipLaunchKernelGGL((potrf_diag_kernel<R>), dim3(batch), dim3(256), 0, st, A, lda, sA, j0, Dinv, sD, flag);
+  hipLaunchKernelGGL((potrf_diag_kernel<R>), dim3(batch), dim3(1024), 0, st, A, lda, sA, j0, Dinv, sD, flag);
   return (int)hipGetLastError();
 }
 template int potrf_diag<double>(double2*, long, long, int, int, double2*, long, int*, hipStream_t);

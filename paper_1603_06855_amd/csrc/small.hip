@@ -110,6 +110,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
   __shared__ int order[64];
   __shared__ int stop;
   __shared__ int rotated;
+  __shared__ int nact;
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
   const double2* Gk = G + (long)k * m * m;
@@ -182,8 +183,13 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
     __syncthreads();
     if (stop) break;
     for (int r = 0; r < mm - 1; ++r) {
+      // Pair setup (wave 0): rotations below threshold are skipped; the pairs that do
+      // rotate are compacted so that the two update phases touch only their columns.
+      bool act = false;
+      int p = 0, q = 0;
+      double cs = 1.0, sn = 0.0;
+      double2 ph = make_double2(1.0, 0.0);
       if (tid < half) {
-        int p, q;
         if (tid == 0) { p = r; q = mm - 1; }
         else { p = (r + tid) % (mm - 1); q = (r - tid + mm - 1) % (mm - 1); }
         const double a = As[p][p].x, b = As[q][q].x;
@@ -195,14 +201,12 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
           const double xr = c.x / cm, yr = c.y / cm;
           ac = cm * sqrt(xr * xr + yr * yr);
         }
-        double cs = 1.0, sn = 0.0;
-        double2 ph = make_double2(1.0, 0.0);
         if (!(ac > floor_abs && ac > 1e-15 * sqrt(fabs(a) * fabs(b)))) {
           // below the thresholds: set to zero (this pair owns both entries)
           As[q][p] = make_double2(0.0, 0.0);
           As[p][q] = make_double2(0.0, 0.0);
         } else {
-          rotated = 1;
+          act = true;
           ph = make_double2(c.x / ac, -c.y / ac);
           const double tau = (b - a) / (2.0 * ac);
           double t;
@@ -211,11 +215,23 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
           cs = 1.0 / sqrt(1.0 + t * t);
           sn = t * cs;
         }
-        pp[tid] = p; qq[tid] = q; cs_[tid] = cs; sn_[tid] = sn; ph_[tid] = ph;
+      }
+      if (tid < 64) {
+        const unsigned long long mask = __ballot(act);
+        if (act) {
+          const int slot = __popcll(mask & ((1ull << tid) - 1ull));
+          pp[slot] = p; qq[slot] = q; cs_[slot] = cs; sn_[slot] = sn; ph_[slot] = ph;
+        }
+        if (tid == 0) {
+          nact = __popcll(mask);
+          if (nact) rotated = 1;
+        }
       }
       __syncthreads();
+      const int na = nact;
+      if (na == 0) continue;  // uniform: every thread read the same count after the barrier
       // columns: A <- A J, V <- V J
-      for (int e = tid; e < half * mm; e += SMALL_NT) {
+      for (int e = tid; e < na * mm; e += SMALL_NT) {
         const int i = e / mm, row = e % mm;
         const int p = pp[i], q = qq[i];
         const double cs = cs_[i], sn = sn_[i];
@@ -231,7 +247,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
       }
       __syncthreads();
       // rows: A <- J^H A
-      for (int e = tid; e < half * mm; e += SMALL_NT) {
+      for (int e = tid; e < na * mm; e += SMALL_NT) {
         const int i = e / mm, col = e % mm;
         const int p = pp[i], q = qq[i];
         const double cs = cs_[i], sn = sn_[i];
@@ -242,7 +258,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
         As[col][q] = cadd(cscale(ap, sn), cscale(phaq, cs));
       }
       __syncthreads();
-      if (tid < half && sn_[tid] != 0.0) {
+      if (tid < na) {
         const int p = pp[tid], q = qq[tid];
         As[q][p] = make_double2(0.0, 0.0);
         As[p][q] = make_double2(0.0, 0.0);
