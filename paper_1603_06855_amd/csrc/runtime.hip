@@ -640,14 +640,15 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     cholqr(sv);
     cholqr(sv);
     rayleigh_ritz(sv);
-    // K X and Omega X afresh from the Ritz vectors: the residual then never inherits the
-    // rounding drift that the implicit recurrences KX <- KS C accumulate over iterations.
-    // Near convergence the previous direction P is a small difference of nearly equal
-    // vectors, so its recurrence-built images lose accuracy relative to P itself; they
-    // are recomputed too.
-    if (it > 0) {
+    // The images K X, Omega X (and those of the previous direction P) follow the basis
+    // through the same coefficient updates.  Their rounding drift grows like the unit
+    // roundoff over the size of P, which shrinks with the residual, so once the residual
+    // is small enough for that drift to reach the tolerance they are recomputed from
+    // the Ritz vectors every iteration (with FP64 unit roundoff: residual below 1e-13/tol,
+    // i.e. only the last iterations of an FP64-tolerance solve).
+    if (it > 0 && near) {
       apply_ops(sv, sv.Big, 0, s);
-      if (near) apply_ops(sv, sv.Big, 2 * s, s);
+      apply_ops(sv, sv.Big, 2 * s, s);
     }
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
@@ -687,7 +688,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       out.converged = true;
       break;
     }
-    near = near || worst < 1e-5;
+    near = near || worst < 1e-13 / tol;
     if (it == ctx->opt.maxit) break;
     precondition<R>(sv);
     apply_ops(sv, sv.Big, s, s);
