@@ -64,13 +64,19 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
-  ACC cr[2][2], ci[2][2];
+  // FP32: three real products per complex product (Karatsuba): t1 = Re A Re B,
+  // t2 = Im A Im B, t3 = (Re A + Im A)(Re B + Im B); Re C = t1 - t2, Im C = t3 - t1 - t2.
+  // FP64: four products (t1 = Re C, t3 = Im C, t2 unused): the third accumulator set
+  // would halve the occupancy of the FP64 tiles.
+  constexpr bool K3 = sizeof(R) == 4;
+  ACC t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      cr[i][j] = (ACC){0, 0, 0, 0};
-      ci[i][j] = (ACC){0, 0, 0, 0};
+      t1[i][j] = (ACC){0, 0, 0, 0};
+      t2[i][j] = (ACC){0, 0, 0, 0};
+      t3[i][j] = (ACC){0, 0, 0, 0};
     }
 
   // Group index gi = tid + 256 * r.  OPA = 0 (A column-major, contiguous in i): group
@@ -140,22 +146,32 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      R ar[2], ai[2], br[2], bi[2];
+      R ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
         ai[x] = Asi[kr][wr * 32 + x * 16 + (lane & 15)];
         br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
         bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
+        if (K3) {
+          as[x] = ar[x] + ai[x];
+          bs[x] = br[x] + bi[x];
+        }
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          cr[x][y] = mfma16(br[y], ar[x], cr[x][y]);
-          ci[x][y] = mfma16(bi[y], ar[x], ci[x][y]);
-          cr[x][y] = mfma16(-bi[y], ai[x], cr[x][y]);
-          ci[x][y] = mfma16(br[y], ai[x], ci[x][y]);
+          if (K3) {
+            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+            t2[x][y] = mfma16(bi[y], ai[x], t2[x][y]);
+            t3[x][y] = mfma16(bs[y], as[x], t3[x][y]);
+          } else {
+            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+            t3[x][y] = mfma16(bi[y], ar[x], t3[x][y]);
+            t1[x][y] = mfma16(-bi[y], ai[x], t1[x][y]);
+            t3[x][y] = mfma16(br[y], ai[x], t3[x][y]);
+          }
         }
     }
   }
@@ -177,7 +193,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
         // row l/16 + 4r of the 16x16 block, column l%16 in both (here rows are C columns).
         const int col = col0 + wc * 32 + y * 16 + (sizeof(R) == 8 ? ((lane >> 4) + 4 * r) : (((lane >> 4) << 2) + r));
         if (row < g.M && col < g.N) {
-          C acc = mk<R>(cr[x][y][r], ci[x][y][r]);
+          C acc = K3 ? mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r])
+                     : mk<R>(t1[x][y][r], t3[x][y][r]);
           C v = cmul(g.alpha, acc);
           if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * ldc]));
           Cb[row + (long)col * ldc] = v;
