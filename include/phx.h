@@ -87,7 +87,9 @@ const char* phx_last_error(const phx_ctx* ctx);
  * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
  * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
  * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
- * "mem_gb" (device memory budget for one k-chunk, default 64), "coarse" (1:
+ * "mem_gb" (device memory budget for one k-chunk, default 64; per worker
+ * context of phx_sens_batch_dev), "streams" (1..8, see phx_sens_batch_dev),
+ * "coarse" (1:
  * for M >= 4 every k-chunk is first solved at order M-2 to the residual
  * "coarse_tol", default 1e-3, and its Ritz vectors, embedded in the order-M
  * plane-wave set, start the order-M solve; 0: start from plane-wave unit
@@ -185,6 +187,18 @@ int phx_bands_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int
 int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
                  int nbands, phx_precision prec, int nsens, const int* band_no, double* omega_dev,
                  double* domega_dev, void* stream);
+/* Several designs (cells may differ in lattice, nv and M) at the same k-points:
+ * rho_dev[d] (nv_d^3), omega_dev[d] (nk * nbands), domega_dev[d]
+ * (nk * nsens * nv_d^3, only if nsens > 0; domega_dev may be NULL otherwise)
+ * are device arrays.  The designs are spread over up to "streams" (option,
+ * default 4) worker contexts, each with its own HIP stream and workspaces, so
+ * the latency-bound steps of one design overlap the matrix-core work of
+ * another; the highest M goes first.  Statistics and kernel-class timers of
+ * the workers are merged into ctx.  Returns the first error (naming the
+ * design), else PHX_ENOCONV if any design did not converge. */
+int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const double* const* rho_dev, int nk,
+                       const double* q_host, int nbands, phx_precision prec, int nsens, const int* band_no,
+                       double* const* omega_dev, double* const* domega_dev, void* stream);
 /* grad_dev = sum_{k, j} weight_dev[k * nsens + j] d omega_{band_no[j]}(k) / d rho_e
  * (the backward of any objective of the band frequencies); omega_dev may be NULL. */
 int phx_adjoint_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,

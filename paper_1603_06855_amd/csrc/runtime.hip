@@ -17,11 +17,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <map>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/phx.h"
@@ -46,6 +48,7 @@ struct Opts {
   double mem_gb = 64.0;
   int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
+  int streams = 4;           // designs solved concurrently by the batched call
 };
 
 struct Stats {
@@ -152,6 +155,7 @@ struct phx_ctx {
   Stats stats;
   bool trace = false;
   Profiler prof;
+  std::vector<phx_ctx*> workers;  // contexts (own stream and workspaces) of the batched call
   phx::ProfHook hook{hook_begin, hook_end, nullptr};
   const phx::ProfHook* hk() {
     hook.user = &prof;
@@ -860,12 +864,15 @@ int phx_create(phx_ctx** out, int hip_device) {
     delete c;
     return PHX_EHIP;
   }
+  c->prof.st = c->stream;
   *out = c;
   return PHX_OK;
 }
 
 int phx_destroy(phx_ctx* ctx) {
   if (!ctx) return PHX_EINVAL;
+  for (phx_ctx* w : ctx->workers) phx_destroy(w);
+  ctx->workers.clear();
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->bufs)
@@ -894,6 +901,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
   else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
+  else if (k == "streams") { if (!(v >= 1 && v <= 8)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -1242,6 +1250,91 @@ int phx_adjoint_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, i
     if (nsens < 1) fail(ctx, PHX_EINVAL, "nsens must be at least 1");
     return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, nullptr, weight_dev,
                     grad_dev, stream);
+  });
+}
+
+int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const double* const* rho_dev, int nk,
+                       const double* q_host, int nbands, phx_precision prec, int nsens, const int* band_no,
+                       double* const* omega_dev, double* const* domega_dev, void* stream) {
+  return guard(ctx, [&]() {
+    if (ndesign < 1 || !cells || !rho_dev || !omega_dev) fail(ctx, PHX_EINVAL, "ndesign, cells, rho_dev and omega_dev are required");
+    if (nsens > 0 && !domega_dev) fail(ctx, PHX_EINVAL, "domega_dev is NULL");
+    check_q(ctx, q_host, nk);
+    for (int d = 0; d < ndesign; ++d) {
+      check_cell(ctx, &cells[d]);
+      check_bands(ctx, &cells[d], nbands, nsens, band_no);
+      if (!rho_dev[d] || !omega_dev[d] || (nsens > 0 && !domega_dev[d]))
+        fail(ctx, PHX_EINVAL, "a per-design pointer is NULL");
+    }
+    if (prec != PHX_FP64 && prec != PHX_MIXED) fail(ctx, PHX_EINVAL, "unknown precision");
+    if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int nw = std::min(ctx->opt.streams, ndesign);
+    while ((int)ctx->workers.size() < nw) {
+      phx_ctx* w = nullptr;
+      if (phx_create(&w, ctx->device) != PHX_OK) fail(ctx, PHX_EHIP, "could not create a worker stream");
+      ctx->workers.push_back(w);
+    }
+    for (int i = 0; i < nw; ++i) {
+      ctx->workers[i]->opt = ctx->opt;
+      ctx->workers[i]->prof.on = ctx->prof.on;
+      ctx->workers[i]->trace = ctx->trace;
+    }
+    // most expensive designs first: the per-k cost grows like (3N)^3
+    std::vector<int> order(ndesign);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cells[a].M > cells[b].M; });
+    std::atomic<int> next(0);
+    std::vector<int> rcs(ndesign, PHX_OK);
+    std::vector<std::string> errs(ndesign);
+    auto work = [&](phx_ctx* w) {
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= ndesign) break;
+        const int d = order[i];
+        rcs[d] = guard(w, [&]() {
+          return dev_impl(w, &cells[d], rho_dev[d], nk, q_host, nbands, prec, nsens, band_no, omega_dev[d],
+                          nsens > 0 ? domega_dev[d] : nullptr, nullptr, nullptr, nullptr);
+        });
+        if (rcs[d] != PHX_OK) errs[d] = w->err;
+      }
+    };
+    if (nw == 1) {
+      work(ctx->workers[0]);
+    } else {
+      std::vector<std::thread> th;
+      for (int i = 0; i < nw; ++i) th.emplace_back(work, ctx->workers[i]);
+      for (auto& t : th) t.join();
+    }
+    ctx->stats = Stats();
+    for (int i = 0; i < nw; ++i) {
+      phx_ctx* w = ctx->workers[i];
+      for (int c = 0; c < PROF_NCLASS; ++c) {
+        ctx->prof.acc[c].ms += w->prof.acc[c].ms;
+        ctx->prof.acc[c].flops += w->prof.acc[c].flops;
+        ctx->prof.acc[c].bytes += w->prof.acc[c].bytes;
+        ctx->prof.acc[c].count += w->prof.acc[c].count;
+      }
+      w->prof.reset();
+      ctx->stats.iters = std::max(ctx->stats.iters, w->stats.iters);
+      ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, w->stats.rr_sweeps);
+      ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, w->stats.coarse_iters);
+      ctx->stats.chunks += w->stats.chunks;
+      ctx->stats.block = std::max(ctx->stats.block, w->stats.block);
+      ctx->stats.kchunk = std::max(ctx->stats.kchunk, w->stats.kchunk);
+    }
+    int worst = PHX_OK;
+    for (int d = 0; d < ndesign; ++d) {
+      if (rcs[d] < 0 && rcs[d] != PHX_ENOCONV) {
+        ctx->err = "design " + std::to_string(d) + ": " + errs[d];
+        return rcs[d];
+      }
+      if (rcs[d] == PHX_ENOCONV) {
+        worst = PHX_ENOCONV;
+        ctx->err = "design " + std::to_string(d) + ": " + errs[d];
+      }
+    }
+    return worst;
   });
 }
 

@@ -71,6 +71,8 @@ def load():
                                  c_void_p, c_void_p]),
         "phx_adjoint_dev": (c_int, [P, POINTER(Cell), c_void_p, c_int, D, c_int, c_int, c_int, I, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
+        "phx_sens_batch_dev": (c_int, [P, c_int, POINTER(Cell), POINTER(c_void_p), c_int, D, c_int, c_int, c_int,
+                                       I, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
         "phx_zgemm": (c_int, [P, c_int, c_char, c_char, c_int, c_int, c_int, D, D, c_long, c_long, D, c_long,
                               c_long, D, D, c_long, c_long, c_int]),
         "phx_zposv": (c_int, [P, c_int, c_int, c_int, c_int, D, D]),
@@ -287,6 +289,28 @@ class Context:
                                              PRECISION[precision], len(b), _iptr(b), c_void_p(w.data_ptr()), None,
                                              c_void_p(g.data_ptr()), c_void_p(stream)))
         return g
+
+    def sens_batch_dev(self, cells, rhos, q, nbands: int, band_no: Sequence[int] = (), precision: str = "fp64"):
+        """Several designs (device float64 tensors, uneven M allowed) in one call; returns
+        (omega list, domega list or None) as device tensors."""
+        import torch
+        nd = len(cells)
+        carr = (Cell * nd)(*[make_cell(c) for c in cells])
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        nk = qq.shape[0]
+        b = np.ascontiguousarray(band_no, dtype=np.int32)
+        rs = [r.detach().contiguous().to(torch.float64).reshape(-1) for r in rhos]
+        dev = rs[0].device
+        oms = [torch.empty((nk, nbands), dtype=torch.float64, device=dev) for _ in range(nd)]
+        dws = [torch.empty((nk, len(b), r.numel()), dtype=torch.float64, device=dev) for r in rs] if len(b) else None
+        VP = c_void_p * nd
+        rp = VP(*[r.data_ptr() for r in rs])
+        op = VP(*[o.data_ptr() for o in oms])
+        dp = VP(*[d.data_ptr() for d in dws]) if dws is not None else None
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self._check(self.lib.phx_sens_batch_dev(self.h, nd, carr, rp, nk, _dptr(qq), nbands, PRECISION[precision],
+                                                len(b), _iptr(b) if len(b) else None, op, dp, c_void_p(stream)))
+        return oms, dws
 
     # -------------------------------------------------------------- dense building blocks
     def zgemm(self, opa: str, opb: str, A, B, C=None, alpha=1.0, beta=0.0, precision: str = "fp64"):

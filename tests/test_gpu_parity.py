@@ -306,3 +306,20 @@ def test_small_eig_graded_near_diagonal(ctx, m, s, nzero):
         assert np.all(np.abs(th[b] - ref) <= tol), np.abs(th[b] - ref) / np.maximum(np.abs(ref), 1e-300)
         R = G[b] @ C[b] - C[b] * th[b][None, :]
         assert np.abs(R).max() < 1e-12 * d.max()
+
+
+def test_sens_batch_uneven_m_matches_single_design_calls(ctx):
+    """Designs of different lattice and M through the concurrent batched call give exactly
+    the per-design results (same kernels, same inputs, deterministic reductions)."""
+    import torch
+    from oracle import geometry
+    specs = [("FCC", 9, 4, 11), ("SC", 8, 2, 12), ("BCC", 9, 3, 13), ("FCC", 9, 2, 14), ("SC", 9, 4, 15)]
+    cells = [synth.Cell(lat, 1.0, nv, M) for lat, nv, M, _ in specs]
+    rhos = [torch.from_numpy(synth.box_smoothed_uniform(nv, seed)).to("cuda:0") for _, nv, _, seed in specs]
+    q = geometry.kpath("SC", 10, "GXMGR")[[1, 4, 7]]
+    ctx.set_option("streams", 3)
+    oms, dws = ctx.sens_batch_dev(cells, rhos, q, 8, (2, 5), "mixed")
+    for c, r, om, dw in zip(cells, rhos, oms, dws):
+        om1, dw1 = ctx.sens_dev(c, r, q, 8, (2, 5), "mixed")
+        assert torch.equal(om, om1) and torch.equal(dw, dw1), c
+    ctx.set_option("streams", 4)
