@@ -125,6 +125,7 @@ def main():
             "frac": achieved / (PEAK[fp] / 1e12), "traffic": None, "kernel": name, "dtype": fp,
             "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1),
             "flops_per_launch": p["flops"] / max(p["count"], 1)}
+    roof["traffic"] = measured_traffic(name)
     other = [c for c in single if c != dom][0]
     po = prof[other]
     roof["next"] = {"kernel": single[other][0], "achieved": po["flops"] / max(po["ms"], 1e-9) / 1e9,
@@ -160,6 +161,25 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "herk_fcc32_m5_traffic.md")
+    if kernel != "phx::zgemm_kernel<float, 0, 1, 64, 64, 1>" or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    src = os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "dense.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(M: int):

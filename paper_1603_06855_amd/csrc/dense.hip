@@ -40,9 +40,21 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WM, wc = wave / WM;
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by linear id, so
+  // the linear ids are remapped to give every XCD one contiguous range of
+  // (tile, batch) indices; neighbouring tiles share operand panels in that XCD's L2.
+  long tile_lin, bat;
+  {
+    const long nx = gridDim.x, total = nx * (long)gridDim.y;
+    const long lin = blockIdx.x + nx * (long)blockIdx.y;
+    const long per = total / 8, rem = total % 8, xcd = lin % 8, idx = lin / 8;
+    const long logical = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    tile_lin = logical % nx;
+    bat = logical / nx;
+  }
   int ti, tj;
   if (MODE == 1) {
-    const long t = blockIdx.x;
+    const long t = tile_lin;
     long r = (long)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
     while (r * (r + 1) / 2 > t) --r;
@@ -50,11 +62,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
     tj = (int)(t - r * (r + 1) / 2);
   } else {
     const int tm = (g.M + BM - 1) / BM;
-    ti = blockIdx.x % tm;
-    tj = blockIdx.x / tm;
+    ti = (int)(tile_lin % tm);
+    tj = (int)(tile_lin / tm);
   }
   const int row0 = ti * BM, col0 = tj * BN;
-  const int b = blockIdx.y;
+  const int b = (int)bat;
   const int sp = blockIdx.z;
   const C* A = g.A + (long)(b / g.dA) * g.sA;
   const C* B = g.B + (long)(b / g.dB) * g.sB;
