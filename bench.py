@@ -36,7 +36,8 @@ def main():
     ap.add_argument("--nk", type=int, default=60)
     ap.add_argument("--M", type=int, default=5)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--streams", type=int, default=4, help="designs solved concurrently (library option)")
+    ap.add_argument("--streams", type=int, default=8, help="designs solved concurrently (library option)")
+    ap.add_argument("--coarse-tol", type=float, default=None, help="library option coarse_tol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gate", action="store_true", help="skip the mixed-vs-FP64 accuracy gate")
     args = ap.parse_args()
@@ -62,6 +63,8 @@ def main():
     torch.cuda.synchronize()
 
     ctx.set_option("streams", args.streams)
+    if args.coarse_tol is not None:
+        ctx.set_option("coarse_tol", args.coarse_tol)
 
     def step():
         # every design of the step through one batched call (designs spread over

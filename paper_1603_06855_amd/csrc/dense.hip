@@ -440,12 +440,13 @@ template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, 
 //   UPPER (L^H Y = Z):  for t = T-1..0:  Y_t = Dinv_t^H Z_t;  Z_u -= L_tu^H Y_t (u < t)
 // The super-block's right-hand side (rows J0 .. J0 + 64T of Bin) is held in LDS;
 // the solution rows go to X.  The rest of the solve is a GEMM per super-block.
-// Wave w computes 16-row stripes; MFMA k-index mapping: k = 4 ks + lane/16 when
+// Sixteen waves: waves 0-3 compute the diagonal tile's 16-row stripes, then every wave
+// takes update stripes; MFMA k-index mapping: k = 4 ks + lane/16 when
 // the operand is read down columns (coalesced over rows), k = 16 (lane/16) + ks
 // when it is read along columns of L (each lane walks contiguous memory).
 // ---------------------------------------------------------------------------
 template <typename R, bool LOWER, int WS>
-__global__ __launch_bounds__(256) void trsv_block_kernel(const C_t<R>* L, long lda, long sL, const C_t<R>* Dinv,
+__global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long lda, long sL, const C_t<R>* Dinv,
                                                          long sD, const C_t<R>* Bin, long ldb, long sB, C_t<R>* X,
                                                          long ldx, long sX, int J0, int T, int nc) {
   typedef C_t<R> C;
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(256) void trsv_block_kernel(const C_t<R>* L, long l
   const C* Bb = Bin + b * sB;
   C* Xb = X + b * sX;
   const int rows = 64 * T;
-  for (int e = tid; e < rows * 32; e += 256) {
+  for (int e = tid; e < rows * 32; e += 1024) {
     const int r = e % rows, c = e / rows;
     C v = mk<R>(0, 0);
     if (c < nc) v = Bb[(J0 + r) + (long)c * ldb];
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void trsv_block_kernel(const C_t<R>* L, long l
       cr[y] = (ACC){0, 0, 0, 0};
       ci[y] = (ACC){0, 0, 0, 0};
     }
-    {  // diagonal tile: rows 16 wave .. +16 of Dinv_t (or Dinv_t^H) times the tile's rhs
+    if (wave < 4) {  // diagonal tile: rows 16 wave .. +16 of Dinv_t (or Dinv_t^H) times the tile's rhs
       const C* Dt = Db + (long)((J0 >> 6) + t) * 4096;
       const int i = 16 * wave + li;
       C av[16];  // all 16 operand loads in flight before the first product
@@ -505,18 +506,20 @@ __global__ __launch_bounds__(256) void trsv_block_kernel(const C_t<R>* L, long l
       }
     }
     __syncthreads();
+    if (wave < 4) {
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = tb + 16 * wave + li, col = 16 * y + colmap(r);
-        Sr[row][SW(row, col)] = cr[y][r];
-        Si[row][SW(row, col)] = ci[y][r];
-        if (col < nc) Xb[(J0 + row) + (long)col * ldx] = mk<R>(cr[y][r], ci[y][r]);
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int row = tb + 16 * wave + li, col = 16 * y + colmap(r);
+          Sr[row][SW(row, col)] = cr[y][r];
+          Si[row][SW(row, col)] = ci[y][r];
+          if (col < nc) Xb[(J0 + row) + (long)col * ldx] = mk<R>(cr[y][r], ci[y][r]);
+        }
+    }
     __syncthreads();
     const int nu = LOWER ? T - 1 - t : t;
-    for (int q = wave; q < 4 * nu; q += 4) {
+    for (int q = wave; q < 4 * nu; q += 16) {
       const int u = LOWER ? t + 1 + q / 4 : q / 4;
       const int r0 = 64 * u + 16 * (q % 4);
 #pragma unroll
@@ -570,7 +573,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
   for (int sbi = 0; sbi < nsb; ++sbi) {  // forward: L Z = B
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
-    hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch), dim3(256), 0, st, L, lda, sL, Dinv, sD, B,
+    hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, B,
                        ldb, sB, Z, ldz, sZ, J0, T, nc);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;
@@ -591,7 +594,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
   for (int sbi = nsb - 1; sbi >= 0; --sbi) {  // backward: L^H Y = Z, Y into B
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
-    hipLaunchKernelGGL((trsv_block_kernel<R, false, WS>), dim3(batch), dim3(256), 0, st, L, lda, sL, Dinv, sD, Z,
+    hipLaunchKernelGGL((trsv_block_kernel<R, false, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, Z,
                        ldz, sZ, B, ldb, sB, J0, T, nc);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;

@@ -47,6 +47,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m "
                           "paper_1603_06855_amd.build")
+    # PyTorch carries its own HIP runtime (same soname).  Loaded first, it is the one
+    # libphx.so binds to, so tensors' device pointers and torch streams are objects of
+    # the library's own runtime, and torch keeps seeing the device.  Without torch the
+    # system ROCm runtime is used.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     D = POINTER(c_double)
     I = POINTER(c_int)

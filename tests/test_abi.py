@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -99,3 +100,18 @@ def test_create_without_device_reports_ehip():
     lib = phx.load()
     h = ctypes.c_void_p()
     assert lib.phx_create(ctypes.byref(h), 0) == phx.EHIP
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library and then using torch must leave a single HIP runtime in the
+    process (two runtimes would not share devices, pointers or streams)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1603_06855_amd import phx\n"
+            "phx.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = sorted(set(l.split()[-1] for l in maps if 'libamdhip64' in l))\n"
+            "print(len(libs), libs)\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("1 "), out.stdout

@@ -1,0 +1,92 @@
+"""GPU: the larger workloads end to end through the C ABI.
+
+* BCC primitive cell, 24^3 blurred-ball design, M=4, 48 k-points, 12 bands: the
+  mixed-precision path against the FP64 path at every band and k (per-band error
+  reported), and the FP64 path against the oracle at two k-points.
+* FCC primitive cell, 32^3, 16 designs of uneven M in {3, 4, 5}, 60 k-points, 12 bands
+  and the adjoint of bands 6/7 through one batched call: every design converges, the
+  batch equals per-design calls, and the M=3 designs match the oracle at one k-point.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1603_06855_amd import phx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = phx.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(om, ref):
+    scale = ref.max()
+    rel = np.abs(om - ref) / np.maximum(ref, 1e-300)
+    acoustic = ref < 1e-3 * scale
+    rel[acoustic] = np.abs(om - ref)[acoustic] / scale * 1e-3
+    return rel
+
+
+def test_bcc_blob_m4_mixed_vs_fp64_and_oracle(ctx):
+    from oracle import geometry, solve
+    wl = synth.config3()
+    cell, rho = wl.cells[0], wl.designs[0]
+    q = phx.kpath(cell.lattice, wl.nk, wl.path)
+    t = time.time()
+    ctx.set_option("tol_fp64", 1e-10)
+    om64 = ctx.bands(cell, rho, q, wl.nbands, "fp64")
+    it64 = ctx.stat("iters")
+    t64 = time.time() - t
+    t = time.time()
+    om32 = ctx.bands(cell, rho, q, wl.nbands, "mixed")
+    t32 = time.time() - t
+    per_band = _rel(om32, om64).max(axis=0)
+    log("BCC 24^3 M=4 blob, 48 k: fp64", round(t64, 3), "s (iters", it64, "), mixed", round(t32, 3),
+        "s; mixed vs fp64 per band:", " ".join(f"{e:.1e}" for e in per_band))
+    assert per_band.max() <= 1e-6
+    Q = geometry.kpath(cell.lattice, wl.nk, wl.path)
+    ks = [5, 29]
+    t = time.time()
+    ref = solve.bands(cell, rho, Q[ks], wl.nbands)
+    log("oracle 2 k", round(time.time() - t, 1), "s")
+    err = _rel(om64[ks], ref)
+    log("fp64 vs oracle", err.max())
+    assert err.max() <= 1e-9
+    ctx.set_option("tol_fp64", 1e-8)
+
+
+def test_fcc_uneven_m_batch(ctx):
+    import torch
+    from oracle import geometry, solve
+    wl = synth.config4(all_m5=False, ndesign=16)
+    q = phx.kpath("FCC", wl.nk, wl.path)
+    rhos = [torch.from_numpy(d).to("cuda:0") for d in wl.designs]
+    t = time.time()
+    oms, dws = ctx.sens_batch_dev(wl.cells, rhos, q, wl.nbands, wl.sens_bands, "mixed")
+    torch.cuda.synchronize()
+    log("FCC 32^3 uneven M x16, 60 k, batched:", round(time.time() - t, 2), "s; iters", ctx.stat("iters"))
+    for d in (0, 1, 2):  # one design of each M
+        om1, dw1 = ctx.sens_dev(wl.cells[d], rhos[d], q, wl.nbands, wl.sens_bands, "mixed")
+        assert torch.equal(oms[d], om1) and torch.equal(dws[d], dw1)
+    for d in range(16):
+        assert torch.isfinite(oms[d]).all() and torch.isfinite(dws[d]).all()
+    # the M=3 designs against the oracle at one k-point
+    Q = geometry.kpath("FCC", wl.nk, wl.path)
+    k = 17
+    for d in (0, 3):
+        assert wl.cells[d].M == 3
+        ref = solve.bands(wl.cells[d], wl.designs[d], Q[[k]], wl.nbands)
+        err = _rel(oms[d].cpu().numpy()[[k]], ref)
+        log("design", d, "M=3 mixed vs oracle at k", k, err.max())
+        assert err.max() <= 1e-6
