@@ -38,6 +38,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--streams", type=int, default=8, help="designs solved concurrently (library option)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="library option coarse_tol")
+    ap.add_argument("--shift", type=float, default=None, help="library option shift")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gate", action="store_true", help="skip the mixed-vs-FP64 accuracy gate")
     args = ap.parse_args()
@@ -65,6 +66,8 @@ def main():
     ctx.set_option("streams", args.streams)
     if args.coarse_tol is not None:
         ctx.set_option("coarse_tol", args.coarse_tol)
+    if args.shift is not None:
+        ctx.set_option("shift", args.shift)
 
     def step():
         # every design of the step through one batched call (designs spread over

@@ -214,6 +214,72 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
       }
 }
 
+// Tall-skinny products C = A W (beta = 0, alpha = 1) with K, N <= 64: the subspace
+// updates [S | KS | Omega S] C of the eigensolver.  W (at most 64 x 64) is staged in LDS
+// once per workgroup; the A operand goes straight from global memory into MFMA operand
+// registers (16 consecutive rows per load), so a workgroup is one pass over 128 rows
+// without a k-loop pipeline.  Wave w computes rows 32 w .. 32 w + 31 in two stripes.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void skinny_kernel(GemmArgs<R> g) {
+  typedef C_t<R> C;
+  typedef typename acc_t<R>::type ACC;
+  __shared__ R Wr[64][65], Wi[64][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int b = blockIdx.y;
+  const C* A = g.A + (long)(b / g.dA) * g.sA;
+  const C* W = g.B + (long)(b / g.dB) * g.sB;
+  C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int k = e & 63, j = e >> 6;
+    C v = mk<R>(0, 0);
+    if (k < g.K && j < g.N) v = W[k + (long)j * g.ldb];
+    Wr[k][j] = v.x;
+    Wi[k][j] = v.y;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int stripe = 0; stripe < 2; ++stripe) {
+    const int i0 = blockIdx.x * 128 + wave * 32 + 16 * stripe;
+    if (i0 >= g.M) break;
+    const int i = i0 + li;
+    ACC cr[NB], ci[NB];
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      cr[y] = (ACC){0, 0, 0, 0};
+      ci[y] = (ACC){0, 0, 0, 0};
+    }
+#pragma unroll 1
+    for (int kg = 0; kg < 4; ++kg) {  // four groups of four k-steps: loads of a group in flight together
+      C av[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 16 * kg + 4 * q + lg;
+        av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 16 * kg + 4 * q + lg;
+#pragma unroll
+        for (int y = 0; y < NB; ++y) {
+          const R br = Wr[k][16 * y + li], bi = Wi[k][16 * y + li];
+          cr[y] = mfma16(br, av[q].x, cr[y]);
+          ci[y] = mfma16(bi, av[q].x, ci[y]);
+          cr[y] = mfma16(-bi, av[q].y, cr[y]);
+          ci[y] = mfma16(br, av[q].y, ci[y]);
+        }
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = 16 * y + (sizeof(R) == 8 ? (lg + 4 * r) : (4 * lg + r));
+        if (i < g.M && col < g.N) Cb[i + (long)col * g.ldc] = mk<R>(cr[y][r], ci[y][r]);
+      }
+  }
+}
+
 template <typename R>
 __global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
@@ -240,6 +306,14 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.K <= 0) {  // C = beta C
     g.ksplit = 1;
+  }
+  // Tall-skinny updates (the eigensolver's basis times a small coefficient matrix).
+  if (opa == 0 && opb == 0 && !g.tri && !g.op && g.ksplit == 1 && g.K <= 64 && g.N <= 64 && g.M >= 256 &&
+      g.alpha.x == 1 && g.alpha.y == 0 && g.beta.x == 0 && g.beta.y == 0) {
+    dim3 grid2((unsigned)((g.M + 127) / 128), (unsigned)g.batch);
+    if (g.N <= 32) hipLaunchKernelGGL((skinny_kernel<R, 2>), grid2, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((skinny_kernel<R, 4>), grid2, dim3(256), 0, st, g);
+    return (int)hipGetLastError();
   }
   // Narrow outputs (N <= 32: triangular solves and updates with the s search
   // vectors) use 128 x 32 tiles; everything else 64 x 64.

@@ -49,6 +49,21 @@ def test_zgemm(ctx, prec, tol, opa, opb, m, n, k, batch):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-5)])
+@pytest.mark.parametrize("m,n,k,batch", [(4032, 63, 63, 3), (600, 21, 42, 2), (257, 64, 17, 1), (300, 5, 64, 2)])
+def test_zgemm_tall_skinny(ctx, prec, tol, m, n, k, batch):
+    """C = A W with K, N <= 64 and many rows (the eigensolver's basis updates) takes the
+    tall-skinny kernel; ragged rows and columns included."""
+    log("zgemm skinny", prec, m, n, k, batch)
+    rng = np.random.default_rng(m + n + k)
+    A = _rand(rng, batch, m, k)
+    B = _rand(rng, batch, k, n)
+    got = ctx.zgemm("N", "N", A, B, None, 1.0, 0.0, precision=prec)
+    ref = A @ B
+    err = np.abs(got - ref).max() / (np.abs(A).max() * np.abs(B).max() * k)
+    assert err < tol, err
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 5e-4)])
 @pytest.mark.parametrize("n,nrhs,batch", [(64, 3, 1), (192, 21, 2), (320, 7, 3)])
 def test_zposv(ctx, prec, tol, n, nrhs, batch):
