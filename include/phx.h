@@ -87,6 +87,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
  * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
  * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
+ * "rr_fused" (1, default: one Omega-orthonormalisation of the search basis,
+ * the second folded into the Rayleigh-Ritz step in the small m x m space, except
+ * in the last iterations of a solve whose residual is below 1e-13/tolerance; 0:
+ * always two explicit orthonormalisations of the basis before Rayleigh-Ritz),
  * "mem_gb" (device memory budget for one k-chunk, default 64; per worker
  * context of phx_sens_batch_dev), "streams" (1..8, see phx_sens_batch_dev),
  * "coarse" (1:
@@ -233,6 +237,15 @@ int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, cons
 int phx_small_orth(phx_ctx* ctx, int m, int batch, const double* G, double drop, double* C0, int* keep);
 int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const int* keep, double* C,
                   double* theta);
+/* phx_small_rr: Rayleigh-Ritz on a basis S that is only approximately
+ * Omega-orthonormal, from G2 = S^H [K S | Omega S] (m x 2m per batch item):
+ * Omega-Cholesky with scaling and dropping as phx_small_orth, then the s lowest
+ * eigenpairs of the projected K.  Cx (m x s): Ritz-vector coefficients in S
+ * ((S Cx)^H Omega (S Cx) = I, G_K Cx = G_Omega Cx diag(theta)); Cp (m x s): the
+ * same with only the contributions of columns s.. of the orthonormalised basis
+ * (the previous-direction update); keep (m): columns kept by the Cholesky. */
+int phx_small_rr(phx_ctx* ctx, int m, int s, int batch, const double* G2, double drop, double* Cx, double* Cp,
+                 double* theta, int* keep);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,7 @@ struct Opts {
   int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
   int streams = 4;           // designs solved concurrently by the batched call
+  int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
 };
 
 struct Stats {
@@ -417,6 +418,7 @@ struct Solver {
   double* sigma_d;
   double2 *Y, *Tr, *Zy, *Zt;
   double2 *G, *Gpart, *C0, *Cr;
+  double2 *G2, *G2part, *Cp;
   int* keep;
   int* sweeps;
   double *theta, *rn, *rnorm;
@@ -526,6 +528,30 @@ void rayleigh_ritz(Solver& sv) {
   std::swap(sv.Big, sv.Big2);
 }
 
+// Rayleigh-Ritz on the once-orthonormalised basis: both Gram matrices S^H [KS | Omega S]
+// in one GEMM, the small kernel re-orthonormalises in the m x m space and solves the
+// projected problem, and the Ritz vectors X and previous directions P are formed from
+// the whole basis with the combined coefficients.
+void rayleigh_ritz_fused(Solver& sv) {
+  phx_ctx* ctx = sv.ctx;
+  const long n3 = sv.n3, m = sv.m, s = sv.s;
+  PROF_BEGIN(PROF_GRAM);
+  gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
+               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part);
+  PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nk, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nk);
+  PROF_BEGIN(PROF_SMALL);
+  launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cr, sv.Cp, sv.theta, sv.sweeps, ctx->stream);
+  PROF_END(PROF_SMALL, 0, 0);
+  KCHK(hipGetLastError());
+  PROF_BEGIN(PROF_UPDATE);
+  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
+               ZERO);
+  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, m * s, 3, sv.Big2 + 2 * s * n3, n3,
+               n3 * m, ONE, ZERO);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nk, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
+  std::swap(sv.Big, sv.Big2);
+}
+
 template <typename R>
 void precondition(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
@@ -573,6 +599,9 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.Gpart = dbuf<double2>(ctx, "Gpart", (long)sv.ksplit * nk * m * m);
   sv.C0 = dbuf<double2>(ctx, "C0", (long)nk * m * m);
   sv.Cr = dbuf<double2>(ctx, "Cr", (long)nk * m * s);
+  sv.Cp = dbuf<double2>(ctx, "Cp", (long)nk * m * s);
+  sv.G2 = dbuf<double2>(ctx, "G2", (long)nk * 2 * m * m);
+  sv.G2part = dbuf<double2>(ctx, "G2part", (long)sv.ksplit * nk * 2 * m * m);
   sv.keep = dbuf<int>(ctx, "keep", (long)nk * m);
   sv.sweeps = dbuf<int>(ctx, "sweeps", nk);
   sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
@@ -642,8 +671,16 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   bool near = false;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
     cholqr(sv);
-    cholqr(sv);
-    rayleigh_ritz(sv);
+    // The folded form multiplies the Gram matrix of K by the second orthonormalisation's
+    // coefficients in the small space, which amplifies its rounding when the basis is
+    // nearly dependent; near convergence (the same test as for recomputing the images)
+    // the second orthonormalisation is applied to the basis explicitly.
+    if (ctx->opt.rr_fused && !near) {
+      rayleigh_ritz_fused(sv);
+    } else {
+      cholqr(sv);
+      rayleigh_ritz(sv);
+    }
     // The images K X, Omega X (and those of the previous direction P) follow the basis
     // through the same coefficient updates.  Their rounding drift grows like the unit
     // roundoff over the size of P, which shrinks with the residual, so once the residual
@@ -902,6 +939,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
   else if (k == "streams") { if (!(v >= 1 && v <= 8)) return bad(); ctx->opt.streams = (int)v; }
+  else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -1416,6 +1454,31 @@ int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const 
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(C, dc, (long)m * s * batch * sizeof(double2), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(theta, dt, (long)s * batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PHX_OK;
+  });
+}
+
+int phx_small_rr(phx_ctx* ctx, int m, int s, int batch, const double* G2, double drop, double* Cx, double* Cp,
+                 double* theta, int* keep) {
+  return guard(ctx, [&]() {
+    if (m < 1 || m > 64 || s < 1 || s > m || batch < 1 || !G2 || !Cx || !Cp || !theta || !keep || !(drop > 0))
+      fail(ctx, PHX_EINVAL, "bad arguments");
+    hipStream_t st = ctx->stream;
+    const long n2 = 2L * m * m * batch, ns = (long)m * s * batch;
+    double2* dg = dbuf<double2>(ctx, "tA", n2);
+    double2* dc0 = dbuf<double2>(ctx, "tB", (long)m * m * batch);
+    double2* dx = dbuf<double2>(ctx, "tC", ns);
+    double2* dp = dbuf<double2>(ctx, "tD", ns);
+    int* dk = dbuf<int>(ctx, "tK", (long)m * batch);
+    double* dt = dbuf<double>(ctx, "tT", (long)s * batch);
+    HIPCHK(hipMemcpyAsync(dg, G2, n2 * sizeof(double2), hipMemcpyHostToDevice, st));
+    launch_rr_gen(dg, m, s, batch, drop, dc0, dk, dx, dp, dt, nullptr, st);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(Cx, dx, ns * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(Cp, dp, ns * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(theta, dt, (long)s * batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(keep, dk, (long)m * batch * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return PHX_OK;
   });

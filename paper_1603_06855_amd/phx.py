@@ -86,6 +86,7 @@ def load():
         "phx_zposv": (c_int, [P, c_int, c_int, c_int, c_int, D, D]),
         "phx_small_orth": (c_int, [P, c_int, c_int, D, c_double, D, I]),
         "phx_small_eig": (c_int, [P, c_int, c_int, c_int, D, I, D, D]),
+        "phx_small_rr": (c_int, [P, c_int, c_int, c_int, D, c_double, D, D, D, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -381,3 +382,17 @@ class Context:
         self._check(self.lib.phx_small_eig(self.h, m, s, batch, _dptr(np.ascontiguousarray(Gf)), _iptr(k), _dptr(C),
                                            _dptr(th)))
         return C.view(np.complex128).reshape(batch, s, m).transpose(0, 2, 1), th.reshape(batch, s)
+
+    def small_rr(self, G2, s: int, drop: float = 1e-12):
+        """G2: (batch, m, 2m) = S^H [K S | Omega S]; returns Cx, Cp (batch, m, s), theta, keep."""
+        G2 = np.asarray(G2, dtype=np.complex128)
+        batch, m, _ = G2.shape
+        Gf = np.concatenate([np.asfortranarray(g).reshape(-1, order="F") for g in G2]).view(np.float64)
+        Cx = np.zeros(2 * m * s * batch)
+        Cp = np.zeros(2 * m * s * batch)
+        th = np.zeros(s * batch)
+        keep = np.zeros(m * batch, dtype=np.int32)
+        self._check(self.lib.phx_small_rr(self.h, m, s, batch, _dptr(np.ascontiguousarray(Gf)), drop, _dptr(Cx),
+                                          _dptr(Cp), _dptr(th), _iptr(keep)))
+        f = lambda a: a.view(np.complex128).reshape(batch, s, m).transpose(0, 2, 1)
+        return f(Cx), f(Cp), th.reshape(batch, s), keep.reshape(batch, m)

@@ -169,6 +169,20 @@ def test_bands_mixed_config1(ctx, config1_ref):
     assert err.max() <= 1e-6
 
 
+@pytest.mark.parametrize("fused", [0, 1])
+def test_bands_fp64_config1_both_rayleigh_ritz_forms(ctx, config1_ref, fused):
+    """The Rayleigh-Ritz step with the second orthonormalisation folded into the small
+    problem and the one with two explicit orthonormalisations both meet the FP64 bar."""
+    cell, rho, Q, ref = config1_ref
+    ctx.set_option("rr_fused", fused)
+    ctx.set_option("tol_fp64", 1e-10)
+    om = ctx.bands(cell, rho, Q, ref.shape[1], "fp64")
+    log("rr_fused", fused, "iters", ctx.stat("iters"), "max rel err", _om_err(om, ref).max())
+    ctx.set_option("rr_fused", 1)
+    ctx.set_option("tol_fp64", 1e-8)
+    assert _om_err(om, ref).max() <= 1e-9
+
+
 @pytest.mark.parametrize("lat", ["SC", "BCC", "FCC"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_homogeneous_closed_form(ctx, lat, prec):
@@ -338,3 +352,40 @@ def test_sens_batch_uneven_m_matches_single_design_calls(ctx):
         om1, dw1 = ctx.sens_dev(c, r, q, 8, (2, 5), "mixed")
         assert torch.equal(om, om1) and torch.equal(dw, dw1), c
     ctx.set_option("streams", 4)
+
+
+@pytest.mark.parametrize("m,s,ndep", [(63, 21, 0), (48, 16, 3), (54, 18, 0), (9, 4, 1)])
+def test_small_rr_generalised(ctx, m, s, ndep):
+    """Rayleigh-Ritz from the two Gram matrices of a non-orthonormal basis (with dependent
+    and zero columns): Omega-orthonormal Ritz vectors, the pencil's lowest eigenvalues on
+    the kept subspace, and the previous-direction coefficients."""
+    rng = np.random.default_rng(m + s + ndep)
+    n = 200
+    S = _rand(rng, 2, n, m)
+    for b in range(2):
+        for d in range(ndep):
+            S[b, :, 3 + 2 * d] = S[b, :, 0] * (1.5 + d)
+        if ndep:
+            S[b, :, m - 1] = 0
+    Kh = _rand(rng, n, n)
+    K = Kh @ np.conj(Kh.T) / n
+    W = np.diag(1.0 + rng.random(n))
+    G2 = np.concatenate([np.conj(np.transpose(S, (0, 2, 1))) @ K @ S,
+                         np.conj(np.transpose(S, (0, 2, 1))) @ W @ S], axis=2)
+    Cx, Cp, th, keep = ctx.small_rr(G2, s)
+    import scipy.linalg as sla
+    for b in range(2):
+        X = S[b] @ Cx[b]
+        assert np.abs(np.conj(X.T) @ W @ X - np.eye(s)).max() < 1e-10
+        # Galerkin condition: the residual is orthogonal to every basis column
+        R = np.conj(S[b].T) @ (K @ X - W @ X * th[b][None, :])
+        assert np.abs(R).max() < 1e-9 * np.abs(K).max() * np.abs(S[b]).max() * n
+        # the lowest eigenvalues of the pencil on the span of the kept columns
+        Q, _ = np.linalg.qr(S[b][:, keep[b].astype(bool)])
+        ref = sla.eigh(np.conj(Q.T) @ K @ Q, np.conj(Q.T) @ W @ Q, eigvals_only=True)[:s]
+        assert np.abs(th[b] - ref).max() < 1e-11 * np.abs(ref).max()
+        assert keep[b].sum() == m - (ndep + 1 if ndep else 0)
+        # X - P lies in the span of the first s basis columns (the Cholesky is triangular)
+        D = S[b] @ (Cx[b] - Cp[b])
+        coef, *_ = np.linalg.lstsq(S[b][:, :s], D, rcond=None)
+        assert np.abs(S[b][:, :s] @ coef - D).max() < 1e-9 * max(np.abs(D).max(), 1.0)
