@@ -171,7 +171,8 @@ def main():
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none or the kernel source changed since it was taken."""
+    summary, or None when there is none or the kernel's source text (the GEMM kernel
+    template's definition) changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "herk_fcc32_m5_traffic.md")
     if kernel != "phx::zgemm_kernel<float, 0, 1, 64, 64, 1>" or not os.path.exists(path):
@@ -181,8 +182,10 @@ def measured_traffic(kernel: str):
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
-    src = os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "dense.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    src = open(os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "dense.hip")).read()
+    start = src.index("template <typename R, int OPA, int OPB, int BM, int BN, int MODE>")
+    end = src.index("\n}\n", start) + 3  # the kernel's definition
+    sha = hashlib.sha256(src[start:end].encode()).hexdigest()
     if fields.get("kernel_source_sha256") != sha:
         return None
     return float(fields["traffic_bytes_per_launch"])
