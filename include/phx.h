@@ -87,6 +87,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
  * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
  * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
+ * "sbinv" (1, default: the preconditioner's triangular solves use explicit
+ * inverses of the factor's 256-wide (FP64: 128-wide) diagonal blocks, computed
+ * once per factorisation, so every solve step is a matrix product; 0: blocked
+ * substitution inside each diagonal block),
  * "rr_fused" (1, default: one Omega-orthonormalisation of the search basis,
  * the second folded into the Rayleigh-Ritz step in the small m x m space, except
  * in the last iterations of a solve whose residual is below 1e-13/tolerance; 0:
@@ -222,7 +226,9 @@ int phx_zgemm(phx_ctx* ctx, phx_precision prec, char opa, char opb, int m, int n
 
 /* Batched Hermitian positive definite solve A_b X_b = B_b by Cholesky: A is
  * batch x n x n (lower triangle read), B is batch x n x nrhs; X overwrites B.
- * n must be a multiple of 64.  PHX_ENOTPD if a pivot is not positive. */
+ * n must be a multiple of 64.  PHX_ENOTPD if a pivot is not positive.  With the
+ * option "sbinv" set, solves with at most 32 right-hand sides go through the
+ * diagonal super-block inverses, as in the eigensolver. */
 int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, const double* A, double* B);
 
 /* Small dense kernels of the block eigensolver (one workgroup per batch item,

@@ -519,10 +519,14 @@ template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, 
 // the operand is read down columns (coalesced over rows), k = 16 (lane/16) + ks
 // when it is read along columns of L (each lane walks contiguous memory).
 // ---------------------------------------------------------------------------
+// inv_n > 0 selects the inverse mode (LOWER only): the right-hand side is the identity,
+// the workgroup (b, J, c) solves columns 32c .. 32c + 31 of L_JJ^{-1} for the diagonal
+// super-block J0 = J WS of a matrix of order inv_n, and writes them to
+// X + b sX + J WS^2 (a WS x WS column-major block, ld WS).
 template <typename R, bool LOWER, int WS>
 __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long lda, long sL, const C_t<R>* Dinv,
                                                          long sD, const C_t<R>* Bin, long ldb, long sB, C_t<R>* X,
-                                                         long ldx, long sX, int J0, int T, int nc) {
+                                                         long ldx, long sX, int J0, int T, int nc, int inv_n) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
   __shared__ R Sr[WS][32], Si[WS][32];
@@ -534,13 +538,22 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long 
   const long b = blockIdx.x;
   const C* Lb = L + b * sL;
   const C* Db = Dinv + b * sD;
-  const C* Bb = Bin + b * sB;
   C* Xb = X + b * sX;
+  int c0 = 0;
+  if (inv_n > 0) {
+    J0 = blockIdx.y * WS;
+    T = min(WS, inv_n - J0) / 64;
+    c0 = blockIdx.z * 32;
+    if (c0 >= 64 * T) return;  // the whole workgroup: columns beyond the block
+    nc = 32;
+    Xb += (long)blockIdx.y * WS * WS - J0 + (long)c0 * ldx;  // row J0 + r of the solution -> row r
+  }
   const int rows = 64 * T;
   for (int e = tid; e < rows * 32; e += 1024) {
     const int r = e % rows, c = e / rows;
     C v = mk<R>(0, 0);
-    if (c < nc) v = Bb[(J0 + r) + (long)c * ldb];
+    if (inv_n > 0) v = mk<R>(r == c0 + c ? (R)1 : (R)0, 0);
+    else if (c < nc) v = Bin[b * sB + (J0 + r) + (long)c * ldb];
     Sr[r][SW(r, c)] = v.x;
     Si[r][SW(r, c)] = v.y;
   }
@@ -636,6 +649,92 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long 
 #undef SW
 }
 
+// Explicit inverses of the diagonal super-blocks of a batch of Cholesky factors
+// (WS x WS blocks, ld WS, nsb = ceil(n / WS) per matrix, batch stride nsb WS^2): one
+// launch of the super-block kernel in inverse mode.  With them every step of a narrow
+// solve is a GEMM (no sequential dependency inside a super-block).
+template <typename R>
+int sb_inverse_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+                       C_t<R>* SBinv, hipStream_t st) {
+  constexpr int WS = sizeof(R) == 4 ? 256 : 128;
+  const int nsb = (n + WS - 1) / WS;
+  hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch, nsb, WS / 32), dim3(1024), 0, st, L, lda, sL,
+                     Dinv, sD, (const C_t<R>*)nullptr, 0L, 0L, SBinv, (long)WS, (long)nsb * WS * WS, 0, 0, 0, n);
+  return (int)hipGetLastError();
+}
+template int sb_inverse_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*,
+                                        hipStream_t);
+template int sb_inverse_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*,
+                                       hipStream_t);
+
+// Narrow solve with the super-block inverses: per super-block one GEMM with the inverse
+// (or its conjugate transpose) and one GEMM for the rows beyond it.
+template <typename R>
+int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* SBinv, C_t<R>* B, long ldb,
+                long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook) {
+  constexpr int WS = sizeof(R) == 4 ? 256 : 128;
+  const double cb = (double)sizeof(C_t<R>);
+  const int nsb = (n + WS - 1) / WS;
+  const long sI = (long)nsb * WS * WS;
+  int e;
+  for (int sbi = 0; sbi < nsb; ++sbi) {  // forward: L Z = B
+    const int J0 = sbi * WS, w = std::min(WS, n - J0);
+    {
+      GemmArgs<R> g{};
+      g.M = w; g.N = nc; g.K = w; g.batch = batch;
+      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;
+      g.B = B + J0; g.ldb = ldb; g.sB = sB;
+      g.Cm = Z + J0; g.ldc = ldz; g.sC = sZ;
+      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
+      if (e) return e;
+    }
+    const int rem = n - J0 - w;
+    if (rem > 0) {
+      GemmArgs<R> g{};
+      g.M = rem; g.N = nc; g.K = w; g.batch = batch;
+      g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL;
+      g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
+      g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * rem * w * nc, batch * cb * ((double)rem * w + 2.0 * rem * nc));
+      if (e) return e;
+    }
+  }
+  for (int sbi = nsb - 1; sbi >= 0; --sbi) {  // backward: L^H Y = Z, Y into B
+    const int J0 = sbi * WS, w = std::min(WS, n - J0);
+    {
+      GemmArgs<R> g{};
+      g.M = w; g.N = nc; g.K = w; g.batch = batch;
+      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;  // op = C: the inverse of L_JJ^H
+      g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
+      g.Cm = B + J0; g.ldc = ldb; g.sC = sB;
+      g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      e = zgemm<R>(g, 1, 0, st);
+      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
+      if (e) return e;
+    }
+    if (J0 > 0) {
+      GemmArgs<R> g{};
+      g.M = J0; g.N = nc; g.K = w; g.batch = batch;
+      g.A = L + J0; g.lda = lda; g.sA = sL;  // rows J0..J0+w, cols 0..J0-1; op = C
+      g.B = B + J0; g.ldb = ldb; g.sB = sB;
+      g.Cm = Z; g.ldc = ldz; g.sC = sZ;
+      g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      e = zgemm<R>(g, 1, 0, st);
+      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * J0 * w * nc, batch * cb * ((double)J0 * w + 2.0 * J0 * nc));
+      if (e) return e;
+    }
+  }
+  return 0;
+}
+
 // Narrow solve (nc <= 32): super-block kernels plus one GEMM per super-block.
 template <typename R>
 int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD, C_t<R>* B,
@@ -648,7 +747,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
     hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, B,
-                       ldb, sB, Z, ldz, sZ, J0, T, nc);
+                       ldb, sB, Z, ldz, sZ, J0, T, nc, 0);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;
     const int rem = n - J0 - w;
@@ -669,7 +768,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
     hipLaunchKernelGGL((trsv_block_kernel<R, false, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, Z,
-                       ldz, sZ, B, ldb, sB, J0, T, nc);
+                       ldz, sZ, B, ldb, sB, J0, T, nc, 0);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;
     if (J0 > 0) {
@@ -696,7 +795,8 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook) {
+                  const ProfHook* hook, const C_t<R>* sbinv) {
+  if (nc <= 32 && sbinv) return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   if (nc <= 32) return potrs_narrow<R>(L, n, lda, sL, batch, Dinv, sD, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   const int T = n / 64;
   const double cb = (double)sizeof(C_t<R>);
@@ -758,8 +858,8 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
   return 0;
 }
 template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
-                                   long, double2*, long, long, int, hipStream_t, const ProfHook*);
+                                   long, double2*, long, long, int, hipStream_t, const ProfHook*, const double2*);
 template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
-                                  long, float2*, long, long, int, hipStream_t, const ProfHook*);
+                                  long, float2*, long, long, int, hipStream_t, const ProfHook*, const float2*);
 
 }  // namespace phx

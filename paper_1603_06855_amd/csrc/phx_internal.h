@@ -51,9 +51,17 @@ template <typename R>
 int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, long sD, int* flag,
                   hipStream_t st, const ProfHook* hook = nullptr);
 
+// sbinv (may be NULL): inverses of the diagonal super-blocks from sb_inverse_batched;
+// given, narrow solves (nc <= 32) run as GEMMs only.
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook = nullptr);
+                  const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr);
+
+// Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
+// Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS).
+template <typename R>
+int sb_inverse_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+                       C_t<R>* SBinv, hipStream_t st);
 
 }  // namespace phx

@@ -50,6 +50,7 @@ struct Opts {
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
   int streams = 4;           // designs solved concurrently by the batched call
   int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
+  int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
 };
 
 struct Stats {
@@ -424,6 +425,7 @@ struct Solver {
   double *theta, *rn, *rnorm;
   void* A;     // nk x n3 x n3 (prec)
   void* Dinv;  // nk x n3/64 x 4096 (prec)
+  void* SBinv; // nk x nsb x WS^2 inverses of the factor's diagonal super-blocks, or NULL
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -557,7 +559,8 @@ void precondition(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3;
   KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
-                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk()));
+                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk(),
+                        (const C_t<R>*)sv.SBinv));
   launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream);
   KCHK(hipGetLastError());
 }
@@ -571,7 +574,9 @@ int choose_block(phx_ctx* ctx, int nb, int N) {
 long per_k_bytes(const Design& d, int s, int prec) {
   const long n3 = d.n3, m = 3 * s;
   const long pc = prec == PHX_FP64 ? 16 : 8;
-  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + 2L * 3 * n3 * m * 16 + 2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
+  const long ws = prec == PHX_FP64 ? 128 : 256;
+  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc + 2L * 3 * n3 * m * 16 +
+         2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
 }
 
 // init (may be NULL): nk blocks of s start vectors (n3 x s, k-stride n3 s) replacing
@@ -651,6 +656,16 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
   KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st,
                         ctx->hk()));
+  sv.SBinv = nullptr;
+  if (ctx->opt.sbinv) {
+    constexpr int WS = sizeof(R) == 4 ? 256 : 128;
+    const long nsb = (n3 + WS - 1) / WS;
+    sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nk * nsb * WS * WS);
+    PROF_BEGIN(PROF_TRSM_DIAG);
+    KCHK(sb_inverse_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (const C_t<R>*)sv.Dinv,
+                               (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, st));
+    PROF_END(PROF_TRSM_DIAG, (double)nk * 8.0 * n3 * WS * WS / 6.0, (double)nk * sizeof(C_t<R>) * n3 * WS);
+  }
 
   // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
@@ -940,6 +955,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
   else if (k == "streams") { if (!(v >= 1 && v <= 8)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
+  else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -1503,8 +1519,14 @@ int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, cons
       HIPCHK(hipMemcpyAsync(db, hb.data(), nb * sizeof(Cx), hipMemcpyHostToDevice, st));
       HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
       KCHK(potrf_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, ctx->dflag, st));
+      Cx* sbi = nullptr;
+      if (ctx->opt.sbinv) {
+        const long ws = sizeof(R) == 4 ? 256 : 128;
+        sbi = dbuf<Cx>(ctx, "tS", (long)batch * ((n + ws - 1) / ws) * ws * ws);
+        KCHK(sb_inverse_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, sbi, st));
+      }
       KCHK(potrs_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, db, n, (long)n * nrhs, dz, n,
-                            (long)n * nrhs, nrhs, st));
+                            (long)n * nrhs, nrhs, st, nullptr, sbi));
       int flag = 0;
       HIPCHK(hipMemcpyAsync(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hb.data(), db, nb * sizeof(Cx), hipMemcpyDeviceToHost, st));

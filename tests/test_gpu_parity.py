@@ -64,15 +64,18 @@ def test_zgemm_tall_skinny(ctx, prec, tol, m, n, k, batch):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("sbinv", [0, 1])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 5e-4)])
-@pytest.mark.parametrize("n,nrhs,batch", [(64, 3, 1), (192, 21, 2), (320, 7, 3)])
-def test_zposv(ctx, prec, tol, n, nrhs, batch):
-    log("zposv", prec, n, nrhs, batch)
+@pytest.mark.parametrize("n,nrhs,batch", [(64, 3, 1), (192, 21, 2), (320, 7, 3), (576, 32, 2)])
+def test_zposv(ctx, prec, tol, n, nrhs, batch, sbinv):
+    log("zposv", prec, n, nrhs, batch, "sbinv", sbinv)
+    ctx.set_option("sbinv", sbinv)
     rng = np.random.default_rng(n + nrhs)
     G = _rand(rng, batch, n, n)
     A = G @ np.conj(np.transpose(G, (0, 2, 1))) / n + np.eye(n)[None] * 0.5
     B = _rand(rng, batch, n, nrhs)
     X = ctx.zposv(A, B, precision=prec)
+    ctx.set_option("sbinv", 1)
     ref = np.linalg.solve(A, B)
     err = np.abs(X - ref).max() / np.abs(ref).max()
     assert err < tol, err
