@@ -100,11 +100,13 @@ def main():
     iters = 0
     sweeps = 0
     coarse_iters = 0
+    iters_mean_k = 0
     for _ in range(args.steps):
         step()
         iters = max(iters, ctx.stat("iters"))
         sweeps = max(sweeps, ctx.stat("rr_sweeps"))
         coarse_iters = max(coarse_iters, ctx.stat("coarse_iters"))
+        iters_mean_k = ctx.stat("iters_mean_k")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_option("profile", 0)
@@ -160,7 +162,7 @@ def main():
                    "designs": args.designs, "k_points": args.nk, "nbands": nb, "sens_bands": list(bands),
                    "M": args.M, "precision": args.precision, "parallelism": f"single GPU, {args.streams} design streams",
                    "eigensolver_iters_max": iters, "jacobi_sweeps_max": sweeps,
-                   "coarse_start_iters_max": coarse_iters},
+                   "coarse_start_iters_max": coarse_iters, "iters_to_converge_mean_over_k": iters_mean_k},
         "roofline": roof,
         "stage_ms_per_step": breakdown,
         "accuracy_gate": gate,

@@ -91,6 +91,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * inverses of the factor's 256-wide (FP64: 128-wide) diagonal blocks, computed
  * once per factorisation, so every solve step is a matrix product; 0: blocked
  * substitution inside each diagonal block),
+ * "kskip" (1, default: a k-point whose wanted bands all meet the tolerance is
+ * frozen, its vectors, eigenvalues and residuals kept, and the remaining
+ * iterations of its chunk skip it; 0: every k-point of a chunk iterates until the
+ * slowest converges),
  * "rr_fused" (1, default: one Omega-orthonormalisation of the search basis,
  * the second folded into the Rayleigh-Ritz step in the small m x m space, except
  * in the last iterations of a solve whose residual is below 1e-13/tolerance; 0:

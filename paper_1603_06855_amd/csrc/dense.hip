@@ -67,6 +67,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
   }
   const int row0 = ti * BM, col0 = tj * BN;
   const int b = (int)bat;
+  if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
   const int sp = blockIdx.z;
   const C* A = g.A + (long)(b / g.dA) * g.sA;
   const C* B = g.B + (long)(b / g.dB) * g.sB;
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(GemmArgs<R> g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int b = blockIdx.y;
+  if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
   const C* A = g.A + (long)(b / g.dA) * g.sA;
   const C* W = g.B + (long)(b / g.dB) * g.sB;
   C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
@@ -285,6 +287,7 @@ __global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   const long MN = (long)g.M * g.N;
   const int b = blockIdx.y;
+  if (g.kact && !g.kact[b / g.kdiv]) return;
   C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
   const bool useBeta = (g.beta.x != 0 || g.beta.y != 0);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
@@ -303,6 +306,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.dA <= 0) g.dA = 1;
   if (g.dB <= 0) g.dB = 1;
   if (g.dC <= 0) g.dC = 1;
+  if (g.kdiv <= 0) g.kdiv = 1;
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.K <= 0) {  // C = beta C
     g.ksplit = 1;
@@ -671,7 +675,8 @@ template int sb_inverse_batched<float>(const float2*, int, long, long, int, cons
 // (or its conjugate transpose) and one GEMM for the rows beyond it.
 template <typename R>
 int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* SBinv, C_t<R>* B, long ldb,
-                long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook) {
+                long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook,
+                const int* kact) {
   constexpr int WS = sizeof(R) == 4 ? 256 : 128;
   const double cb = (double)sizeof(C_t<R>);
   const int nsb = (n + WS - 1) / WS;
@@ -681,7 +686,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     const int J0 = sbi * WS, w = std::min(WS, n - J0);
     {
       GemmArgs<R> g{};
-      g.M = w; g.N = nc; g.K = w; g.batch = batch;
+      g.M = w; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z + J0; g.ldc = ldz; g.sC = sZ;
@@ -694,7 +699,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     const int rem = n - J0 - w;
     if (rem > 0) {
       GemmArgs<R> g{};
-      g.M = rem; g.N = nc; g.K = w; g.batch = batch;
+      g.M = rem; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL;
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
@@ -709,7 +714,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     const int J0 = sbi * WS, w = std::min(WS, n - J0);
     {
       GemmArgs<R> g{};
-      g.M = w; g.N = nc; g.K = w; g.batch = batch;
+      g.M = w; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;  // op = C: the inverse of L_JJ^H
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0; g.ldc = ldb; g.sC = sB;
@@ -721,7 +726,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     }
     if (J0 > 0) {
       GemmArgs<R> g{};
-      g.M = J0; g.N = nc; g.K = w; g.batch = batch;
+      g.M = J0; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       g.A = L + J0; g.lda = lda; g.sA = sL;  // rows J0..J0+w, cols 0..J0-1; op = C
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
@@ -795,8 +800,8 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook, const C_t<R>* sbinv) {
-  if (nc <= 32 && sbinv) return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
+                  const ProfHook* hook, const C_t<R>* sbinv, const int* kact) {
+  if (nc <= 32 && sbinv) return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook, kact);
   if (nc <= 32) return potrs_narrow<R>(L, n, lda, sL, batch, Dinv, sD, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   const int T = n / 64;
   const double cb = (double)sizeof(C_t<R>);
@@ -858,8 +863,10 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
   return 0;
 }
 template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
-                                   long, double2*, long, long, int, hipStream_t, const ProfHook*, const double2*);
+                                   long, double2*, long, long, int, hipStream_t, const ProfHook*, const double2*,
+                                   const int*);
 template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
-                                  long, float2*, long, long, int, hipStream_t, const ProfHook*, const float2*);
+                                  long, float2*, long, long, int, hipStream_t, const ProfHook*, const float2*,
+                                  const int*);
 
 }  // namespace phx

@@ -21,6 +21,8 @@ struct GemmArgs {
   C_t<R> alpha, beta;
   int tri;
   int op;  // 1: A is a k-shared operator (stride 0); selects a separately named kernel
+  const int* kact;  // optional device mask: batch item b is skipped when kact[b / kdiv] == 0
+  int kdiv;
   int ksplit;
   C_t<R>* Cpart;
 };
@@ -52,11 +54,12 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
                   hipStream_t st, const ProfHook* hook = nullptr);
 
 // sbinv (may be NULL): inverses of the diagonal super-blocks from sb_inverse_batched;
-// given, narrow solves (nc <= 32) run as GEMMs only.
+// given, narrow solves (nc <= 32) run as GEMMs only, skipping the matrices whose kact
+// entry is 0 (kact may be NULL).
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr);
+                  const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr, const int* kact = nullptr);
 
 // Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
 // Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS).

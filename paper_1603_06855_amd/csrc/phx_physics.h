@@ -27,10 +27,13 @@ void launch_kvec(const double* Q, const Recip& T, int M, int N, int Np, int nk, 
 template <typename R>
 void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                      int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st);
+// kact (optional, device): per-k mask; k-points with kact[k] == 0 are skipped.
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st);
+                   double2* tr, hipStream_t st, const int* kact = nullptr);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st);
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr);
+void launch_copy_inactive(const double2* src, double2* dst, long n, long stride, int nk, const int* kact,
+                          hipStream_t st);
 void launch_zero(double2* X, long n, hipStream_t st);
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
 void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,
@@ -38,9 +41,10 @@ void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, doub
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
-                     hipStream_t st);
+                     hipStream_t st, const int* kact = nullptr);
 template <typename R>
-void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st);
+void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st,
+                  const int* kact = nullptr);
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
                        int Np, int nk, double2* Fc, hipStream_t st);
 void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int nsel, long n, int nk, double2* Y,
@@ -51,10 +55,11 @@ void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rh
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st);
 
 // small.hip: per-k dense kernels on m x m (m <= 64) Gram matrices, FP64.
-void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st);
+void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st,
+                      const int* kact = nullptr);
 void launch_rr_gen(const double2* G2, int m, int s, int nk, double drop, double2* C0, int* keep, double2* Cx,
-                   double2* Cp, double* theta, int* sweeps, hipStream_t st);
+                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact = nullptr);
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta,
-                   int* sweeps, hipStream_t st);
+                   int* sweeps, hipStream_t st, const int* kact = nullptr);
 
 }  // namespace phx

@@ -211,11 +211,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double2* Dm, const 
 // X: 3Np x ncol per k (ld ldx, k-stride sX).  Y: Np x 6 ncol per k, t: Np x ncol.
 // ---------------------------------------------------------------------------
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
-                              double2* Y, double2* tr) {
+                              double2* Y, double2* tr, const int* kact) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np) return;
+  if (p >= Np || (kact && !kact[k])) return;
   const double* K = Kv + ((long)k * Np + p) * 3;
   const double2* x = X + (long)k * sX + (long)j * ldx + p;
   const double2 x1 = x[0], x2 = x[Np], x3 = x[2 * Np];
@@ -233,11 +233,11 @@ __global__ void strain_kernel(const double2* X, long ldx, long sX, const double*
 // Mandel stress coefficients S = Zy + (Zt / 3) [1,1,1,0,0,0] and the force
 // (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
-                             double2* KX, long ldk, long sK) {
+                             double2* KX, long ldk, long sK, const int* kact) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np) return;
+  if (p >= Np || (kact && !kact[k])) return;
   const double* K = Kv + ((long)k * Np + p) * 3;
   const double2* z = Zy + (long)k * Np * 6 * ncol + (long)(6 * j) * Np + p;
   const double2 t3 = cscale(Zt[(long)k * Np * ncol + (long)j * Np + p], 1.0 / 3.0);
@@ -273,8 +273,9 @@ template <typename R>
 __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, long mcols, long sBig,
                                                        const double* theta, int s, const double* sigma,
                                                        double act_tol, C_t<R>* Rp, long sR, double* rn,
-                                                       double* rnorm) {
+                                                       double* rnorm, const int* kact) {
   const int j = blockIdx.x, k = blockIdx.y;
+  if (kact && !kact[k]) return;  // converged k-point: its residuals stay as they were
   double2* S = Big + (long)k * sBig;
   const double2* kx = S + (mcols + j) * n3;      // KS block, column j (X part)
   const double2* ox = S + (2 * mcols + j) * n3;  // OS block, column j
@@ -319,8 +320,9 @@ __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, lo
 }
 
 template <typename R>
-__global__ void widen_kernel(const C_t<R>* Rp, long sR, long n, double2* W, long sW) {
+__global__ void widen_kernel(const C_t<R>* Rp, long sR, long n, double2* W, long sW, const int* kact) {
   const int k = blockIdx.y;
+  if (kact && !kact[k]) return;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     const C_t<R> v = Rp[(long)k * sR + e];
     W[(long)k * sW + e] = make_double2((double)v.x, (double)v.y);
@@ -473,15 +475,30 @@ template void launch_assemble<float>(const double2*, const double2*, const doubl
                                      double, const double*, float2*, long, int, hipStream_t);
 
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st) {
+                   double2* tr, hipStream_t st, const int* kact) {
   hipLaunchKernelGGL(strain_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
-                     tr);
+                     tr, kact);
 }
 
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st) {
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact) {
   hipLaunchKernelGGL(force_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
-                     ldk, sK);
+                     ldk, sK, kact);
+}
+
+// For the k-points with kact[k] == 0: n values at src + k stride -> dst + k stride (the
+// basis of a converged k-point follows the double-buffer swap unchanged).
+__global__ void copy_inactive_kernel(const double2* src, double2* dst, long n, long stride, const int* kact) {
+  const int k = blockIdx.y;
+  if (kact[k]) return;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    dst[(long)k * stride + e] = src[(long)k * stride + e];
+}
+
+void launch_copy_inactive(const double2* src, double2* dst, long n, long stride, int nk, const int* kact,
+                          hipStream_t st) {
+  unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 1024);
+  hipLaunchKernelGGL(copy_inactive_kernel, dim3(nb, nk), dim3(256), 0, st, src, dst, n, stride, kact);
 }
 
 void launch_zero(double2* X, long n, hipStream_t st) {
@@ -496,22 +513,22 @@ void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, i
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
-                     hipStream_t st) {
+                     hipStream_t st, const int* kact) {
   hipLaunchKernelGGL((residual_kernel<R>), dim3(s, nk), dim3(256), 0, st, Big, n3, mcols, sBig, theta, s, sigma,
-                     act_tol, Rp, sR, rn, rnorm);
+                     act_tol, Rp, sR, rn, rnorm, kact);
 }
 template void launch_residual<double>(double2*, long, long, long, const double*, int, int, const double*, double,
-                                      double2*, long, double*, double*, hipStream_t);
+                                      double2*, long, double*, double*, hipStream_t, const int*);
 template void launch_residual<float>(double2*, long, long, long, const double*, int, int, const double*, double,
-                                     float2*, long, double*, double*, hipStream_t);
+                                     float2*, long, double*, double*, hipStream_t, const int*);
 
 template <typename R>
-void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st) {
+void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st, const int* kact) {
   unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 4096);
-  hipLaunchKernelGGL((widen_kernel<R>), dim3(nb, nk), dim3(256), 0, st, Rp, sR, n, W, sW);
+  hipLaunchKernelGGL((widen_kernel<R>), dim3(nb, nk), dim3(256), 0, st, Rp, sR, n, W, sW, kact);
 }
-template void launch_widen<double>(const double2*, long, long, double2*, long, int, hipStream_t);
-template void launch_widen<float>(const float2*, long, long, double2*, long, int, hipStream_t);
+template void launch_widen<double>(const double2*, long, long, double2*, long, int, hipStream_t, const int*);
+template void launch_widen<float>(const float2*, long, long, double2*, long, int, hipStream_t, const int*);
 
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
                        int Np, int nk, double2* Fc, hipStream_t st) {

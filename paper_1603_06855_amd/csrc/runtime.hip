@@ -51,12 +51,14 @@ struct Opts {
   int streams = 4;           // designs solved concurrently by the batched call
   int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
   int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
+  int kskip = 1;             // 1: k-points whose wanted bands have converged skip later iterations
 };
 
 struct Stats {
   int iters = 0, chunks = 0, block = 0, kchunk = 0;
   int rr_sweeps = 0;  // most Jacobi sweeps any k needed in a Rayleigh-Ritz step of the last solve
   int coarse_iters = 0;  // eigensolver iterations of the coarse start (slowest chunk)
+  long k_conv_iters = 0, k_count = 0;  // sum over k of the iteration at which k converged
 };
 
 // Kernel-class timing with HIP events recorded on the context stream.
@@ -426,6 +428,7 @@ struct Solver {
   void* A;     // nk x n3 x n3 (prec)
   void* Dinv;  // nk x n3/64 x 4096 (prec)
   void* SBinv; // nk x nsb x WS^2 inverses of the factor's diagonal super-blocks, or NULL
+  int* kact;   // per k: 1 while a wanted band of that k-point has not met the tolerance
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -434,9 +437,11 @@ struct Solver {
 template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
-          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0) {
+          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1) {
   GemmArgs<R> g{};
   g.op = op;
+  g.kact = kact;
+  g.kdiv = kdiv;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.lda = lda; g.sA = sA; g.dA = dA;
   g.B = B; g.ldb = ldb; g.sB = sB; g.dB = dB;
@@ -460,28 +465,33 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   double2* X = Big + c0 * n3;
   const double Np = d.Np, nk = sv.nk;
   PROF_BEGIN(PROF_APPLY);
-  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st);
+  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, sv.kact);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
-  const int ny = 6 * ncol * sv.nk, nt = ncol * sv.nk;
   // algorithmic flops of an operator product: 8 Np^2 per column; the operator is read
-  // once and the block read and written once
+  // once and the block read and written once.  The deviatoric product runs one batch
+  // item per k-point (shared operator, stride 0) so that converged k-points are
+  // skipped; the volumetric one (a sixth of the columns, too narrow per k for a full
+  // tile) runs over all k-points as one product (columns of converged k-points are
+  // computed from their last strains and not used).
+  const int ny = 6 * ncol, nt = ncol * sv.nk;
+  const long sy = (long)d.Np * ny;
   PROF_BEGIN(PROF_OP_GEMM);
-  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, 1, d.Bm, d.Np, 0, 1, sv.Y, d.Np, 0, 1, sv.Zy, d.Np, 0, ONE, ZERO, 1,
-               nullptr, 1);
-  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * ny, 16.0 * (Np * Np + 2.0 * Np * ny));
+  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
+               nullptr, 1, sv.kact, 1);
+  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * ny * nk, 16.0 * (Np * Np + 2.0 * Np * ny * nk));
   PROF_BEGIN(PROF_OP_GEMM);
   gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
                nullptr, 1);
   PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
   PROF_BEGIN(PROF_APPLY);
-  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st);
+  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, sv.kact);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
   PROF_BEGIN(PROF_OP_GEMM);
   gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
-               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1);
+               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1, sv.kact, 1);
   PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
 }
 
@@ -491,7 +501,7 @@ void gram(Solver& sv, double2* Big, int block) {
   const long n3 = sv.n3, m = sv.m;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
-               m * m, ONE, ZERO, sv.ksplit, sv.Gpart);
+               m * m, ONE, ZERO, sv.ksplit, sv.Gpart, 0, sv.kact, 1);
   PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nk, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nk);
 }
 
@@ -500,13 +510,14 @@ void cholqr(Solver& sv) {
   const long n3 = sv.n3, m = sv.m;
   gram(sv, sv.Big, 2);
   PROF_BEGIN(PROF_SMALL);
-  launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream);
+  launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream, sv.kact);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
   PROF_BEGIN(PROF_UPDATE);
   gemm<double>(ctx, 0, 0, n3, m, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.C0, m, m * m, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO);
+               ZERO, 1, nullptr, 0, sv.kact, 3);
+  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nk, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nk);
   std::swap(sv.Big, sv.Big2);
 }
@@ -516,15 +527,16 @@ void rayleigh_ritz(Solver& sv) {
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   gram(sv, sv.Big, 1);
   PROF_BEGIN(PROF_SMALL);
-  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream);
+  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream, sv.kact);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // X <- [S] Cr ; P <- [W P] Cr[s:m]
   PROF_BEGIN(PROF_UPDATE);
   gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO);
+               ZERO, 1, nullptr, 0, sv.kact, 3);
   gemm<double>(ctx, 0, 0, n3, s, m - s, 3 * sv.nk, sv.Big + s * n3, n3, n3 * m, 1, sv.Cr + s, m, m * s, 3,
-               sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO);
+               sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3);
+  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nk,
            16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
   std::swap(sv.Big, sv.Big2);
@@ -539,17 +551,19 @@ void rayleigh_ritz_fused(Solver& sv) {
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
-               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part);
+               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, sv.kact, 1);
   PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nk, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nk);
   PROF_BEGIN(PROF_SMALL);
-  launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cr, sv.Cp, sv.theta, sv.sweeps, ctx->stream);
+  launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cr, sv.Cp, sv.theta, sv.sweeps, ctx->stream,
+                sv.kact);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
   gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO);
+               ZERO, 1, nullptr, 0, sv.kact, 3);
   gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, m * s, 3, sv.Big2 + 2 * s * n3, n3,
-               n3 * m, ONE, ZERO);
+               n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3);
+  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nk, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
   std::swap(sv.Big, sv.Big2);
 }
@@ -560,8 +574,9 @@ void precondition(Solver& sv) {
   const long n3 = sv.n3;
   KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
                         (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk(),
-                        (const C_t<R>*)sv.SBinv));
-  launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream);
+                        (const C_t<R>*)sv.SBinv, sv.kact));
+  launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
+                  sv.kact);
   KCHK(hipGetLastError());
 }
 
@@ -609,6 +624,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.G2part = dbuf<double2>(ctx, "G2part", (long)sv.ksplit * nk * 2 * m * m);
   sv.keep = dbuf<int>(ctx, "keep", (long)nk * m);
   sv.sweeps = dbuf<int>(ctx, "sweeps", nk);
+  sv.kact = dbuf<int>(ctx, "kact", nk);
   sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
   sv.rn = dbuf<double>(ctx, "rn", (long)nk * s);
   sv.rnorm = dbuf<double>(ctx, "rnorm", (long)nk * s);
@@ -667,6 +683,12 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     PROF_END(PROF_TRSM_DIAG, (double)nk * 8.0 * n3 * WS * WS / 6.0, (double)nk * sizeof(C_t<R>) * n3 * WS);
   }
 
+  // Per-k activity: every k-point starts active; one whose wanted bands all meet the
+  // tolerance is frozen (its basis, Ritz values and residual norms stay as they were)
+  // and the remaining iterations skip it.
+  std::vector<int> act_h(nk, 1);
+  HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+
   // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
   if (init) {
@@ -681,6 +703,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   const double tol = tol_override > 0 ? tol_override : ctx->opt.tol[prec];
   std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
   std::vector<int> sw_h(nk);
+  std::vector<char> kdone(nk, 0);
   out.converged = false;
   int it = 0;
   bool near = false;
@@ -708,7 +731,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     }
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
-                       sv.rn, sv.rnorm, st);
+                       sv.rn, sv.rnorm, st, sv.kact);
     PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * nk + (double)sizeof(C_t<R>) * 3.0 * d.N * s * nk);
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -722,8 +745,21 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
     }
     double worst = 0;
-    for (int k = 0; k < nk; ++k)
-      for (int j = 0; j < nb; ++j) worst = std::max(worst, rn_h[(size_t)k * s + j]);
+    for (int k = 0; k < nk; ++k) {
+      double wk = 0;
+      for (int j = 0; j < nb; ++j) wk = std::max(wk, rn_h[(size_t)k * s + j]);
+      if (wk <= tol && !kdone[k]) {
+        kdone[k] = 1;
+        if (ctx->opt.kskip) act_h[k] = 0;
+        if (!tol_override) {
+          ctx->stats.k_conv_iters += it;
+          ctx->stats.k_count += 1;
+        }
+      }
+      worst = std::max(worst, wk);
+    }
+    if (ctx->opt.kskip && worst > tol)
+      HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
     if (ctx->trace) {
       std::vector<int> kh((size_t)nk * m);
       std::vector<double> th((size_t)nk * s);
@@ -813,6 +849,8 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
   ctx->stats.iters = 0;
   ctx->stats.rr_sweeps = 0;
   ctx->stats.coarse_iters = 0;
+  ctx->stats.k_conv_iters = 0;
+  ctx->stats.k_count = 0;
   bool conv = true;
   for (int k0 = 0; k0 < nk; k0 += kc) {
     const int nkc = std::min(kc, nk - k0);
@@ -956,6 +994,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "streams") { if (!(v >= 1 && v <= 8)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
+  else if (k == "kskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.kskip = (int)v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -971,6 +1010,7 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "kchunk") *value = ctx->stats.kchunk;
   else if (k == "rr_sweeps") *value = ctx->stats.rr_sweeps;
   else if (k == "coarse_iters") *value = ctx->stats.coarse_iters;
+  else if (k == "iters_mean_k") *value = ctx->stats.k_count ? (double)ctx->stats.k_conv_iters / ctx->stats.k_count : 0;
   else if (k.rfind("prof.", 0) == 0) {
     const size_t dot = k.rfind('.');
     const std::string cls = k.substr(5, dot - 5), f = k.substr(dot + 1);
@@ -1373,6 +1413,8 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
       ctx->stats.iters = std::max(ctx->stats.iters, w->stats.iters);
       ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, w->stats.rr_sweeps);
       ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, w->stats.coarse_iters);
+      ctx->stats.k_conv_iters += w->stats.k_conv_iters;
+      ctx->stats.k_count += w->stats.k_count;
       ctx->stats.chunks += w->stats.chunks;
       ctx->stats.block = std::max(ctx->stats.block, w->stats.block);
       ctx->stats.kchunk = std::max(ctx->stats.kchunk, w->stats.kchunk);

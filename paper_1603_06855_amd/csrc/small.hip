@@ -22,7 +22,8 @@ namespace phx {
 constexpr int SMALL_NT = 1024;  // threads per workgroup of the small kernels (latency bound)
 
 __global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, int m, double drop, double2* C0,
-                                                        int* keep) {
+                                                        int* keep, const int* kact) {
+  if (kact && !kact[blockIdx.x]) return;  // a converged k-point
   __shared__ double2 Ls[64][65];  // [col][row]
   __shared__ double2 Xs[64][65];
   __shared__ double D[64];
@@ -259,7 +260,8 @@ __device__ void select_lowest(JacobiLDS& L, int m, int s) {
 }
 
 __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, const int* keep, int m, int s, double2* C,
-                                                     double* theta, int* sweeps_out) {
+                                                     double* theta, int* sweeps_out, const int* kact) {
+  if (kact && !kact[blockIdx.x]) return;  // a converged k-point: its Ritz values stay
   __shared__ JacobiLDS L;
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
@@ -312,7 +314,8 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
 // C0 (m x m per k) is scratch written and read back here.
 __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int m, int s, double drop, double2* C0g,
                                                      int* keep, double2* Cx, double2* Cp, double* theta,
-                                                     int* sweeps_out) {
+                                                     int* sweeps_out, const int* kact) {
+  if (kact && !kact[blockIdx.x]) return;  // a converged k-point: its Ritz values stay
   __shared__ JacobiLDS L;
   __shared__ double D[64];
   __shared__ int kp[64];
@@ -492,19 +495,20 @@ __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int
   if (tid < s) theta[k * s + tid] = L.As[L.order[tid]][L.order[tid]].x;
 }
 
-void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st) {
-  hipLaunchKernelGGL(chol_drop_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, m, drop, C0, keep);
+void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st,
+                      const int* kact) {
+  hipLaunchKernelGGL(chol_drop_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, m, drop, C0, keep, kact);
 }
 
 void launch_rr_gen(const double2* G2, int m, int s, int nk, double drop, double2* C0, int* keep, double2* Cx,
-                   double2* Cp, double* theta, int* sweeps, hipStream_t st) {
+                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact) {
   hipLaunchKernelGGL(rr_gen_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G2, m, s, drop, C0, keep, Cx, Cp, theta,
-                     sweeps);
+                     sweeps, kact);
 }
 
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta, int* sweeps,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(rr_eig_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, keep, m, s, C, theta, sweeps);
+                   hipStream_t st, const int* kact) {
+  hipLaunchKernelGGL(rr_eig_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G, keep, m, s, C, theta, sweeps, kact);
 }
 
 }  // namespace phx
