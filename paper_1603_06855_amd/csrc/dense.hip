@@ -25,7 +25,7 @@ namespace phx {
 // operator times a block (same code as 0; a separate instantiation so that profilers
 // report the matrix-free operator products on their own).
 template <typename R, int OPA, int OPB, int BM, int BN, int MODE>
-__global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
+__global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
   constexpr int WM = BM / 32;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<R> g) {
 // registers (16 consecutive rows per load), so a workgroup is one pass over 128 rows
 // without a k-loop pipeline.  Wave w computes rows 32 w .. 32 w + 31 in two stripes.
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void skinny_kernel(GemmArgs<R> g) {
+__global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
   __shared__ R Wr[64][65], Wi[64][65];
