@@ -282,6 +282,135 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
   }
 }
 
+// Products with few right-hand sides, C = alpha op(A) B + beta C with N <= 16 NB and
+// op(B) = B: the steps of the triangular solves, bound by the one pass over A.  A goes
+// from global memory straight into MFMA operand registers, 16 k at a time, with the
+// next 16 in flight while the current ones are multiplied; B is staged in LDS 64 rows
+// at a time.  Wave w computes rows 16 X w .. 16 X (w + 1) - 1 of the workgroup's 64 X.
+// OPA = 1 (A^H, stored A contiguous in k): a lane reads four consecutive k of one
+// column of the stored A, so inside a 16-deep group the k order is permuted, the same
+// permutation for both operands.
+template <typename R, int OPA, int NB, int X>
+__global__ __launch_bounds__(256, 3) void nrhs_kernel(GemmArgs<R> g) {
+  typedef C_t<R> C;
+  typedef typename acc_t<R>::type ACC;
+  constexpr bool K3 = sizeof(R) == 4;  // FP32: three real products per complex product
+  constexpr int KC = 64;
+  constexpr int NC = 16 * NB;
+  // row pitch: lanes 16..31 read the next k row (OPA = 0) or the row four further
+  // (OPA = 1); the pitch puts them on the other 16 of 32 banks
+  constexpr int LDB = OPA == 0 ? 48 : (NC == 16 ? 20 : 36);
+  __shared__ R Br[KC][LDB], Bi[KC][LDB], Bs[K3 ? KC : 1][LDB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int b = blockIdx.y;
+  if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
+  const C* A = g.A + (long)(b / g.dA) * g.sA;
+  const C* Bm = g.B + (long)(b / g.dB) * g.sB;
+  C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
+  const int i0 = blockIdx.x * 64 * X + wave * 16 * X;
+
+  ACC t1[X][NB], t2[X][NB], t3[X][NB];
+#pragma unroll
+  for (int x = 0; x < X; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      t1[x][y] = (ACC){0, 0, 0, 0};
+      t2[x][y] = (ACC){0, 0, 0, 0};
+      t3[x][y] = (ACC){0, 0, 0, 0};
+    }
+  // k of slot q of this lane inside a 16-deep group
+  auto kof = [&](int q) { return OPA == 0 ? 4 * q + lg : 4 * lg + q; };
+  auto loadA = [&](int k0, C (&v)[X][4]) {
+#pragma unroll
+    for (int x = 0; x < X; ++x) {
+      const int i = i0 + 16 * x + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + kof(q);
+        C a = mk<R>(0, 0);
+        if (i < g.M && k < g.K) a = OPA == 0 ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+        v[x][q] = a;
+      }
+    }
+  };
+  auto stageB = [&](int k0) {
+    for (int e = tid; e < KC * NC; e += 256) {
+      const int k = e % KC, j = e / KC;
+      C v = mk<R>(0, 0);
+      if (k0 + k < g.K && j < g.N) v = Bm[k0 + k + (long)j * g.ldb];
+      Br[k][j] = v.x;
+      Bi[k][j] = v.y;
+      if (K3) Bs[k][j] = v.x + v.y;
+    }
+  };
+  auto mult = [&](const C (&v)[X][4], int kl) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kl + kof(q);
+      R ar[X], ai[X], as[X];
+#pragma unroll
+      for (int x = 0; x < X; ++x) {
+        ar[x] = v[x][q].x;
+        ai[x] = OPA == 0 ? v[x][q].y : -v[x][q].y;
+        if (K3) as[x] = ar[x] + ai[x];
+      }
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        const R br = Br[k][16 * y + li], bi = Bi[k][16 * y + li];
+#pragma unroll
+        for (int x = 0; x < X; ++x) {
+          if (K3) {
+            const R bs = Bs[k][16 * y + li];
+            t1[x][y] = mfma16(br, ar[x], t1[x][y]);
+            t2[x][y] = mfma16(bi, ai[x], t2[x][y]);
+            t3[x][y] = mfma16(bs, as[x], t3[x][y]);
+          } else {
+            t1[x][y] = mfma16(br, ar[x], t1[x][y]);
+            t3[x][y] = mfma16(bi, ar[x], t3[x][y]);
+            t1[x][y] = mfma16(-bi, ai[x], t1[x][y]);
+            t3[x][y] = mfma16(br, ai[x], t3[x][y]);
+          }
+        }
+      }
+    }
+  };
+
+  const int ng = (g.K + 15) / 16;
+  C va[X][4], vb[X][4];
+  loadA(0, va);
+  for (int gi = 0; gi < ng; gi += 2) {
+    if ((gi * 16) % KC == 0) {
+      __syncthreads();
+      stageB(gi * 16);
+      __syncthreads();
+    }
+    if (gi + 1 < ng) loadA((gi + 1) * 16, vb);
+    mult(va, (gi * 16) % KC);
+    if (gi + 1 >= ng) break;
+    if (gi + 2 < ng) loadA((gi + 2) * 16, va);
+    mult(vb, ((gi + 1) * 16) % KC);
+  }
+
+  const bool useBeta = g.beta.x != 0 || g.beta.y != 0;
+#pragma unroll
+  for (int x = 0; x < X; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 16 * x + li;
+        const int col = 16 * y + (sizeof(R) == 8 ? (lg + 4 * r) : (4 * lg + r));
+        if (row < g.M && col < g.N) {
+          const C acc = K3 ? mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r])
+                           : mk<R>(t1[x][y][r], t3[x][y][r]);
+          C v = cmul(g.alpha, acc);
+          if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * g.ldc]));
+          Cb[row + (long)col * g.ldc] = v;
+        }
+      }
+}
+
 template <typename R>
 __global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
@@ -317,6 +446,20 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     dim3 grid2((unsigned)((g.M + 127) / 128), (unsigned)g.batch);
     if (g.N <= 32) hipLaunchKernelGGL((skinny_kernel<R, 2>), grid2, dim3(256), 0, st, g);
     else hipLaunchKernelGGL((skinny_kernel<R, 4>), grid2, dim3(256), 0, st, g);
+    return (int)hipGetLastError();
+  }
+  // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
+  // FP32 A^H the LDS-staged 128 x 32 tiles below read A faster).
+  if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 && (opa == 0 || sizeof(R) == 8)) {
+    constexpr int X = 1;
+    dim3 grid2((unsigned)((g.M + 64 * X - 1) / (64 * X)), (unsigned)g.batch);
+    if (opa == 0) {
+      if (g.N <= 16) hipLaunchKernelGGL((nrhs_kernel<R, 0, 1, X>), grid2, dim3(256), 0, st, g);
+      else hipLaunchKernelGGL((nrhs_kernel<R, 0, 2, X>), grid2, dim3(256), 0, st, g);
+    } else {
+      if (g.N <= 16) hipLaunchKernelGGL((nrhs_kernel<R, 1, 1, X>), grid2, dim3(256), 0, st, g);
+      else hipLaunchKernelGGL((nrhs_kernel<R, 1, 2, X>), grid2, dim3(256), 0, st, g);
+    }
     return (int)hipGetLastError();
   }
   // Narrow outputs (N <= 32: triangular solves and updates with the s search

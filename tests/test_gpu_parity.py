@@ -33,7 +33,8 @@ def _rand(rng, *shape):
 @pytest.mark.parametrize("opa", ["N", "C"])
 @pytest.mark.parametrize("opb", ["N", "C"])
 @pytest.mark.parametrize("m,n,k,batch", [(1, 1, 1, 1), (70, 45, 33, 3), (130, 64, 200, 2), (64, 128, 16, 1),
-                                           (200, 21, 64, 2), (129, 32, 17, 1), (300, 7, 130, 3)])
+                                           (200, 21, 64, 2), (129, 32, 17, 1), (300, 7, 130, 3),
+                                           (700, 16, 300, 2), (257, 31, 256, 1)])
 def test_zgemm(ctx, prec, tol, opa, opb, m, n, k, batch):
     log("zgemm", prec, opa, opb, m, n, k, batch)
     rng = np.random.default_rng(m * 7 + n + k)
