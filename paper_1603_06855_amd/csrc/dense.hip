@@ -30,12 +30,15 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef typename acc_t<R>::type ACC;
   constexpr int WM = BM / 32;
   static_assert(WM * (BN / 32) == 4, "four waves per tile");
-  // per-thread staging: A holds BM*16 elements, B holds 16*BN, in groups of VA / VB
+  // KS: depth of one LDS stage.  DB: two LDS stages, one barrier per stage (FP32 and
+  // the FP64 Hermitian update; the other FP64 tiles would drop to two waves per SIMD).
+  constexpr int KS = 16, DB = (sizeof(R) == 4 || MODE == 1) ? 1 : 0;
+  // per-thread staging: A holds BM*KS elements, B holds KS*BN, in groups of VA / VB
   // consecutive elements along the operand's contiguous dimension
-  constexpr int NA = BM * 16 / 256, NB = BN * 16 / 256;
+  constexpr int NA = BM * KS / 256, NB = BN * KS / 256;
   constexpr int VA = NA < 4 ? NA : 4, VB = NB < 4 ? NB : 4;
   constexpr int GA = NA / VA, GB = NB / VB;
-  __shared__ R Asr[16][BM + 4], Asi[16][BM + 4], Bsr[16][BN + 4], Bsi[16][BN + 4];
+  __shared__ R Asr[DB + 1][KS][BM + 4], Asi[DB + 1][KS][BM + 4], Bsr[DB + 1][KS][BN + 4], Bsi[DB + 1][KS][BN + 4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   const C* B = g.B + (long)(b / g.dB) * g.sB;
 
   int kchunk = g.K;
-  if (g.ksplit > 1) kchunk = (((g.K + g.ksplit - 1) / g.ksplit) + 15) & ~15;
+  if (g.ksplit > 1) kchunk = (((g.K + g.ksplit - 1) / g.ksplit) + KS - 1) / KS * KS;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
       for (int q = 0; q < VA; ++q) {
         int i, k;
         if (OPA == 0) { i = row0 + (gi % (BM / VA)) * VA + q; k = k0 + gi / (BM / VA); }
-        else { k = k0 + (gi % (16 / VA)) * VA + q; i = row0 + gi / (16 / VA); }
+        else { k = k0 + (gi % (KS / VA)) * VA + q; i = row0 + gi / (KS / VA); }
         C v = mk<R>(0, 0);
         if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
         ra[r * VA + q] = v;
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
       for (int q = 0; q < VB; ++q) {
         int j, k;
-        if (OPB == 0) { k = k0 + (gi % (16 / VB)) * VB + q; j = col0 + gi / (16 / VB); }
+        if (OPB == 0) { k = k0 + (gi % (KS / VB)) * VB + q; j = col0 + gi / (KS / VB); }
         else { j = col0 + (gi % (BN / VB)) * VB + q; k = k0 + gi / (BN / VB); }
         C w = mk<R>(0, 0);
         if (j < g.N && k < kend) w = (OPB == 0) ? B[k + (long)j * g.ldb] : B[j + (long)k * g.ldb];
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int sb) {
 #pragma unroll
     for (int r = 0; r < GA; ++r) {
       const int gi = tid + 256 * r;
@@ -131,9 +134,9 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
       for (int q = 0; q < VA; ++q) {
         int ii, kk;
         if (OPA == 0) { ii = (gi % (BM / VA)) * VA + q; kk = gi / (BM / VA); }
-        else { kk = (gi % (16 / VA)) * VA + q; ii = gi / (16 / VA); }
-        Asr[kk][ii] = ra[r * VA + q].x;
-        Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
+        else { kk = (gi % (KS / VA)) * VA + q; ii = gi / (KS / VA); }
+        Asr[sb][kk][ii] = ra[r * VA + q].x;
+        Asi[sb][kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
       }
     }
 #pragma unroll
@@ -142,30 +145,25 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
       for (int q = 0; q < VB; ++q) {
         int jj, kk;
-        if (OPB == 0) { kk = (gi % (16 / VB)) * VB + q; jj = gi / (16 / VB); }
+        if (OPB == 0) { kk = (gi % (KS / VB)) * VB + q; jj = gi / (KS / VB); }
         else { jj = (gi % (BN / VB)) * VB + q; kk = gi / (BN / VB); }
-        Bsr[kk][jj] = rb[r * VB + q].x;
-        Bsi[kk][jj] = OPB == 0 ? rb[r * VB + q].y : -rb[r * VB + q].y;
+        Bsr[sb][kk][jj] = rb[r * VB + q].x;
+        Bsi[sb][kk][jj] = OPB == 0 ? rb[r * VB + q].y : -rb[r * VB + q].y;
       }
     }
   };
 
-  if (kbeg < kend) load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + 16 < kend) load(k0 + 16);
+  auto compute = [&](int sb) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < KS / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
       R ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
-        ai[x] = Asi[kr][wr * 32 + x * 16 + (lane & 15)];
-        br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
-        bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
+        ar[x] = Asr[sb][kr][wr * 32 + x * 16 + (lane & 15)];
+        ai[x] = Asi[sb][kr][wr * 32 + x * 16 + (lane & 15)];
+        br[x] = Bsr[sb][kr][wc * 32 + x * 16 + (lane & 15)];
+        bi[x] = Bsi[sb][kr][wc * 32 + x * 16 + (lane & 15)];
         if (K3) {
           as[x] = ar[x] + ai[x];
           bs[x] = br[x] + bi[x];
@@ -186,6 +184,34 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
             t3[x][y] = mfma16(br[y], ai[x], t3[x][y]);
           }
         }
+    }
+  };
+
+  if (DB) {
+    // two LDS stages: the stage computed from is never the one being filled, so one
+    // barrier per stage separates the fill of stage i + 1 from its use
+    int sb = 0;
+    if (kbeg < kend) {
+      load(kbeg);
+      store(0);
+    }
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+      const bool more = k0 + KS < kend;
+      if (more) load(k0 + KS);
+      compute(sb);
+      if (more) store(sb ^ 1);
+      __syncthreads();
+      sb ^= 1;
+    }
+  } else {
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+      __syncthreads();
+      store(0);
+      __syncthreads();
+      if (k0 + KS < kend) load(k0 + KS);
+      compute(0);
     }
   }
 
