@@ -7,7 +7,8 @@
 //                 explicit inverse of the factor (used to turn panel and block
 //                 triangular solves into GEMMs).
 //
-// Complex products are built from four real MFMA products.  The MFMA is fed the
+// Complex products in the tiled GEMM take three real MFMA products (Karatsuba), those
+// of the streaming kernels four (FP64) or three (FP32).  The MFMA is fed the
 // B tile as its first operand and the A tile as its second, so the 16x16 result
 // it returns is C transposed: each lane then holds four *columns* of one row,
 // and lanes 0..15 cover 16 consecutive rows, which makes the stores to
@@ -30,15 +31,15 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef typename acc_t<R>::type ACC;
   constexpr int WM = BM / 32;
   static_assert(WM * (BN / 32) == 4, "four waves per tile");
-  // KS: depth of one LDS stage.  DB: two LDS stages, one barrier per stage (FP32 and
-  // the FP64 Hermitian update; the other FP64 tiles would drop to two waves per SIMD).
-  constexpr int KS = 16, DB = (sizeof(R) == 4 || MODE == 1) ? 1 : 0;
+  // KS: depth of one LDS stage (16 for FP32, 8 for FP64: the same bytes).  Two LDS
+  // stages, one barrier per stage: the stage being filled is never the one read.
+  constexpr int KS = sizeof(R) == 4 ? 16 : 8;
   // per-thread staging: A holds BM*KS elements, B holds KS*BN, in groups of VA / VB
   // consecutive elements along the operand's contiguous dimension
   constexpr int NA = BM * KS / 256, NB = BN * KS / 256;
   constexpr int VA = NA < 4 ? NA : 4, VB = NB < 4 ? NB : 4;
   constexpr int GA = NA / VA, GB = NB / VB;
-  __shared__ R Asr[DB + 1][KS][BM + 4], Asi[DB + 1][KS][BM + 4], Bsr[DB + 1][KS][BN + 4], Bsi[DB + 1][KS][BN + 4];
+  __shared__ R Asr[2][KS][BM + 4], Asi[2][KS][BM + 4], Bsr[2][KS][BN + 4], Bsi[2][KS][BN + 4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -80,11 +81,9 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
-  // FP32: three real products per complex product (Karatsuba): t1 = Re A Re B,
+  // Three real products per complex product (Karatsuba): t1 = Re A Re B,
   // t2 = Im A Im B, t3 = (Re A + Im A)(Re B + Im B); Re C = t1 - t2, Im C = t3 - t1 - t2.
-  // FP64: four products (t1 = Re C, t3 = Im C, t2 unused): the third accumulator set
-  // would halve the occupancy of the FP64 tiles.
-  constexpr bool K3 = sizeof(R) == 4;
+  // Its rounding error is bounded by a small multiple of eps |A| |B|, as for four.
   ACC t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -164,55 +163,35 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         ai[x] = Asi[sb][kr][wr * 32 + x * 16 + (lane & 15)];
         br[x] = Bsr[sb][kr][wc * 32 + x * 16 + (lane & 15)];
         bi[x] = Bsi[sb][kr][wc * 32 + x * 16 + (lane & 15)];
-        if (K3) {
-          as[x] = ar[x] + ai[x];
-          bs[x] = br[x] + bi[x];
-        }
+        as[x] = ar[x] + ai[x];
+        bs[x] = br[x] + bi[x];
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          if (K3) {
-            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
-            t2[x][y] = mfma16(bi[y], ai[x], t2[x][y]);
-            t3[x][y] = mfma16(bs[y], as[x], t3[x][y]);
-          } else {
-            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
-            t3[x][y] = mfma16(bi[y], ar[x], t3[x][y]);
-            t1[x][y] = mfma16(-bi[y], ai[x], t1[x][y]);
-            t3[x][y] = mfma16(br[y], ai[x], t3[x][y]);
-          }
+          t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+          t2[x][y] = mfma16(bi[y], ai[x], t2[x][y]);
+          t3[x][y] = mfma16(bs[y], as[x], t3[x][y]);
         }
     }
   };
 
-  if (DB) {
-    // two LDS stages: the stage computed from is never the one being filled, so one
-    // barrier per stage separates the fill of stage i + 1 from its use
-    int sb = 0;
-    if (kbeg < kend) {
-      load(kbeg);
-      store(0);
-    }
+  // Two LDS stages: the stage computed from is never the one being filled, so one
+  // barrier per stage separates the fill of stage i + 1 from its use.
+  int sb = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += KS) {
+    const bool more = k0 + KS < kend;
+    if (more) load(k0 + KS);
+    compute(sb);
+    if (more) store(sb ^ 1);
     __syncthreads();
-    for (int k0 = kbeg; k0 < kend; k0 += KS) {
-      const bool more = k0 + KS < kend;
-      if (more) load(k0 + KS);
-      compute(sb);
-      if (more) store(sb ^ 1);
-      __syncthreads();
-      sb ^= 1;
-    }
-  } else {
-    if (kbeg < kend) load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += KS) {
-      __syncthreads();
-      store(0);
-      __syncthreads();
-      if (k0 + KS < kend) load(k0 + KS);
-      compute(0);
-    }
+    sb ^= 1;
   }
 
   // Epilogue.
@@ -232,8 +211,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         // row l/16 + 4r of the 16x16 block, column l%16 in both (here rows are C columns).
         const int col = col0 + wc * 32 + y * 16 + (sizeof(R) == 8 ? ((lane >> 4) + 4 * r) : (((lane >> 4) << 2) + r));
         if (row < g.M && col < g.N) {
-          C acc = K3 ? mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r])
-                     : mk<R>(t1[x][y][r], t3[x][y][r]);
+          const C acc = mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
           C v = cmul(g.alpha, acc);
           if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * ldc]));
           Cb[row + (long)col * ldc] = v;
