@@ -219,16 +219,19 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
       }
 }
 
-// Tall-skinny products C = A W (beta = 0, alpha = 1) with K, N <= 64: the subspace
-// updates [S | KS | Omega S] C of the eigensolver.  W (at most 64 x 64) is staged in LDS
-// once per workgroup; the A operand goes straight from global memory into MFMA operand
-// registers (16 consecutive rows per load), so a workgroup is one pass over 128 rows
-// without a k-loop pipeline.  Wave w computes rows 32 w .. 32 w + 31 in two stripes.
-template <typename R, int NB>
-__global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
+// Tall-skinny products C = A W (beta = 0, alpha = 1) with K <= 64, N <= 16 NB: the
+// subspace updates [S | KS | Omega S] C of the eigensolver.  Optionally output columns
+// j >= csplit go to column j + cgap (two coefficient blocks, one pass over A).  W is staged in LDS once
+// per workgroup; a wave takes ST stripes of 16 rows and, per stripe, issues the loads of
+// all its A values (16 consecutive rows per load, every k) before the first product, so
+// one stripe's whole row block is in flight at once.  Three real products per complex
+// product (Karatsuba).
+template <typename R, int NB, int ST>
+__global__ __launch_bounds__(256, 2) void skinny_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
-  __shared__ R Wr[64][65], Wi[64][65];
+  constexpr int NC = 16 * NB;
+  __shared__ R Wr[64][NC + 1], Wi[64][NC + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int b = blockIdx.y;
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
   const C* A = g.A + (long)(b / g.dA) * g.sA;
   const C* W = g.B + (long)(b / g.dB) * g.sB;
   C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
-  for (int e = tid; e < 64 * 64; e += 256) {
+  for (int e = tid; e < 64 * NC; e += 256) {
     const int k = e & 63, j = e >> 6;
     C v = mk<R>(0, 0);
     if (k < g.K && j < g.N) v = W[k + (long)j * g.ldb];
@@ -245,35 +248,33 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
   }
   __syncthreads();
 #pragma unroll 1
-  for (int stripe = 0; stripe < 2; ++stripe) {
-    const int i0 = blockIdx.x * 128 + wave * 32 + 16 * stripe;
+  for (int stripe = 0; stripe < ST; ++stripe) {
+    const int i0 = blockIdx.x * 64 * ST + wave * 16 * ST + 16 * stripe;
     if (i0 >= g.M) break;
     const int i = i0 + li;
-    ACC cr[NB], ci[NB];
+    C av[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lg;
+      av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
+    }
+    ACC t1[NB], t2[NB], t3[NB];
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
-      cr[y] = (ACC){0, 0, 0, 0};
-      ci[y] = (ACC){0, 0, 0, 0};
+      t1[y] = (ACC){0, 0, 0, 0};
+      t2[y] = (ACC){0, 0, 0, 0};
+      t3[y] = (ACC){0, 0, 0, 0};
     }
-#pragma unroll 1
-    for (int kg = 0; kg < 4; ++kg) {  // four groups of four k-steps: loads of a group in flight together
-      C av[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = 16 * kg + 4 * q + lg;
-        av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
-      }
+    for (int q = 0; q < 16; ++q) {  // k >= K: A is zero there and W's rows are zero
+      const int k = 4 * q + lg;
+      const R ar = av[q].x, ai = av[q].y, as = ar + ai;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = 16 * kg + 4 * q + lg;
-#pragma unroll
-        for (int y = 0; y < NB; ++y) {
-          const R br = Wr[k][16 * y + li], bi = Wi[k][16 * y + li];
-          cr[y] = mfma16(br, av[q].x, cr[y]);
-          ci[y] = mfma16(bi, av[q].x, ci[y]);
-          cr[y] = mfma16(-bi, av[q].y, cr[y]);
-          ci[y] = mfma16(br, av[q].y, ci[y]);
-        }
+      for (int y = 0; y < NB; ++y) {
+        const R br = Wr[k][16 * y + li], bi = Wi[k][16 * y + li];
+        t1[y] = mfma16(br, ar, t1[y]);
+        t2[y] = mfma16(bi, ai, t2[y]);
+        t3[y] = mfma16(br + bi, as, t3[y]);
       }
     }
 #pragma unroll
@@ -281,7 +282,9 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = 16 * y + (sizeof(R) == 8 ? (lg + 4 * r) : (4 * lg + r));
-        if (i < g.M && col < g.N) Cb[i + (long)col * g.ldc] = mk<R>(cr[y][r], ci[y][r]);
+        const int cc = (g.csplit > 0 && col >= g.csplit) ? col + g.cgap : col;
+        if (i < g.M && col < g.N)
+          Cb[i + (long)cc * g.ldc] = mk<R>(t1[y][r] - t2[y][r], t3[y][r] - t1[y][r] - t2[y][r]);
       }
   }
 }
@@ -445,13 +448,16 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     g.ksplit = 1;
   }
   // Tall-skinny updates (the eigensolver's basis times a small coefficient matrix).
-  if (opa == 0 && opb == 0 && !g.tri && !g.op && g.ksplit == 1 && g.K <= 64 && g.N <= 64 && g.M >= 256 &&
+  if (opa == 0 && opb == 0 && !g.tri && !g.op && g.ksplit == 1 && g.K <= 64 && g.N <= 64 && (g.M >= 256 || g.csplit > 0) &&
       g.alpha.x == 1 && g.alpha.y == 0 && g.beta.x == 0 && g.beta.y == 0) {
-    dim3 grid2((unsigned)((g.M + 127) / 128), (unsigned)g.batch);
-    if (g.N <= 32) hipLaunchKernelGGL((skinny_kernel<R, 2>), grid2, dim3(256), 0, st, g);
-    else hipLaunchKernelGGL((skinny_kernel<R, 4>), grid2, dim3(256), 0, st, g);
+    dim3 grid2((unsigned)((g.M + 64 * 4 - 1) / (64 * 4)), (unsigned)g.batch);
+    if (g.N <= 16) hipLaunchKernelGGL((skinny_kernel<R, 1, 4>), grid2, dim3(256), 0, st, g);
+    else if (g.N <= 32) hipLaunchKernelGGL((skinny_kernel<R, 2, 4>), grid2, dim3(256), 0, st, g);
+    else if (g.N <= 48) hipLaunchKernelGGL((skinny_kernel<R, 3, 4>), grid2, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((skinny_kernel<R, 4, 4>), grid2, dim3(256), 0, st, g);
     return (int)hipGetLastError();
   }
+  if (g.csplit > 0) return (int)hipErrorInvalidValue;  // split output only in the tall-skinny kernel
   // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
   // FP32 A^H the LDS-staged 128 x 32 tiles below read A faster).
   if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 && (opa == 0 || sizeof(R) == 8)) {

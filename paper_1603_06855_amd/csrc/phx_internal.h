@@ -25,6 +25,7 @@ struct GemmArgs {
   int kdiv;
   int ksplit;
   C_t<R>* Cpart;
+  int csplit, cgap;  // tall-skinny only: output column j >= csplit (if > 0) is stored at j + cgap
 };
 
 template <typename R>

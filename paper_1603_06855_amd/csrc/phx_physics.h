@@ -57,8 +57,10 @@ void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long 
 // small.hip: per-k dense kernels on m x m (m <= 64) Gram matrices, FP64.
 void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st,
                       const int* kact = nullptr);
+// Cx, Cp: m x s per k at k-stride sCx (0: m s).
 void launch_rr_gen(const double2* G2, int m, int s, int nk, double drop, double2* C0, int* keep, double2* Cx,
-                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact = nullptr);
+                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact = nullptr,
+                   long sCx = 0);
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta,
                    int* sweeps, hipStream_t st, const int* kact = nullptr);
 

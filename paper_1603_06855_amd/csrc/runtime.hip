@@ -437,8 +437,11 @@ struct Solver {
 template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
-          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1) {
+          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1,
+          int csplit = 0, int cgap = 0) {
   GemmArgs<R> g{};
+  g.csplit = csplit;
+  g.cgap = cgap;
   g.op = op;
   g.kact = kact;
   g.kdiv = kdiv;
@@ -554,15 +557,15 @@ void rayleigh_ritz_fused(Solver& sv) {
                2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, sv.kact, 1);
   PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nk, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nk);
   PROF_BEGIN(PROF_SMALL);
-  launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cr, sv.Cp, sv.theta, sv.sweeps, ctx->stream,
-                sv.kact);
+  // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
+  // the basis produces both: columns 0..s-1 -> X, s..2s-1 -> P (basis columns 2s..3s-1)
+  launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cp, sv.Cp + m * s, sv.theta, sv.sweeps,
+                ctx->stream, sv.kact, 2 * m * s);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
-  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO, 1, nullptr, 0, sv.kact, 3);
-  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, m * s, 3, sv.Big2 + 2 * s * n3, n3,
-               n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3);
+  gemm<double>(ctx, 0, 0, n3, 2 * s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, 2 * m * s, 3, sv.Big2, n3, n3 * m,
+               ONE, ZERO, 1, nullptr, 0, sv.kact, 3, (int)s, (int)s);
   launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nk, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
   std::swap(sv.Big, sv.Big2);
@@ -619,7 +622,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.Gpart = dbuf<double2>(ctx, "Gpart", (long)sv.ksplit * nk * m * m);
   sv.C0 = dbuf<double2>(ctx, "C0", (long)nk * m * m);
   sv.Cr = dbuf<double2>(ctx, "Cr", (long)nk * m * s);
-  sv.Cp = dbuf<double2>(ctx, "Cp", (long)nk * m * s);
+  sv.Cp = dbuf<double2>(ctx, "Cp", (long)nk * m * 2 * s);
   sv.G2 = dbuf<double2>(ctx, "G2", (long)nk * 2 * m * m);
   sv.G2part = dbuf<double2>(ctx, "G2part", (long)sv.ksplit * nk * 2 * m * m);
   sv.keep = dbuf<int>(ctx, "keep", (long)nk * m);

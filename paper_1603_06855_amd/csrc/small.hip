@@ -313,7 +313,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_eig_kernel(const double2* G, cons
 // Cp = C0[:, s:] V[s:, sel] (the part of the Ritz vectors outside the first s columns).
 // C0 (m x m per k) is scratch written and read back here.
 __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int m, int s, double drop, double2* C0g,
-                                                     int* keep, double2* Cx, double2* Cp, double* theta,
+                                                     int* keep, double2* Cx, double2* Cp, long sCx, double* theta,
                                                      int* sweeps_out, const int* kact) {
   if (kact && !kact[blockIdx.x]) return;  // a converged k-point: its Ritz values stay
   __shared__ JacobiLDS L;
@@ -489,8 +489,8 @@ __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int
       x = cadd(x, t);
       if (l >= s) pdir = cadd(pdir, t);
     }
-    Cx[(long)k * m * s + r + (long)j * m] = x;
-    Cp[(long)k * m * s + r + (long)j * m] = pdir;
+    Cx[(long)k * sCx + r + (long)j * m] = x;
+    Cp[(long)k * sCx + r + (long)j * m] = pdir;
   }
   if (tid < s) theta[k * s + tid] = L.As[L.order[tid]][L.order[tid]].x;
 }
@@ -501,9 +501,9 @@ void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0,
 }
 
 void launch_rr_gen(const double2* G2, int m, int s, int nk, double drop, double2* C0, int* keep, double2* Cx,
-                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact) {
-  hipLaunchKernelGGL(rr_gen_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G2, m, s, drop, C0, keep, Cx, Cp, theta,
-                     sweeps, kact);
+                   double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact, long sCx) {
+  hipLaunchKernelGGL(rr_gen_kernel, dim3(nk), dim3(SMALL_NT), 0, st, G2, m, s, drop, C0, keep, Cx, Cp,
+                     sCx > 0 ? sCx : (long)m * s, theta, sweeps, kact);
 }
 
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta, int* sweeps,
