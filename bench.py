@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--streams", type=int, default=8, help="designs solved concurrently (library option)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="library option coarse_tol")
     ap.add_argument("--shift", type=float, default=None, help="library option shift")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                    help="any other library option (phx_set_option), repeatable")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gate", action="store_true", help="skip the mixed-vs-FP64 accuracy gate")
     args = ap.parse_args()
@@ -68,6 +70,9 @@ def main():
         ctx.set_option("coarse_tol", args.coarse_tol)
     if args.shift is not None:
         ctx.set_option("shift", args.shift)
+    for kv in args.opt:
+        key, val = kv.split("=", 1)
+        ctx.set_option(key, float(val))
 
     def step():
         # every design of the step through one batched call (designs spread over

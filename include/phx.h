@@ -91,6 +91,12 @@ const char* phx_last_error(const phx_ctx* ctx);
  * inverses of the factor's 256-wide (FP64: 128-wide) diagonal blocks, computed
  * once per factorisation, so every solve step is a matrix product; 0: blocked
  * substitution inside each diagonal block),
+ * "kshare" (1..8, default 4), "kshare_dist" (default 0.5) and "kshare_rel"
+ * (default 0.5): consecutive k-points of a chunk that lie within kshare_dist
+ * (Cartesian, cycles per a) of a group's first k-point, and within kshare_rel
+ * times the shorter of the two wave vectors, share that k-point's
+ * preconditioner factor, at most kshare of them (needs "sbinv"; 1: every
+ * k-point has its own factor; Gamma never shares),
  * "kskip" (1, default: a k-point whose wanted bands all meet the tolerance is
  * frozen, its vectors, eigenvalues and residuals kept, and the remaining
  * iterations of its chunk skip it; 0: every k-point of a chunk iterates until the
@@ -111,7 +117,9 @@ int phx_set_option(phx_ctx* ctx, const char* key, double value);
 /* Statistics of the last solve: "iters" (eigensolver iterations of the
  * slowest chunk), "chunks", "block", "kchunk", "rr_sweeps" (most Jacobi sweeps
  * one Rayleigh-Ritz step needed at any k), "coarse_iters" (iterations of the
- * coarse start).  "prof.<class>.<ms|flops|bytes|count>"
+ * coarse start), "iters_mean_k" (mean over k-points of the iteration at which
+ * each met the tolerance), "factors" (preconditioner factorisations of the
+ * order-M solves).  "prof.<class>.<ms|flops|bytes|count>"
  * reads the kernel-class timers (enabled with the option "profile"). */
 int phx_get_stat(const phx_ctx* ctx, const char* key, double* value);
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   const int b = (int)bat;
   if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
   const int sp = blockIdx.z;
-  const C* A = g.A + (long)(b / g.dA) * g.sA;
+  const C* A = g.A + (long)(g.amap ? g.amap[b] : b / g.dA) * g.sA;
   const C* B = g.B + (long)(b / g.dB) * g.sB;
 
   int kchunk = g.K;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256, 3) void nrhs_kernel(GemmArgs<R> g) {
   const int li = lane & 15, lg = lane >> 4;
   const int b = blockIdx.y;
   if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
-  const C* A = g.A + (long)(b / g.dA) * g.sA;
+  const C* A = g.A + (long)(g.amap ? g.amap[b] : b / g.dA) * g.sA;
   const C* Bm = g.B + (long)(b / g.dB) * g.sB;
   C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
   const int i0 = blockIdx.x * 64 * X + wave * 16 * X;
@@ -448,7 +448,8 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     g.ksplit = 1;
   }
   // Tall-skinny updates (the eigensolver's basis times a small coefficient matrix).
-  if (opa == 0 && opb == 0 && !g.tri && !g.op && g.ksplit == 1 && g.K <= 64 && g.N <= 64 && (g.M >= 256 || g.csplit > 0) &&
+  if (opa == 0 && opb == 0 && !g.tri && !g.op && !g.amap && g.ksplit == 1 && g.K <= 64 && g.N <= 64 &&
+      (g.M >= 256 || g.csplit > 0) &&
       g.alpha.x == 1 && g.alpha.y == 0 && g.beta.x == 0 && g.beta.y == 0) {
     dim3 grid2((unsigned)((g.M + 64 * 4 - 1) / (64 * 4)), (unsigned)g.batch);
     if (g.N <= 16) hipLaunchKernelGGL((skinny_kernel<R, 1, 4>), grid2, dim3(256), 0, st, g);
@@ -458,6 +459,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     return (int)hipGetLastError();
   }
   if (g.csplit > 0) return (int)hipErrorInvalidValue;  // split output only in the tall-skinny kernel
+  if (g.amap && g.ksplit > 1) return (int)hipErrorInvalidValue;
   // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
   // FP32 A^H the LDS-staged 128 x 32 tiles below read A faster).
   if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 && (opa == 0 || sizeof(R) == 8)) {
@@ -829,7 +831,7 @@ template int sb_inverse_batched<float>(const float2*, int, long, long, int, cons
 template <typename R>
 int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* SBinv, C_t<R>* B, long ldb,
                 long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook,
-                const int* kact) {
+                const int* kact, const int* fmap) {
   constexpr int WS = sizeof(R) == 4 ? 256 : 128;
   const double cb = (double)sizeof(C_t<R>);
   const int nsb = (n + WS - 1) / WS;
@@ -840,7 +842,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     {
       GemmArgs<R> g{};
       g.M = w; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
-      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;
+      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI; g.amap = fmap;
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z + J0; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
@@ -853,7 +855,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     if (rem > 0) {
       GemmArgs<R> g{};
       g.M = rem; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
-      g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL;
+      g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL; g.amap = fmap;
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
@@ -868,7 +870,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     {
       GemmArgs<R> g{};
       g.M = w; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
-      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI;  // op = C: the inverse of L_JJ^H
+      g.A = SBinv + (long)sbi * WS * WS; g.lda = WS; g.sA = sI; g.amap = fmap;  // op = C: inverse of L_JJ^H
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
@@ -880,7 +882,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     if (J0 > 0) {
       GemmArgs<R> g{};
       g.M = J0; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
-      g.A = L + J0; g.lda = lda; g.sA = sL;  // rows J0..J0+w, cols 0..J0-1; op = C
+      g.A = L + J0; g.lda = lda; g.sA = sL; g.amap = fmap;  // rows J0..J0+w, cols 0..J0-1; op = C
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
@@ -953,8 +955,10 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook, const C_t<R>* sbinv, const int* kact) {
-  if (nc <= 32 && sbinv) return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook, kact);
+                  const ProfHook* hook, const C_t<R>* sbinv, const int* kact, const int* fmap) {
+  if (nc <= 32 && sbinv)
+    return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook, kact, fmap);
+  if (fmap) return (int)hipErrorInvalidValue;  // shared factors only with the super-block inverses
   if (nc <= 32) return potrs_narrow<R>(L, n, lda, sL, batch, Dinv, sD, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   const int T = n / 64;
   const double cb = (double)sizeof(C_t<R>);
@@ -1017,9 +1021,9 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
 }
 template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
                                    long, double2*, long, long, int, hipStream_t, const ProfHook*, const double2*,
-                                   const int*);
+                                   const int*, const int*);
 template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
                                   long, float2*, long, long, int, hipStream_t, const ProfHook*, const float2*,
-                                  const int*);
+                                  const int*, const int*);
 
 }  // namespace phx

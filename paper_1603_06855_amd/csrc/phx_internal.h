@@ -26,6 +26,7 @@ struct GemmArgs {
   int ksplit;
   C_t<R>* Cpart;
   int csplit, cgap;  // tall-skinny only: output column j >= csplit (if > 0) is stored at j + cgap
+  const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
 };
 
 template <typename R>
@@ -56,11 +57,13 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
 
 // sbinv (may be NULL): inverses of the diagonal super-blocks from sb_inverse_batched;
 // given, narrow solves (nc <= 32) run as GEMMs only, skipping the matrices whose kact
-// entry is 0 (kact may be NULL).
+// entry is 0 (kact may be NULL), and right-hand side b uses factor fmap[b] (device
+// array; NULL: factor b; non-NULL requires sbinv).
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr, const int* kact = nullptr);
+                  const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr, const int* kact = nullptr,
+                  const int* fmap = nullptr);
 
 // Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
 // Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS).

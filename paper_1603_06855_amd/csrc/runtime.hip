@@ -52,6 +52,9 @@ struct Opts {
   int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
   int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
   int kskip = 1;             // 1: k-points whose wanted bands have converged skip later iterations
+  int kshare = 4;            // at most this many consecutive k-points share one preconditioner factor
+  double kshare_dist = 0.5;  // ... if within this Cartesian distance (cycles per a) of the group's first
+  double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
 };
 
 struct Stats {
@@ -59,6 +62,7 @@ struct Stats {
   int rr_sweeps = 0;  // most Jacobi sweeps any k needed in a Rayleigh-Ritz step of the last solve
   int coarse_iters = 0;  // eigensolver iterations of the coarse start (slowest chunk)
   long k_conv_iters = 0, k_count = 0;  // sum over k of the iteration at which k converged
+  long factors = 0;                     // preconditioner factorisations (order M solves)
 };
 
 // Kernel-class timing with HIP events recorded on the context stream.
@@ -429,6 +433,7 @@ struct Solver {
   void* Dinv;  // nk x n3/64 x 4096 (prec)
   void* SBinv; // nk x nsb x WS^2 inverses of the factor's diagonal super-blocks, or NULL
   int* kact;   // per k: 1 while a wanted band of that k-point has not met the tolerance
+  int* fmap;   // per k: index of its preconditioner factor (NULL: its own)
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -577,7 +582,7 @@ void precondition(Solver& sv) {
   const long n3 = sv.n3;
   KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
                         (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk(),
-                        (const C_t<R>*)sv.SBinv, sv.kact));
+                        (const C_t<R>*)sv.SBinv, sv.kact, sv.fmap));
   launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
                   sv.kact);
   KCHK(hipGetLastError());
@@ -631,8 +636,45 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
   sv.rn = dbuf<double>(ctx, "rn", (long)nk * s);
   sv.rnorm = dbuf<double>(ctx, "rnorm", (long)nk * s);
-  sv.A = dbuf<C_t<R>>(ctx, "A", (long)nk * n3 * n3);
-  sv.Dinv = dbuf<C_t<R>>(ctx, "Dinv", (long)nk * (n3 / 64) * 4096);
+  // Preconditioner factors: consecutive k-points of the chunk within kshare_dist of a
+  // group's first k-point, and within kshare_rel of the shorter of the two wave vectors
+  // (at most kshare of them), share that k-point's factor; the shared solves need the
+  // super-block inverses.  The relative bound keeps Gamma, where K has the three rigid
+  // translations as null vectors and the factor is far from that of any other k, on a
+  // factor of its own.
+  std::vector<int> fmap_h(nk), lead;
+  {
+    const int kmax = ctx->opt.sbinv ? ctx->opt.kshare : 1;
+    auto cart = [&](int k, int c) {
+      return q[3 * k] * d.rec.t[0][c] + q[3 * k + 1] * d.rec.t[1][c] + q[3 * k + 2] * d.rec.t[2][c];
+    };
+    for (int k = 0; k < nk; ++k) {
+      bool join = false;
+      if (!lead.empty()) {
+        const int l = lead.back();
+        double dd = 0, kk = 0, ll = 0;
+        for (int c = 0; c < 3; ++c) {
+          dd += (cart(k, c) - cart(l, c)) * (cart(k, c) - cart(l, c));
+          kk += cart(k, c) * cart(k, c);
+          ll += cart(l, c) * cart(l, c);
+        }
+        const double dist = sqrt(dd);
+        join = k - l < kmax && dist <= ctx->opt.kshare_dist &&
+               dist <= ctx->opt.kshare_rel * sqrt(std::min(kk, ll));
+      }
+      if (!join) lead.push_back(k);
+      fmap_h[k] = (int)lead.size() - 1;
+    }
+  }
+  const int nkf = (int)lead.size();
+  if (!tol_override) ctx->stats.factors += nkf;
+  sv.fmap = nullptr;
+  if (nkf < nk) {
+    sv.fmap = dbuf<int>(ctx, "fmap", nk);
+    HIPCHK(hipMemcpyAsync(sv.fmap, fmap_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  sv.A = dbuf<C_t<R>>(ctx, "A", (long)nkf * n3 * n3);
+  sv.Dinv = dbuf<C_t<R>>(ctx, "Dinv", (long)nkf * (n3 / 64) * 4096);
   sv.Rp = dbuf<C_t<R>>(ctx, "Rp", (long)nk * n3 * s);
   sv.Zp = dbuf<C_t<R>>(ctx, "Zp", (long)nk * n3 * s);
   double* qd = dbuf<double>(ctx, "q", 3L * nk);
@@ -668,22 +710,30 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
 
   // Pencil A = K + sigma Omega and its Cholesky factor.
   PROF_BEGIN(PROF_ASSEMBLE);
-  launch_assemble<R>(d.Dm, d.Bm, d.Os, sv.Kv, d.N, d.Np, nk, d.c2, sv.sigma_d, (C_t<R>*)sv.A, n3 * n3, 0, st);
+  const double* Kvf = sv.Kv;
+  if (nkf < nk) {  // wave vectors of the factors' k-points
+    double* kf = dbuf<double>(ctx, "Kvf", (long)nkf * d.Np * 3);
+    for (int i = 0; i < nkf; ++i)
+      HIPCHK(hipMemcpyAsync(kf + (long)i * d.Np * 3, sv.Kv + (long)lead[i] * d.Np * 3, d.Np * 3 * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    Kvf = kf;
+  }
+  launch_assemble<R>(d.Dm, d.Bm, d.Os, Kvf, d.N, d.Np, nkf, d.c2, sv.sigma_d, (C_t<R>*)sv.A, n3 * n3, 0, st);
   // algorithmic bytes: the lower triangle of every A(k) written once, the three N x N operators read once
-  PROF_END(PROF_ASSEMBLE, 0, (double)sizeof(C_t<R>) * nk * (3.0 * d.N) * (3.0 * d.N + 1) / 2 + 48.0 * d.N * d.N);
+  PROF_END(PROF_ASSEMBLE, 0, (double)sizeof(C_t<R>) * nkf * (3.0 * d.N) * (3.0 * d.N + 1) / 2 + 48.0 * d.N * d.N);
   KCHK(hipGetLastError());
   HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
-  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag, st,
-                        ctx->hk()));
+  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag,
+                        st, ctx->hk()));
   sv.SBinv = nullptr;
   if (ctx->opt.sbinv) {
     constexpr int WS = sizeof(R) == 4 ? 256 : 128;
     const long nsb = (n3 + WS - 1) / WS;
-    sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nk * nsb * WS * WS);
+    sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nkf * nsb * WS * WS);
     PROF_BEGIN(PROF_TRSM_DIAG);
-    KCHK(sb_inverse_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nk, (const C_t<R>*)sv.Dinv,
+    KCHK(sb_inverse_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
                                (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, st));
-    PROF_END(PROF_TRSM_DIAG, (double)nk * 8.0 * n3 * WS * WS / 6.0, (double)nk * sizeof(C_t<R>) * n3 * WS);
+    PROF_END(PROF_TRSM_DIAG, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
   }
 
   // Per-k activity: every k-point starts active; one whose wanted bands all meet the
@@ -853,6 +903,7 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
   ctx->stats.rr_sweeps = 0;
   ctx->stats.coarse_iters = 0;
   ctx->stats.k_conv_iters = 0;
+  ctx->stats.factors = 0;
   ctx->stats.k_count = 0;
   bool conv = true;
   for (int k0 = 0; k0 < nk; k0 += kc) {
@@ -998,6 +1049,9 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
   else if (k == "kskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.kskip = (int)v; }
+  else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
+  else if (k == "kshare_dist") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_dist = v; }
+  else if (k == "kshare_rel") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_rel = v; }
   else if (k == "profile") { ctx->prof.on = (v != 0); }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
@@ -1013,6 +1067,7 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "kchunk") *value = ctx->stats.kchunk;
   else if (k == "rr_sweeps") *value = ctx->stats.rr_sweeps;
   else if (k == "coarse_iters") *value = ctx->stats.coarse_iters;
+  else if (k == "factors") *value = (double)ctx->stats.factors;
   else if (k == "iters_mean_k") *value = ctx->stats.k_count ? (double)ctx->stats.k_conv_iters / ctx->stats.k_count : 0;
   else if (k.rfind("prof.", 0) == 0) {
     const size_t dot = k.rfind('.');
@@ -1417,6 +1472,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
       ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, w->stats.rr_sweeps);
       ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, w->stats.coarse_iters);
       ctx->stats.k_conv_iters += w->stats.k_conv_iters;
+      ctx->stats.factors += w->stats.factors;
       ctx->stats.k_count += w->stats.k_count;
       ctx->stats.chunks += w->stats.chunks;
       ctx->stats.block = std::max(ctx->stats.block, w->stats.block);

@@ -211,6 +211,28 @@ def test_bands_config1_converged_k_points_frozen_or_not(ctx, config1_ref, prec, 
     assert _om_err(res[1], res[0]).max() <= bar
 
 
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-10, 1e-9), ("mixed", 1e-6, 1e-6)])
+def test_bands_shared_preconditioner_factors(ctx, prec, tol, bar):
+    """Neighbouring k-points sharing one preconditioner factor (option kshare; SC 16^3,
+    M=3, 30 k-points about 0.13 apart) give the same bands as one factor per k-point,
+    with fewer factorisations."""
+    wl = synth.config2()
+    cell, rho = wl.cells[0], wl.designs[0]
+    q = phx.kpath(cell.lattice, wl.nk, wl.path)
+    key = "tol_fp64" if prec == "fp64" else "tol_mixed"
+    ctx.set_option(key, tol)
+    res, nf = {}, {}
+    for ks in (1, 2):
+        ctx.set_option("kshare", ks)
+        res[ks] = ctx.bands(cell, rho, q, wl.nbands, prec)
+        nf[ks] = ctx.stat("factors")
+        log(prec, "kshare", ks, "factors", nf[ks], "iters", ctx.stat("iters"), "mean", ctx.stat("iters_mean_k"))
+    ctx.set_option("kshare", 2)
+    ctx.set_option(key, 1e-8 if prec == "fp64" else 1e-6)
+    assert nf[1] == wl.nk and nf[2] < wl.nk
+    assert _om_err(res[2], res[1]).max() <= bar
+
+
 @pytest.mark.parametrize("lat", ["SC", "BCC", "FCC"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_homogeneous_closed_form(ctx, lat, prec):
