@@ -46,9 +46,14 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "design-only, see DESIGN.md)"}), flush=True)
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sharding over GPUs is "
+                                   "not built)"}), flush=True)
         sys.exit(2)
+
+    # One hardware queue per design stream (HIP maps streams onto GPU_MAX_HW_QUEUES queues,
+    # 4 by default; two streams on one queue run their kernels one after the other).  Read
+    # when the HIP runtime starts, so set before torch touches the GPU.
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.streams)))
 
     import numpy as np
     import torch
@@ -101,6 +106,7 @@ def main():
     ctx.set_option("profile_reset", 1)
     ctx.set_option("profile", 1)
     torch.cuda.synchronize()
+    w0 = time.monotonic_ns()
     t0 = time.perf_counter()
     iters = 0
     sweeps = 0
@@ -114,6 +120,7 @@ def main():
         iters_mean_k = ctx.stat("iters_mean_k")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    w1 = time.monotonic_ns()
     ctx.set_option("profile", 0)
 
     elapsed = t1 - t0
@@ -121,28 +128,51 @@ def main():
     value = units / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble", "apply", "op_gemm", "gram",
-               "small", "update", "residual", "adjoint"]
+    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "solve_fwd", "solve_bwd", "sbinv",
+               "assemble", "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"]
     prof = {c: {k: ctx.stat(f"prof.{c}.{k}") for k in ("ms", "flops", "bytes", "count")} for c in classes}
-    # Classes that are exactly one kernel (one instantiation, each launch timed on its own
-    # by HIP events on the library stream): the roofline entry is the one of them that took
-    # the most time in the timed region.
+    # Classes that are exactly one kernel, each launch timed by HIP events that the launch
+    # itself records at the kernel's start and end (hipExtLaunchKernelGGL, on the library
+    # stream the kernel runs on): the roofline entry is the one of them that took the most
+    # time in the timed region; the others follow under "others".
     fp_chol = "float" if args.precision == "mixed" else "double"
-    single = {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", "fp32" if fp_chol == "float" else "fp64"),
-              "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 2>", "fp64")}
-    dom = max(single, key=lambda c: prof[c]["ms"])
-    p = prof[dom]
-    name, fp = single[dom]
-    achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[fp] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / (PEAK[fp] / 1e12), "traffic": None, "kernel": name, "dtype": fp,
-            "launches": int(p["count"]), "avg_launch_us": 1e3 * p["ms"] / max(p["count"], 1),
-            "flops_per_launch": p["flops"] / max(p["count"], 1)}
-    roof["traffic"] = measured_traffic(name)
-    other = [c for c in single if c != dom][0]
-    po = prof[other]
-    roof["next"] = {"kernel": single[other][0], "achieved": po["flops"] / max(po["ms"], 1e-9) / 1e9,
-                    "avg_launch_us": 1e3 * po["ms"] / max(po["count"], 1), "launches": int(po["count"])}
+    fpn = "fp32" if fp_chol == "float" else "fp64"
+    nbk = 1 if min(21, nb + max(8, nb)) <= 16 else 2
+    bwd = (f"phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
+           else f"phx::nrhs_kernel<double, 1, {nbk}, 1>")
+    single = {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", fpn, "mfma"),
+              "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 2>", "fp64", "mfma"),
+              "solve_fwd": (f"phx::nrhs_kernel<{fp_chol}, 0, {nbk}, 1>", fpn, "hbm"),
+              "solve_bwd": (bwd, fpn, "hbm")}
+    # The library counts the work of the padded problem (Np = 64 ceil(N / 64) waves per
+    # displacement component); the algorithmic work is that of the N-wave problem: the
+    # Cholesky update scales as the cube of the size, the operator products as the square.
+    N = (2 * args.M + 1) ** 3
+    Np = 64 * ((N + 63) // 64)
+    unpad = {"herk": (N / Np) ** 3, "op_gemm": (N / Np) ** 2}
+    for c in unpad:
+        prof[c]["flops"] *= unpad[c]
+
+    def entry(c):
+        p = prof[c]
+        name, fp, bound = single[c]
+        us = 1e3 * p["ms"] / max(p["count"], 1)
+        if bound == "mfma":
+            achieved = p["flops"] / max(p["ms"] * 1e-3, 1e-12) / 1e12
+            e = {"bound": "mfma", "achieved": achieved, "peak": PEAK[fp] / 1e12, "unit": "TFLOP/s",
+                 "frac": achieved / (PEAK[fp] / 1e12)}
+        else:
+            achieved = p["bytes"] / max(p["ms"] * 1e-3, 1e-12) / 1e9
+            e = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                 "frac": achieved / (PEAK["hbm"] / 1e9)}
+        e.update({"traffic": measured_traffic(name), "kernel": name, "dtype": fp, "launches": int(p["count"]),
+                  "avg_launch_us": us, "flops_per_launch": p["flops"] / max(p["count"], 1),
+                  "alg_bytes_per_launch": p["bytes"] / max(p["count"], 1), "total_ms": p["ms"]})
+        return e
+
+    order = sorted(single, key=lambda c: -prof[c]["ms"])
+    roof = entry(order[0])
+    roof["others"] = [entry(c) for c in order[1:]]
     breakdown = {c: round(prof[c]["ms"] / args.steps, 3) for c in classes}
 
     cpu = None
@@ -171,6 +201,7 @@ def main():
         "roofline": roof,
         "stage_ms_per_step": breakdown,
         "accuracy_gate": gate,
+        "timed_window_monotonic_ns": [w0, w1],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -178,24 +209,23 @@ def main():
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none or the kernel's source text (the GEMM kernel
-    template's definition) changed since it was taken."""
+    summaries (profiles/*_traffic.md, one per kernel), or None when there is none or the
+    kernel's source text (the GEMM kernel template's definition) changed since it was taken."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "herk_fcc32_m5_traffic.md")
-    if kernel != "phx::zgemm_kernel<float, 0, 1, 64, 64, 1>" or not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
-            k, v = line.split(":", 1)
-            fields[k] = v.strip()
     src = open(os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "dense.hip")).read()
     start = src.index("template <typename R, int OPA, int OPB, int BM, int BN, int MODE>")
     end = src.index("\n}\n", start) + 3  # the kernel's definition
     sha = hashlib.sha256(src[start:end].encode()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        fields = {}
+        for line in open(path):
+            key = line.split(":", 1)[0]
+            if ":" in line and key in ("kernel", "traffic_bytes_per_launch", "kernel_source_sha256"):
+                fields[key] = line.split(":", 1)[1].strip()
+        if fields.get("kernel") == kernel and fields.get("kernel_source_sha256") == sha:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(M: int):

@@ -13,6 +13,8 @@
 // it returns is C transposed: each lane then holds four *columns* of one row,
 // and lanes 0..15 cover 16 consecutive rows, which makes the stores to
 // column-major C contiguous.
+#include <hip/hip_ext.h>
+
 #include "phx_common.h"
 #include "phx_internal.h"
 
@@ -435,6 +437,14 @@ __global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
   }
 }
 
+// One launch of kernel K on grid G with the arguments g; with g.ev0 set, the launch
+// records g.ev0 / g.ev1 at the kernel's start and end.
+#define PHX_LAUNCH(K, G)                                                          \
+  do {                                                                            \
+    if (g.ev0) hipExtLaunchKernelGGL(K, G, dim3(256), 0, st, g.ev0, g.ev1, 0, g); \
+    else hipLaunchKernelGGL(K, G, dim3(256), 0, st, g);                          \
+  } while (0)
+
 template <typename R>
 int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   GemmArgs<R> g = g0;
@@ -447,15 +457,16 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.K <= 0) {  // C = beta C
     g.ksplit = 1;
   }
+  if (g.ksplit > 1) g.ev0 = g.ev1 = nullptr;  // two kernels: no single-kernel timing
   // Tall-skinny updates (the eigensolver's basis times a small coefficient matrix).
   if (opa == 0 && opb == 0 && !g.tri && !g.op && !g.amap && g.ksplit == 1 && g.K <= 64 && g.N <= 64 &&
       (g.M >= 256 || g.csplit > 0) &&
       g.alpha.x == 1 && g.alpha.y == 0 && g.beta.x == 0 && g.beta.y == 0) {
     dim3 grid2((unsigned)((g.M + 64 * 4 - 1) / (64 * 4)), (unsigned)g.batch);
-    if (g.N <= 16) hipLaunchKernelGGL((skinny_kernel<R, 1, 4>), grid2, dim3(256), 0, st, g);
-    else if (g.N <= 32) hipLaunchKernelGGL((skinny_kernel<R, 2, 4>), grid2, dim3(256), 0, st, g);
-    else if (g.N <= 48) hipLaunchKernelGGL((skinny_kernel<R, 3, 4>), grid2, dim3(256), 0, st, g);
-    else hipLaunchKernelGGL((skinny_kernel<R, 4, 4>), grid2, dim3(256), 0, st, g);
+    if (g.N <= 16) PHX_LAUNCH((skinny_kernel<R, 1, 4>), grid2);
+    else if (g.N <= 32) PHX_LAUNCH((skinny_kernel<R, 2, 4>), grid2);
+    else if (g.N <= 48) PHX_LAUNCH((skinny_kernel<R, 3, 4>), grid2);
+    else PHX_LAUNCH((skinny_kernel<R, 4, 4>), grid2);
     return (int)hipGetLastError();
   }
   if (g.csplit > 0) return (int)hipErrorInvalidValue;  // split output only in the tall-skinny kernel
@@ -466,11 +477,11 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     constexpr int X = 1;
     dim3 grid2((unsigned)((g.M + 64 * X - 1) / (64 * X)), (unsigned)g.batch);
     if (opa == 0) {
-      if (g.N <= 16) hipLaunchKernelGGL((nrhs_kernel<R, 0, 1, X>), grid2, dim3(256), 0, st, g);
-      else hipLaunchKernelGGL((nrhs_kernel<R, 0, 2, X>), grid2, dim3(256), 0, st, g);
+      if (g.N <= 16) PHX_LAUNCH((nrhs_kernel<R, 0, 1, X>), grid2);
+      else PHX_LAUNCH((nrhs_kernel<R, 0, 2, X>), grid2);
     } else {
-      if (g.N <= 16) hipLaunchKernelGGL((nrhs_kernel<R, 1, 1, X>), grid2, dim3(256), 0, st, g);
-      else hipLaunchKernelGGL((nrhs_kernel<R, 1, 2, X>), grid2, dim3(256), 0, st, g);
+      if (g.N <= 16) PHX_LAUNCH((nrhs_kernel<R, 1, 1, X>), grid2);
+      else PHX_LAUNCH((nrhs_kernel<R, 1, 2, X>), grid2);
     }
     return (int)hipGetLastError();
   }
@@ -483,21 +494,21 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.tri) ntiles = tm * (tm + 1) / 2;
   else ntiles = tm * tn;
   dim3 grid((unsigned)ntiles, (unsigned)g.batch, (unsigned)g.ksplit);
-#define PHX_GEMM_LAUNCH(BMv, BNv, T)                                                                     \
-  do {                                                                                                    \
-    if (opa == 0 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 0, 0, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
-    else if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
-    else if (opa == 1 && opb == 0) hipLaunchKernelGGL((zgemm_kernel<R, 1, 0, BMv, BNv, T>), grid, dim3(256), 0, st, g); \
-    else hipLaunchKernelGGL((zgemm_kernel<R, 1, 1, BMv, BNv, T>), grid, dim3(256), 0, st, g);             \
+#define PHX_GEMM_LAUNCH(BMv, BNv, T)                                      \
+  do {                                                                     \
+    if (opa == 0 && opb == 0) PHX_LAUNCH((zgemm_kernel<R, 0, 0, BMv, BNv, T>), grid); \
+    else if (opa == 0 && opb == 1) PHX_LAUNCH((zgemm_kernel<R, 0, 1, BMv, BNv, T>), grid); \
+    else if (opa == 1 && opb == 0) PHX_LAUNCH((zgemm_kernel<R, 1, 0, BMv, BNv, T>), grid); \
+    else PHX_LAUNCH((zgemm_kernel<R, 1, 1, BMv, BNv, T>), grid);            \
   } while (0)
   // The lower-triangular tile grid (Hermitian rank-k update of the Cholesky trailing
   // matrix) and the k-shared operator products are their own instantiations.
   if (g.tri) {
-    if (opa == 0 && opb == 1) hipLaunchKernelGGL((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid, dim3(256), 0, st, g);
+    if (opa == 0 && opb == 1) PHX_LAUNCH((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid);
     else return (int)hipErrorInvalidValue;
   } else if (g.op) {
     if (opa != 0 || opb != 0) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((zgemm_kernel<R, 0, 0, 64, 64, 2>), grid, dim3(256), 0, st, g);
+    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 2>), grid);
   } else if (narrow) {
     PHX_GEMM_LAUNCH(128, 32, 0);
   } else {
@@ -593,6 +604,8 @@ template int potrf_diag<float>(float2*, long, long, int, int, float2*, long, int
   if (hook) hook->begin(hook->user, (c))
 #define PHX_HOOK_END(c, f, b) \
   if (hook) hook->end(hook->user, (c), (f), (b))
+#define PHX_HOOK_KEV(c, f, b, g) \
+  if (hook && hook->kev) hook->kev(hook->user, (c), (f), (b), &(g).ev0, &(g).ev1)
 
 // Two-level blocking: 64-wide panels inside 256-wide column blocks.  Inside a
 // column block each panel updates only the block's remaining columns; the rest of
@@ -651,11 +664,10 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
       g.B = blk; g.ldb = lda; g.sB = sA;
       g.Cm = A + (J + w) + (long)(J + w) * lda; g.ldc = lda; g.sC = sA;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      PHX_HOOK_BEGIN(PROF_HERK);
-      const int e = zgemm<R>(g, 0, 1, st);
       // algorithmic: rank-w update of the lower triangle (rem2(rem2+1)/2 entries), read+write once
-      PHX_HOOK_END(PROF_HERK, batch * 8.0 * w * (double)rem2 * (rem2 + 1) / 2.0,
-                   batch * cb * ((double)rem2 * (rem2 + 1) + (double)rem2 * w));
+      PHX_HOOK_KEV(PROF_HERK, batch * 8.0 * w * (double)rem2 * (rem2 + 1) / 2.0,
+                   batch * cb * ((double)rem2 * (rem2 + 1) + (double)rem2 * w), g);
+      const int e = zgemm<R>(g, 0, 1, st);
       if (e) return e;
     }
   }
@@ -831,11 +843,12 @@ template int sb_inverse_batched<float>(const float2*, int, long, long, int, cons
 template <typename R>
 int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* SBinv, C_t<R>* B, long ldb,
                 long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st, const ProfHook* hook,
-                const int* kact, const int* fmap) {
+                const int* kact, const int* fmap, int nacc) {
   constexpr int WS = sizeof(R) == 4 ? 256 : 128;
   const double cb = (double)sizeof(C_t<R>);
   const int nsb = (n + WS - 1) / WS;
   const long sI = (long)nsb * WS * WS;
+  const double na = nacc > 0 ? nacc : batch;  // right-hand-side blocks counted as work
   int e;
   for (int sbi = 0; sbi < nsb; ++sbi) {  // forward: L Z = B
     const int J0 = sbi * WS, w = std::min(WS, n - J0);
@@ -846,9 +859,8 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z + J0; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      PHX_HOOK_KEV(PROF_SOLVE_FWD, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
       e = zgemm<R>(g, 0, 0, st);
-      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
       if (e) return e;
     }
     const int rem = n - J0 - w;
@@ -859,9 +871,8 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      PHX_HOOK_KEV(PROF_SOLVE_FWD, na * 8.0 * rem * w * nc, na * cb * ((double)rem * w + 2.0 * rem * nc), g);
       e = zgemm<R>(g, 0, 0, st);
-      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * rem * w * nc, batch * cb * ((double)rem * w + 2.0 * rem * nc));
       if (e) return e;
     }
   }
@@ -874,9 +885,8 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
+      PHX_HOOK_KEV(PROF_SOLVE_BWD, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
       e = zgemm<R>(g, 1, 0, st);
-      PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
       if (e) return e;
     }
     if (J0 > 0) {
@@ -886,9 +896,8 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      PHX_HOOK_BEGIN(PROF_TRSM_UPDATE);
+      PHX_HOOK_KEV(PROF_SOLVE_BWD, na * 8.0 * J0 * w * nc, na * cb * ((double)J0 * w + 2.0 * J0 * nc), g);
       e = zgemm<R>(g, 1, 0, st);
-      PHX_HOOK_END(PROF_TRSM_UPDATE, batch * 8.0 * J0 * w * nc, batch * cb * ((double)J0 * w + 2.0 * J0 * nc));
       if (e) return e;
     }
   }
@@ -955,9 +964,9 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
-                  const ProfHook* hook, const C_t<R>* sbinv, const int* kact, const int* fmap) {
+                  const ProfHook* hook, const C_t<R>* sbinv, const int* kact, const int* fmap, int nacc) {
   if (nc <= 32 && sbinv)
-    return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook, kact, fmap);
+    return potrs_sbinv<R>(L, n, lda, sL, batch, sbinv, B, ldb, sB, Z, ldz, sZ, nc, st, hook, kact, fmap, nacc);
   if (fmap) return (int)hipErrorInvalidValue;  // shared factors only with the super-block inverses
   if (nc <= 32) return potrs_narrow<R>(L, n, lda, sL, batch, Dinv, sD, B, ldb, sB, Z, ldz, sZ, nc, st, hook);
   const int T = n / 64;
@@ -1021,9 +1030,9 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
 }
 template int potrs_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*, long,
                                    long, double2*, long, long, int, hipStream_t, const ProfHook*, const double2*,
-                                   const int*, const int*);
+                                   const int*, const int*, int);
 template int potrs_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*, long,
                                   long, float2*, long, long, int, hipStream_t, const ProfHook*, const float2*,
-                                  const int*, const int*);
+                                  const int*, const int*, int);
 
 }  // namespace phx

@@ -27,6 +27,7 @@ struct GemmArgs {
   C_t<R>* Cpart;
   int csplit, cgap;  // tall-skinny only: output column j >= csplit (if > 0) is stored at j + cgap
   const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
+  hipEvent_t ev0, ev1;  // optional: recorded at the start and the end of the (single) kernel's execution
 };
 
 template <typename R>
@@ -39,11 +40,18 @@ enum ProfClass {
   PROF_HERK,
   PROF_TRSM_DIAG,
   PROF_TRSM_UPDATE,
+  PROF_SOLVE_FWD,  // forward steps of the super-block solves (one kernel)
+  PROF_SOLVE_BWD,  // backward steps of the super-block solves (one kernel)
+  PROF_SBINV,      // inverses of the factor's diagonal super-blocks
   PROF_NCLASS_DENSE
 };
+// begin/end: events recorded on the stream around a group of launches.  kev: two events
+// for one kernel launch to record at its start and end (hipExtLaunchKernelGGL), with the
+// launch's algorithmic work; null events when timing is off.
 struct ProfHook {
   void (*begin)(void* user, int cls);
   void (*end)(void* user, int cls, double flops, double bytes);
+  void (*kev)(void* user, int cls, double flops, double bytes, hipEvent_t* a, hipEvent_t* b);
   void* user;
 };
 
@@ -58,12 +66,13 @@ int potrf_batched(C_t<R>* A, int n, long lda, long sA, int batch, C_t<R>* Dinv, 
 // sbinv (may be NULL): inverses of the diagonal super-blocks from sb_inverse_batched;
 // given, narrow solves (nc <= 32) run as GEMMs only, skipping the matrices whose kact
 // entry is 0 (kact may be NULL), and right-hand side b uses factor fmap[b] (device
-// array; NULL: factor b; non-NULL requires sbinv).
+// array; NULL: factor b; non-NULL requires sbinv).  nacc (> 0): the number of
+// right-hand-side blocks the timing hook counts as work (the active ones).
 template <typename R>
 int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                   C_t<R>* B, long ldb, long sB, C_t<R>* Z, long ldz, long sZ, int nc, hipStream_t st,
                   const ProfHook* hook = nullptr, const C_t<R>* sbinv = nullptr, const int* kact = nullptr,
-                  const int* fmap = nullptr);
+                  const int* fmap = nullptr, int nacc = 0);
 
 // Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
 // Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS).

@@ -77,8 +77,16 @@ enum RtClass {
   PROF_ADJOINT,
   PROF_NCLASS
 };
-const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "assemble",
-                                             "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"};
+const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",    "herk",  "trsm_diag", "trsm_update",
+                                             "solve_fwd",  "solve_bwd", "sbinv", "assemble",  "apply",
+                                             "op_gemm",    "gram",      "small", "update",    "residual",
+                                             "adjoint"};
+
+struct PendKernel {
+  int cls;
+  double flops, bytes;
+  bool set;
+};
 
 struct ProfAcc {
   double ms = 0, flops = 0, bytes = 0;
@@ -111,6 +119,17 @@ struct Profiler {
     if (!on) return;
     open = get();
     if (open) (void)hipEventRecord(open, st);
+  }
+  // Two events for one kernel launch to record at the kernel's start and end; the
+  // measurement is registered now and read at the next flush.
+  void kernel_events(int cls, double flops, double bytes, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (!on) return;
+    hipEvent_t e0 = get(), e1 = get();
+    if (!e0 || !e1) return;
+    pend.push_back({cls, e0, e1, flops, bytes});
+    *a = e0;
+    *b = e1;
   }
   void end(int cls, double flops, double bytes) {
     if (!on || !open) return;
@@ -149,6 +168,9 @@ struct Profiler {
 
 void hook_begin(void* u, int cls) { ((Profiler*)u)->begin(cls); }
 void hook_end(void* u, int cls, double f, double b) { ((Profiler*)u)->end(cls, f, b); }
+void hook_kev(void* u, int cls, double f, double b, hipEvent_t* e0, hipEvent_t* e1) {
+  ((Profiler*)u)->kernel_events(cls, f, b, e0, e1);
+}
 
 }  // namespace
 
@@ -163,8 +185,9 @@ struct phx_ctx {
   Stats stats;
   bool trace = false;
   Profiler prof;
+  PendKernel pk{0, 0, 0, false};  // timing request for the next GEMM launch
   std::vector<phx_ctx*> workers;  // contexts (own stream and workspaces) of the batched call
-  phx::ProfHook hook{hook_begin, hook_end, nullptr};
+  phx::ProfHook hook{hook_begin, hook_end, hook_kev, nullptr};
   const phx::ProfHook* hk() {
     hook.user = &prof;
     prof.st = stream;
@@ -174,6 +197,8 @@ struct phx_ctx {
 
 #define PROF_BEGIN(c) ctx->prof.begin(c)
 #define PROF_END(c, f, b) ctx->prof.end((c), (f), (b))
+// The next GEMM launch on ctx is timed by events recorded at its kernel's start and end.
+#define PROF_KERNEL(c, f, b) ctx->pk = PendKernel{(c), (f), (b), true}
 
 namespace {
 
@@ -434,6 +459,7 @@ struct Solver {
   void* SBinv; // nk x nsb x WS^2 inverses of the factor's diagonal super-blocks, or NULL
   int* kact;   // per k: 1 while a wanted band of that k-point has not met the tolerance
   int* fmap;   // per k: index of its preconditioner factor (NULL: its own)
+  int nact;    // active k-points (host count of kact)
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -445,6 +471,10 @@ void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const 
           int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1,
           int csplit = 0, int cgap = 0) {
   GemmArgs<R> g{};
+  if (ctx->pk.set) {
+    ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &g.ev0, &g.ev1);
+    ctx->pk.set = false;
+  }
   g.csplit = csplit;
   g.cgap = cgap;
   g.op = op;
@@ -471,7 +501,7 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   hipStream_t st = ctx->stream;
   const long n3 = sv.n3, m = sv.m;
   double2* X = Big + c0 * n3;
-  const double Np = d.Np, nk = sv.nk;
+  const double Np = d.Np, nk = sv.nact;  // algorithmic work counts the active k-points only
   PROF_BEGIN(PROF_APPLY);
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, sv.kact);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
@@ -484,23 +514,20 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   // computed from their last strains and not used).
   const int ny = 6 * ncol, nt = ncol * sv.nk;
   const long sy = (long)d.Np * ny;
-  PROF_BEGIN(PROF_OP_GEMM);
+  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * ny * nk, 16.0 * (Np * Np + 2.0 * Np * ny * nk));
   gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
                nullptr, 1, sv.kact, 1);
-  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * ny * nk, 16.0 * (Np * Np + 2.0 * Np * ny * nk));
-  PROF_BEGIN(PROF_OP_GEMM);
+  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
   gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
                nullptr, 1);
-  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
   PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, sv.kact);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
-  PROF_BEGIN(PROF_OP_GEMM);
+  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
   gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
                Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1, sv.kact, 1);
-  PROF_END(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
 }
 
 void gram(Solver& sv, double2* Big, int block) {
@@ -510,7 +537,7 @@ void gram(Solver& sv, double2* Big, int block) {
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
                m * m, ONE, ZERO, sv.ksplit, sv.Gpart, 0, sv.kact, 1);
-  PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nk, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nk);
+  PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nact, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nact);
 }
 
 void cholqr(Solver& sv) {
@@ -526,7 +553,7 @@ void cholqr(Solver& sv) {
   gemm<double>(ctx, 0, 0, n3, m, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.C0, m, m * m, 3, sv.Big2, n3, n3 * m, ONE,
                ZERO, 1, nullptr, 0, sv.kact, 3);
   launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nk, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nk);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nact, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nact);
   std::swap(sv.Big, sv.Big2);
 }
 
@@ -545,8 +572,8 @@ void rayleigh_ritz(Solver& sv) {
   gemm<double>(ctx, 0, 0, n3, s, m - s, 3 * sv.nk, sv.Big + s * n3, n3, n3 * m, 1, sv.Cr + s, m, m * s, 3,
                sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3);
   launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nk,
-           16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nact,
+           16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
   std::swap(sv.Big, sv.Big2);
 }
 
@@ -560,7 +587,7 @@ void rayleigh_ritz_fused(Solver& sv) {
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
                2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, sv.kact, 1);
-  PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nk, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nk);
+  PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nact, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nact);
   PROF_BEGIN(PROF_SMALL);
   // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
   // the basis produces both: columns 0..s-1 -> X, s..2s-1 -> P (basis columns 2s..3s-1)
@@ -572,7 +599,7 @@ void rayleigh_ritz_fused(Solver& sv) {
   gemm<double>(ctx, 0, 0, n3, 2 * s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, 2 * m * s, 3, sv.Big2, n3, n3 * m,
                ONE, ZERO, 1, nullptr, 0, sv.kact, 3, (int)s, (int)s);
   launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nk, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nk);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nact, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
   std::swap(sv.Big, sv.Big2);
 }
 
@@ -582,7 +609,7 @@ void precondition(Solver& sv) {
   const long n3 = sv.n3;
   KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
                         (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk(),
-                        (const C_t<R>*)sv.SBinv, sv.kact, sv.fmap));
+                        (const C_t<R>*)sv.SBinv, sv.kact, sv.fmap, sv.nact));
   launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
                   sv.kact);
   KCHK(hipGetLastError());
@@ -730,10 +757,10 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     constexpr int WS = sizeof(R) == 4 ? 256 : 128;
     const long nsb = (n3 + WS - 1) / WS;
     sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nkf * nsb * WS * WS);
-    PROF_BEGIN(PROF_TRSM_DIAG);
+    PROF_BEGIN(PROF_SBINV);
     KCHK(sb_inverse_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
                                (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, st));
-    PROF_END(PROF_TRSM_DIAG, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
+    PROF_END(PROF_SBINV, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
   }
 
   // Per-k activity: every k-point starts active; one whose wanted bands all meet the
@@ -741,6 +768,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   // and the remaining iterations skip it.
   std::vector<int> act_h(nk, 1);
   HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  sv.nact = nk;
 
   // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
@@ -785,7 +813,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
                        sv.rn, sv.rnorm, st, sv.kact);
-    PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * nk + (double)sizeof(C_t<R>) * 3.0 * d.N * s * nk);
+    PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * sv.nact + (double)sizeof(C_t<R>) * 3.0 * d.N * s * sv.nact);
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(sw_h.data(), sv.sweeps, sw_h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -811,8 +839,10 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       }
       worst = std::max(worst, wk);
     }
-    if (ctx->opt.kskip && worst > tol)
+    if (ctx->opt.kskip && worst > tol) {
       HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+      sv.nact = (int)std::count(act_h.begin(), act_h.end(), 1);
+    }
     if (ctx->trace) {
       std::vector<int> kh((size_t)nk * m);
       std::vector<double> th((size_t)nk * s);

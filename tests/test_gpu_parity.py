@@ -439,3 +439,20 @@ def test_small_rr_generalised(ctx, m, s, ndep):
         D = S[b] @ (Cx[b] - Cp[b])
         coef, *_ = np.linalg.lstsq(S[b][:, :s], D, rcond=None)
         assert np.abs(S[b][:, :s] @ coef - D).max() < 1e-9 * max(np.abs(D).max(), 1.0)
+
+
+def test_kernel_class_timing(ctx):
+    """The single-kernel timing classes (each launch records events at its kernel's start
+    and end) see every launch, with positive durations and work."""
+    wl = synth.config2()
+    cell, rho = wl.cells[0], wl.designs[0]
+    q = phx.kpath(cell.lattice, wl.nk, wl.path)
+    ctx.set_option("profile_reset", 1)
+    ctx.set_option("profile", 1)
+    ctx.bands(cell, rho, q, wl.nbands, "mixed")
+    ctx.set_option("profile", 0)
+    for c in ("herk", "op_gemm", "solve_fwd", "solve_bwd"):
+        n, ms = ctx.stat(f"prof.{c}.count"), ctx.stat(f"prof.{c}.ms")
+        fl, by = ctx.stat(f"prof.{c}.flops"), ctx.stat(f"prof.{c}.bytes")
+        log(c, n, ms, fl, by)
+        assert n > 0 and ms > 0 and fl > 0 and by > 0
