@@ -36,7 +36,7 @@ def main():
     ap.add_argument("--nk", type=int, default=60)
     ap.add_argument("--M", type=int, default=5)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--streams", type=int, default=8, help="designs solved concurrently (library option)")
+    ap.add_argument("--streams", type=int, default=16, help="designs solved concurrently (library option)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="library option coarse_tol")
     ap.add_argument("--shift", type=float, default=None, help="library option shift")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
@@ -207,23 +207,36 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def kernel_source_sha(kernel: str):
+    """SHA-256 of the text of the template definition of `kernel` ("phx::name<...>") in the
+    HIP sources, or None."""
+    import glob
+    import hashlib
+    base = kernel.split("<")[0].split("::")[-1]
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "*.hip"))):
+        src = open(path).read()
+        i = src.find(f" void {base}(")
+        if i < 0:
+            continue
+        start = src.rfind("template <", 0, i)
+        end = src.index("\n}\n", i) + 3
+        return hashlib.sha256(src[start:end].encode()).hexdigest()
+    return None
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summaries (profiles/*_traffic.md, one per kernel), or None when there is none or the
-    kernel's source text (the GEMM kernel template's definition) changed since it was taken."""
+    kernel's source text (its template's definition) changed since the counters were taken."""
     import glob
-    import hashlib
-    src = open(os.path.join(ROOT, "paper_1603_06855_amd", "csrc", "dense.hip")).read()
-    start = src.index("template <typename R, int OPA, int OPB, int BM, int BN, int MODE>")
-    end = src.index("\n}\n", start) + 3  # the kernel's definition
-    sha = hashlib.sha256(src[start:end].encode()).hexdigest()
+    sha = kernel_source_sha(kernel)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
         fields = {}
         for line in open(path):
             key = line.split(":", 1)[0]
             if ":" in line and key in ("kernel", "traffic_bytes_per_launch", "kernel_source_sha256"):
                 fields[key] = line.split(":", 1)[1].strip()
-        if fields.get("kernel") == kernel and fields.get("kernel_source_sha256") == sha:
+        if fields.get("kernel") == kernel and sha and fields.get("kernel_source_sha256") == sha:
             return float(fields["traffic_bytes_per_launch"])
     return None
 

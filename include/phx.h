@@ -106,7 +106,7 @@ const char* phx_last_error(const phx_ctx* ctx);
  * in the last iterations of a solve whose residual is below 1e-13/tolerance; 0:
  * always two explicit orthonormalisations of the basis before Rayleigh-Ritz),
  * "mem_gb" (device memory budget for one k-chunk, default 64; per worker
- * context of phx_sens_batch_dev), "streams" (1..8, see phx_sens_batch_dev),
+ * context of phx_sens_batch_dev), "streams" (1..16, see phx_sens_batch_dev),
  * "coarse" (1:
  * for M >= 4 every k-chunk is first solved at order M-2 to the residual
  * "coarse_tol", default 1e-3, and its Ritz vectors, embedded in the order-M
@@ -213,7 +213,10 @@ int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int 
  * are device arrays.  The designs are spread over up to "streams" (option,
  * default 4) worker contexts, each with its own HIP stream and workspaces, so
  * the latency-bound steps of one design overlap the matrix-core work of
- * another; the highest M goes first.  Statistics and kernel-class timers of
+ * another; the highest M goes first.  HIP maps streams onto GPU_MAX_HW_QUEUES
+ * hardware queues (environment, read when the HIP runtime starts; 4 by
+ * default): streams sharing a queue run their kernels in turn, so set it to at
+ * least "streams".  Statistics and kernel-class timers of
  * the workers are merged into ctx.  Returns the first error (naming the
  * design), else PHX_ENOCONV if any design did not converge. */
 int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const double* const* rho_dev, int nk,

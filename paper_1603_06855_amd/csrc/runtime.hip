@@ -1075,7 +1075,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
   else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
-  else if (k == "streams") { if (!(v >= 1 && v <= 8)) return bad(); ctx->opt.streams = (int)v; }
+  else if (k == "streams") { if (!(v >= 1 && v <= 16)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
   else if (k == "kskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.kskip = (int)v; }
