@@ -87,16 +87,20 @@ const char* phx_last_error(const phx_ctx* ctx);
  * converged; defaults 1e-8 and 1e-6), "maxit" (default 60), "block" (search
  * block size s, 0 = automatic, else nbands < s <= 21), "shift" (preconditioner
  * shift relative to the lowest shear-wave eigenvalue scale, default 0.02),
+ * "drop" (Omega-orthonormalisation drops a search column whose orthogonal part
+ * has squared norm below drop times its own, default 1e-8),
  * "sbinv" (1, default: the preconditioner's triangular solves use explicit
  * inverses of the factor's 256-wide (FP64: 128-wide) diagonal blocks, computed
  * once per factorisation, so every solve step is a matrix product; 0: blocked
  * substitution inside each diagonal block),
- * "kshare" (1..8, default 4), "kshare_dist" (default 0.5) and "kshare_rel"
+ * "kshare" (1..8, default 2), "kshare_dist" (default 0.15) and "kshare_rel"
  * (default 0.5): consecutive k-points of a chunk that lie within kshare_dist
  * (Cartesian, cycles per a) of a group's first k-point, and within kshare_rel
  * times the shorter of the two wave vectors, share that k-point's
  * preconditioner factor, at most kshare of them (needs "sbinv"; 1: every
- * k-point has its own factor; Gamma never shares),
+ * k-point has its own factor; Gamma never shares).  Wider sharing (e.g. 4
+ * within 0.5) saves factorisations on smooth designs but costs iterations on
+ * sharp high-contrast inclusions,
  * "kskip" (1, default: a k-point whose wanted bands all meet the tolerance is
  * frozen, its vectors, eigenvalues and residuals kept, and the remaining
  * iterations of its chunk skip it; 0: every k-point of a chunk iterates until the

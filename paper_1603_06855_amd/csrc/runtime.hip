@@ -44,7 +44,12 @@ struct Opts {
   int maxit = 60;
   int block = 0;
   double shift = 0.02;
-  double drop = 1e-12;
+  // Omega-CholQR drops a column whose squared orthogonal part falls below drop times its
+  // squared norm: kept columns are amplified by at most drop^-1/2 = 1e4, so the rounding
+  // carried by the basis and its K / Omega images stays far below the FP64 tolerances
+  // (with 1e-12, 1e6-fold amplification let the images of nearly dependent columns
+  // drift until the iteration diverged on sharp high-contrast inclusions).
+  double drop = 1e-8;
   double mem_gb = 64.0;
   int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
@@ -52,8 +57,8 @@ struct Opts {
   int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
   int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
   int kskip = 1;             // 1: k-points whose wanted bands have converged skip later iterations
-  int kshare = 4;            // at most this many consecutive k-points share one preconditioner factor
-  double kshare_dist = 0.5;  // ... if within this Cartesian distance (cycles per a) of the group's first
+  int kshare = 2;            // at most this many consecutive k-points share one preconditioner factor
+  double kshare_dist = 0.15; // ... if within this Cartesian distance (cycles per a) of the group's first
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
 };
 

@@ -1,0 +1,83 @@
+"""GPU: the studies of Results, "A note on normalized band gaps", through the C ABI.
+
+* A two-layer laminate (SC cell, 9 voxels, layers normal to a1, 4/9 of the stiff phase), k
+  along the stacking axis: the two degenerate shear branches and the longitudinal branch of
+  the HIP path against the exact transfer-matrix (Rytov) dispersion.  Loose semi-analytic
+  pin: the centroid rule samples the step profile on 9 voxels and the expansion truncates it,
+  so agreement is to 1e-3 at low and a few 1e-3 at higher frequency.
+* The sphere-inclusion sweep on a small case against the oracle (the same designs, the
+  same band edges, Eq. (10)).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1603_06855_amd import phx, studies, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = phx.Context(0)
+    c.set_option("tol_fp64", 1e-10)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("M", [3, 4])
+def test_laminate_branches_match_rytov(ctx, M):
+    m0 = synth.Material(1000.0, 2e9, 0.3)
+    m1 = synth.Material(3000.0, 12e9, 0.25)
+    nv = 9
+    rho = np.zeros((nv, nv, nv))
+    rho[:4, :, :] = 1.0
+    cell = synth.Cell("SC", 1.0, nv, M, m0, m1, 1.0)
+    qs = np.array([[0.1, 0, 0], [0.25, 0, 0], [0.4, 0, 0]])
+    om = ctx.bands(cell, rho, qs, 3, "fp64")
+    # the truncation of the step profile's expansion costs more at higher frequency
+    bar = {0.1: 1e-3, 0.25: 2.5e-3, 0.4: 6e-3}
+    for i, q in enumerate(qs[:, 0]):
+        s = studies.rytov_omega(2 * math.pi * q, m1, m0, 4 / 9, "S", 1)[0]
+        p = studies.rytov_omega(2 * math.pi * q, m1, m0, 4 / 9, "P", 1)[0]
+        assert om[i, 1] == pytest.approx(om[i, 0], rel=1e-8)  # the two shear polarisations
+        es, ep = abs(om[i, 0] - s) / s, abs(om[i, 2] - p) / p
+        log("M", M, "q", q, "shear", es, "longitudinal", ep)
+        assert max(es, ep) < bar[q]
+
+
+def test_sphere_sweep_matches_oracle(ctx):
+    from oracle import geometry, objective, solve
+    nv, M, nk = 12, 2, 12
+    cell = synth.Cell("SC", 1.0, nv, M, synth.EPOXY_PAPER, synth.WC_PAPER, 1.0)
+    res = studies.sphere_sweep(ctx, "SC", (0.3, 0.5), nv=nv, M=M, nk=nk, precision="fp64")
+    Q = geometry.kpath("SC", nk)
+    for r in res:
+        rho = synth.sphere(nv, "SC", studies.sphere_radius("SC", r["fraction"]))
+        assert rho.mean() == pytest.approx(r["voxel_fraction"])
+        om = solve.bands(cell, rho, Q, 8)
+        g = objective.gap(om, 6)
+        log("fraction", r["fraction"], "gap HIP", r["gap"], "oracle", g)
+        assert r["gap"] == pytest.approx(g, rel=1e-8, abs=1e-10)
+
+
+@pytest.mark.parametrize("lat,fracs", [("SC", (0.40, 0.45)), ("BCC", (0.50, 0.55)), ("FCC", (0.55, 0.60))])
+def test_sphere_gaps_near_the_printed_maxima(ctx, lat, fracs):
+    """Loose comparison with the paper's printed maxima (67.5 %, 94.2 %, 93.3 % at volume
+    fractions 0.412, 0.545, 0.588; order and mesh not stated): at 32^3, M=3, 40 k-points the
+    largest gap over two fractions bracketing the printed one lies within 2.5 points."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "normalized_gap_studies.json")))["spheres_3d"][lat]
+    res = studies.sphere_sweep(ctx, lat, fracs, nv=32, M=3, nk=40, precision="mixed")
+    best = max(r["gap"] for r in res)
+    log(lat, [(round(r["voxel_fraction"], 3), round(100 * r["gap"], 2)) for r in res], "paper", ref)
+    assert abs(100 * best - ref["gap_percent"]) < 2.5
