@@ -81,3 +81,17 @@ def test_sphere_gaps_near_the_printed_maxima(ctx, lat, fracs):
     best = max(r["gap"] for r in res)
     log(lat, [(round(r["voxel_fraction"], 3), round(100 * r["gap"], 2)) for r in res], "paper", ref)
     assert abs(100 * best - ref["gap_percent"]) < 2.5
+
+
+def test_band_frequencies_converge_in_the_order(ctx):
+    """A smooth FCC design (32^3, seeded box-smoothed field), orders 2..5: the gap of
+    Eq. (10) forms a Cauchy sequence (each step smaller than the one before) and the band
+    frequencies move by less than 1e-3 (root mean square) from one order to the next."""
+    rho = synth.box_smoothed_uniform(32, 502)
+    res = studies.m_convergence(ctx, "FCC", rho, (2, 3, 4, 5), nk=20)
+    g = [r["gap"] for r in res]
+    steps = [abs(b - a) for a, b in zip(g[:-1], g[1:])]
+    log("orders 2..5: gaps", g, "steps", steps, "rms changes", [r["rms_rel_change"] for r in res[1:]],
+        "max changes", [r["max_rel_change"] for r in res[1:]])
+    assert steps[0] > steps[1] > steps[2]
+    assert max(r["rms_rel_change"] for r in res[1:]) < 1e-3

@@ -50,3 +50,14 @@ def test_short_optimisation_rises_and_resumes(tmp_path):
     assert np.allclose(c.hist.ks_gap, h.ks_gap, rtol=1e-10, atol=0)
     assert float((c.x - a.x).abs().max()) <= 1e-9
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_command_line_run_reports_the_final_higher_order_gap(capsys):
+    """The driver's summary line carries the final design's gap re-evaluated one order up."""
+    import json
+    optimize.main(["--lattice", "SC", "--nv", "12", "--M", "2", "--nk", "12", "--iters", "2", "--precision", "fp64"])
+    lines = [json.loads(l) for l in capsys.readouterr().out.splitlines() if l.startswith("{")]
+    summary = lines[-1]
+    assert summary["iters"] == 2 and summary["final_M"] == 3
+    assert summary["gap_final_M"] is not None and abs(summary["gap_final_M"] - summary["gap_last"]) < 0.2
