@@ -272,6 +272,43 @@ int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const 
 int phx_small_rr(phx_ctx* ctx, int m, int s, int batch, const double* G2, double drop, double* Cx, double* Cp,
                  double* theta, int* keep);
 
+/* ------------------------------------------------------------ design projection */
+
+/* The design parameterisation of the topology optimisation (section "Topology
+ * optimization formulation": the Heaviside projection method with a reduced design
+ * variable field and continuation on the Heaviside parameter; section "Study of cubic
+ * unit cells": the SC design optimised on one eighth of the cell, mirrored about the
+ * cell's mid-planes).  Elements are the nv^3 voxels (centroids at i + 1/2 element
+ * widths along each primitive axis).  Design nodes sit every `spacing` elements, node j
+ * at the centre of elements spacing*j .. spacing*j + spacing - 1; nn = nv / spacing per
+ * axis.  With `octant` the design array holds nodes j < nn/2 per axis and node j >= nn/2
+ * takes the value of node nn - 1 - j.  Per element, with w_en = max(0, radius - |x_e -
+ * x_n|) (periodic minimum image, element widths, index space):
+ *   mu_e  = sum_n w_en x_n / sum_n w_en,
+ *   rho_e = 1 - exp(-beta mu_e) + mu_e exp(-beta)          (beta = 0: rho = mu).   */
+typedef struct {
+  int nv;        /* elements per primitive axis */
+  int spacing;   /* 1 or 2 elements between design nodes; nv % spacing == 0 */
+  double radius; /* projection radius in element widths: > sqrt(3)/2 for spacing 2,
+                    > 0 for spacing 1, and 2 radius + spacing < nv */
+  double beta;   /* Heaviside parameter, 0 <= beta <= 1000 */
+  int octant;    /* 1: mirrored octant design (nn even) */
+} phx_projection;
+
+/* Number of design variables: nn^3, or (nn/2)^3 with the octant.  Host only. */
+int phx_projection_size(const phx_projection* p, long* ndesign);
+/* rho (nv^3, C order [i1][i2][i3]) from the design variables x (C order over the design
+ * nodes).  Host arrays (copied in and out) or device arrays (the _dev form, ordered after
+ * the caller's `stream`, complete on return).  PHX_EINVAL for an invalid projection. */
+int phx_project(phx_ctx* ctx, const phx_projection* p, const double* x, double* rho);
+int phx_project_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, double* rho_dev, void* stream);
+/* grad_x = (d rho / d x)^T grad_rho: the backward of phx_project (chain rule through the
+ * Heaviside, the filter and the mirror images). */
+int phx_project_adjoint(phx_ctx* ctx, const phx_projection* p, const double* x, const double* grad_rho,
+                        double* grad_x);
+int phx_project_adjoint_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, const double* grad_rho_dev,
+                            double* grad_x_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

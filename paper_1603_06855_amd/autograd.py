@@ -63,6 +63,28 @@ class BandFrequencies(torch.autograd.Function):
         return grad.reshape(rho.shape).to(rho.dtype), None
 
 
+class DesignProjection(torch.autograd.Function):
+    """rho = the Heaviside projection of the design variables x (``phx_project_dev``); the
+    backward is ``phx_project_adjoint_dev``."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, lib_ctx: "phx.Context", p: "phx.Projection") -> torch.Tensor:
+        if not x.is_cuda:
+            raise ValueError("x must be a device tensor")
+        ctx.save_for_backward(x)
+        ctx.lib_ctx, ctx.p = lib_ctx, p
+        return lib_ctx.project_dev(p, x)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (x,) = ctx.saved_tensors
+        return ctx.lib_ctx.project_adjoint_dev(ctx.p, x, g).to(x.dtype), None, None
+
+
+def project(x: torch.Tensor, lib_ctx: "phx.Context", p: "phx.Projection") -> torch.Tensor:
+    return DesignProjection.apply(x, lib_ctx, p)
+
+
 def band_frequencies(rho: torch.Tensor, prob: Problem) -> torch.Tensor:
     return BandFrequencies.apply(rho, prob)
 

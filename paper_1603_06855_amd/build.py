@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["dense.hip", "physics.hip", "small.hip", "runtime.hip"]
+SOURCES = ["dense.hip", "physics.hip", "small.hip", "design.hip", "runtime.hip"]
 LIB = os.path.join(HERE, "libphx.so")
 
 

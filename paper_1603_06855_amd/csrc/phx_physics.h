@@ -54,6 +54,11 @@ void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rh
                    double c2, const double* lam_nd, double lscale, double* out, hipStream_t st);
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st);
 
+// design.hip: Heaviside projection of a (reduced, optionally octant-mirrored) design field.
+void launch_project(int nv, int sp, double r, double beta, int oct, const double* x, double* rho, hipStream_t st);
+void launch_project_adjoint(int nv, int sp, double r, double beta, int oct, const double* x, const double* grad_rho,
+                            double* coef, double* grad_x, hipStream_t st);
+
 // small.hip: per-k dense kernels on m x m (m <= 64) Gram matrices, FP64.
 void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st,
                       const int* kact = nullptr);

@@ -1679,4 +1679,93 @@ int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, cons
   });
 }
 
+// ------------------------------------------------------------------ design projection
+
+static long check_projection(phx_ctx* ctx, const phx_projection* p) {
+  if (!p) fail(ctx, PHX_EINVAL, "projection is NULL");
+  if (p->nv < 2 || (p->spacing != 1 && p->spacing != 2) || p->nv % p->spacing)
+    fail(ctx, PHX_EINVAL, "nv must be a positive multiple of spacing (1 or 2)");
+  const int nn = p->nv / p->spacing;
+  if (p->octant && nn % 2) fail(ctx, PHX_EINVAL, "the octant needs an even number of design nodes per axis");
+  const double rmin = p->spacing == 2 ? 0.8660254037844387 : 0.0;  // farthest element centroid from a node
+  if (!(p->radius > rmin) || !(2.0 * p->radius + p->spacing < p->nv))
+    fail(ctx, PHX_EINVAL, "radius must reach the nearest design node and stay below half the cell");
+  if (!(p->beta >= 0) || !(p->beta <= 1e3)) fail(ctx, PHX_EINVAL, "beta must lie in [0, 1000]");
+  const long nd = p->octant ? nn / 2 : nn;
+  return nd * nd * nd;
+}
+
+int phx_projection_size(const phx_projection* p, long* ndesign) {
+  if (!p || !ndesign || p->nv < 2 || (p->spacing != 1 && p->spacing != 2) || p->nv % p->spacing) return PHX_EINVAL;
+  const long nn = p->nv / p->spacing;
+  if (p->octant && nn % 2) return PHX_EINVAL;
+  const long nd = p->octant ? nn / 2 : nn;
+  *ndesign = nd * nd * nd;
+  return PHX_OK;
+}
+
+int phx_project_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, double* rho_dev, void* stream) {
+  return guard(ctx, [&]() {
+    check_projection(ctx, p);
+    if (!x_dev || !rho_dev) fail(ctx, PHX_EINVAL, "x_dev or rho_dev is NULL");
+    if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    launch_project(p->nv, p->spacing, p->radius, p->beta, p->octant, x_dev, rho_dev, ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PHX_OK;
+  });
+}
+
+int phx_project_adjoint_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, const double* grad_rho_dev,
+                            double* grad_x_dev, void* stream) {
+  return guard(ctx, [&]() {
+    check_projection(ctx, p);
+    if (!x_dev || !grad_rho_dev || !grad_x_dev) fail(ctx, PHX_EINVAL, "a device pointer is NULL");
+    if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const long ne = (long)p->nv * p->nv * p->nv;
+    double* coef = dbuf<double>(ctx, "proj_coef", ne);
+    launch_project_adjoint(p->nv, p->spacing, p->radius, p->beta, p->octant, x_dev, grad_rho_dev, coef, grad_x_dev,
+                           ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PHX_OK;
+  });
+}
+
+int phx_project(phx_ctx* ctx, const phx_projection* p, const double* x, double* rho) {
+  return guard(ctx, [&]() {
+    const long nx = check_projection(ctx, p);
+    if (!x || !rho) fail(ctx, PHX_EINVAL, "x or rho is NULL");
+    const long ne = (long)p->nv * p->nv * p->nv;
+    double* xd = dbuf<double>(ctx, "proj_x", nx);
+    double* rd = dbuf<double>(ctx, "proj_rho", ne);
+    HIPCHK(hipMemcpyAsync(xd, x, nx * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    launch_project(p->nv, p->spacing, p->radius, p->beta, p->octant, xd, rd, ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(rho, rd, ne * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PHX_OK;
+  });
+}
+
+int phx_project_adjoint(phx_ctx* ctx, const phx_projection* p, const double* x, const double* grad_rho,
+                        double* grad_x) {
+  return guard(ctx, [&]() {
+    const long nx = check_projection(ctx, p);
+    if (!x || !grad_rho || !grad_x) fail(ctx, PHX_EINVAL, "a pointer is NULL");
+    const long ne = (long)p->nv * p->nv * p->nv;
+    double* xd = dbuf<double>(ctx, "proj_x", nx);
+    double* gd = dbuf<double>(ctx, "proj_grho", ne);
+    double* coef = dbuf<double>(ctx, "proj_coef", ne);
+    double* gx = dbuf<double>(ctx, "proj_gx", nx);
+    HIPCHK(hipMemcpyAsync(xd, x, nx * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(gd, grad_rho, ne * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    launch_project_adjoint(p->nv, p->spacing, p->radius, p->beta, p->octant, xd, gd, coef, gx, ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(grad_x, gx, nx * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PHX_OK;
+  });
+}
+
 }  // extern "C"

@@ -12,6 +12,12 @@ voxels with periodic wrap, and the step rho <- clip(rho + eta g / max|g|, 0, 1).
 filter and the step run as PyTorch operations on the device; the band structure and its
 adjoint run in the library.  A run can be check-pointed to an ``.npz`` file (design,
 iteration, history) and resumed from it.
+
+With ``hpm`` the design variables instead live on nodes every `spacing` elements (the
+paper's reduced design field) and the physical density is their Heaviside projection
+(``phx_project_dev``, backward ``phx_project_adjoint_dev``), with continuation on the
+Heaviside parameter from 1; ``octant`` optimises one eighth of the cell, mirrored about
+its mid-planes, as the paper does for SC.
 """
 from __future__ import annotations
 
@@ -52,27 +58,65 @@ class History:
     seconds: List[float] = field(default_factory=list)
 
 
+@dataclass
+class HPM:
+    """The paper's design parameterisation (Methods, "Topology optimization formulation"):
+    Heaviside projection of design variables on nodes every `spacing` elements, projection
+    radius in element widths, continuation on the Heaviside parameter (beta0, doubled every
+    `beta_every` iterations up to beta_max); `octant` optimises one eighth of the cell,
+    mirrored about its mid-planes (the paper's SC setting)."""
+    spacing: int = 2
+    radius: float = 2.8
+    octant: bool = False
+    beta0: float = 1.0
+    beta_max: float = 64.0
+    beta_every: int = 20
+
+    def beta(self, it: int) -> float:
+        return min(self.beta_max, self.beta0 * 2.0 ** (it // self.beta_every))
+
+
 class GapOptimizer:
     def __init__(self, ctx: "phx.Context", cell, q: np.ndarray, nbands: int, t: int, rho0: np.ndarray,
                  precision: str = "mixed", beta: float = 100.0, radius: float = 1.5, step: float = 0.05,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", hpm: Optional[HPM] = None):
         self.prob = autograd.Problem(ctx, cell, np.ascontiguousarray(q, dtype=np.float64), nbands, precision)
         self.t = t
         self.beta = beta
         self.step_size = step
-        self.w = hat_kernel(radius).to(device)
-        self.x = torch.from_numpy(np.ascontiguousarray(rho0, dtype=np.float64)).to(device)
+        self.hpm = hpm
+        self.ctx = ctx
+        r0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        if hpm is None:
+            self.w = hat_kernel(radius).to(device)
+        else:
+            # design variables: the start design averaged over each node's block of elements
+            nv, sp = r0.shape[0], hpm.spacing
+            nn = nv // sp
+            r0 = r0.reshape(nn, sp, nn, sp, nn, sp).mean(axis=(1, 3, 5))
+            if hpm.octant:
+                r0 = np.ascontiguousarray(r0[: nn // 2, : nn // 2, : nn // 2])
+        self.x = torch.from_numpy(np.ascontiguousarray(r0)).to(device)
         self.it = 0
         self.omega_ref: Optional[float] = None
         self.hist = History()
 
+    def projection(self):
+        h = self.hpm
+        return phx.projection(self.prob.cell.nv, h.spacing, h.radius, h.beta(self.it), h.octant)
+
+    def design_map(self, x: torch.Tensor) -> torch.Tensor:
+        if self.hpm is None:
+            return density_filter(x, self.w)
+        return autograd.project(x, self.ctx, self.projection())
+
     def physical(self) -> torch.Tensor:
-        return density_filter(self.x, self.w)
+        return self.design_map(self.x)
 
     def step(self) -> float:
         t0 = time.perf_counter()
         x = self.x.clone().requires_grad_(True)
-        rho = density_filter(x, self.w)
+        rho = self.design_map(x)
         om = autograd.band_frequencies(rho, self.prob)
         if self.omega_ref is None:
             self.omega_ref = float(om[:, self.t].detach().mean())
@@ -128,6 +172,12 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=60)
     ap.add_argument("--seed", type=int, default=502)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--hpm", action="store_true", help="Heaviside projection of a reduced design field")
+    ap.add_argument("--spacing", type=int, default=2, help="HPM: elements between design nodes")
+    ap.add_argument("--proj-radius", type=float, default=2.8, help="HPM: projection radius (element widths)")
+    ap.add_argument("--octant", action="store_true", help="HPM: design one octant, mirrored (SC)")
+    ap.add_argument("--beta-every", type=int, default=20, help="HPM: iterations per doubling of beta")
+    ap.add_argument("--beta-max", type=float, default=64.0)
     ap.add_argument("--final-M", type=int, default=None,
                     help="re-evaluate the final design at this plane-wave order (default M + 1)")
     ap.add_argument("--checkpoint", default=None)
@@ -137,15 +187,19 @@ def main(argv=None):
     rho0 = synth.box_smoothed_uniform(a.nv, a.seed)
     ctx = phx.Context(0)
     q = phx.kpath(a.lattice, a.nk)
-    opt = GapOptimizer(ctx, cell, q, a.nbands, a.t, rho0, a.precision)
+    hpm = HPM(a.spacing, a.proj_radius, a.octant, 1.0, a.beta_max, a.beta_every) if a.hpm else None
+    opt = GapOptimizer(ctx, cell, q, a.nbands, a.t, rho0, a.precision, hpm=hpm)
     if a.resume and a.checkpoint and os.path.exists(a.checkpoint):
         opt.load(a.checkpoint)
     t0 = time.perf_counter()
     while opt.it < a.iters:
         opt.step()
         h = opt.hist
-        print(json.dumps({"iter": opt.it, "ks_gap": h.ks_gap[-1], "gap": h.gap[-1], "volume": h.volume[-1],
-                          "seconds": h.seconds[-1]}), flush=True)
+        rec = {"iter": opt.it, "ks_gap": h.ks_gap[-1], "gap": h.gap[-1], "volume": h.volume[-1],
+               "seconds": h.seconds[-1]}
+        if hpm is not None:
+            rec["beta"] = hpm.beta(opt.it - 1)
+        print(json.dumps(rec), flush=True)
         if a.checkpoint and (opt.it % 10 == 0 or opt.it == a.iters):
             opt.save(a.checkpoint)
     dt = time.perf_counter() - t0

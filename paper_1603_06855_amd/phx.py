@@ -87,6 +87,11 @@ def load():
         "phx_small_orth": (c_int, [P, c_int, c_int, D, c_double, D, I]),
         "phx_small_eig": (c_int, [P, c_int, c_int, c_int, D, I, D, D]),
         "phx_small_rr": (c_int, [P, c_int, c_int, c_int, D, c_double, D, D, D, I]),
+        "phx_projection_size": (c_int, [POINTER(Projection), POINTER(c_long)]),
+        "phx_project": (c_int, [P, POINTER(Projection), D, D]),
+        "phx_project_adjoint": (c_int, [P, POINTER(Projection), D, D, D]),
+        "phx_project_dev": (c_int, [P, POINTER(Projection), c_void_p, c_void_p, c_void_p]),
+        "phx_project_adjoint_dev": (c_int, [P, POINTER(Projection), c_void_p, c_void_p, c_void_p, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -94,6 +99,24 @@ def load():
         f.argtypes = args
     _lib = lib
     return lib
+
+
+class Projection(ctypes.Structure):
+    """phx_projection: the Heaviside projection of a reduced (optionally mirrored-octant)
+    design field onto the nv^3 elements."""
+    _fields_ = [("nv", c_int), ("spacing", c_int), ("radius", c_double), ("beta", c_double), ("octant", c_int)]
+
+
+def projection(nv: int, spacing: int = 2, radius: float = 2.8, beta: float = 1.0, octant: bool = False) -> Projection:
+    return Projection(nv, spacing, radius, beta, 1 if octant else 0)
+
+
+def projection_size(p: Projection) -> int:
+    lib = load()
+    n = c_long(0)
+    if lib.phx_projection_size(byref(p), byref(n)) != OK:
+        raise PhxError(EINVAL, "invalid projection")
+    return n.value
 
 
 def _dptr(a: np.ndarray):
@@ -396,3 +419,47 @@ class Context:
                                           _dptr(Cp), _dptr(th), _iptr(keep)))
         f = lambda a: a.view(np.complex128).reshape(batch, s, m).transpose(0, 2, 1)
         return f(Cx), f(Cp), th.reshape(batch, s), keep.reshape(batch, m)
+
+    # ---------------------------------------------------------------- design projection
+    def project(self, p: Projection, x) -> np.ndarray:
+        xx = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        if xx.size != projection_size(p):
+            raise ValueError("x has the wrong number of design variables")
+        rho = np.zeros(p.nv ** 3)
+        self._check(self.lib.phx_project(self.h, byref(p), _dptr(xx), _dptr(rho)))
+        return rho.reshape(p.nv, p.nv, p.nv)
+
+    def project_adjoint(self, p: Projection, x, grad_rho) -> np.ndarray:
+        xx = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        g = np.ascontiguousarray(grad_rho, dtype=np.float64).reshape(-1)
+        if xx.size != projection_size(p) or g.size != p.nv ** 3:
+            raise ValueError("wrong array sizes")
+        out = np.zeros(xx.size)
+        self._check(self.lib.phx_project_adjoint(self.h, byref(p), _dptr(xx), _dptr(g), _dptr(out)))
+        return out
+
+    def project_dev(self, p: Projection, x_t):
+        """torch CUDA tensors: design variables (projection_size(p) values) -> rho (nv, nv, nv)."""
+        import torch
+        x_t = x_t.detach().contiguous().to(torch.float64)
+        if x_t.numel() != projection_size(p):
+            raise ValueError("x has the wrong number of design variables")
+        rho = torch.empty((p.nv, p.nv, p.nv), dtype=torch.float64, device=x_t.device)
+        st = torch.cuda.current_stream(x_t.device).cuda_stream
+        self._check(self.lib.phx_project_dev(self.h, byref(p), c_void_p(x_t.data_ptr()), c_void_p(rho.data_ptr()),
+                                             c_void_p(st)))
+        return rho
+
+    def project_adjoint_dev(self, p: Projection, x_t, grad_rho_t):
+        """torch CUDA tensors: the backward of project_dev (shaped like x_t)."""
+        import torch
+        x_t = x_t.detach().contiguous().to(torch.float64)
+        g_t = grad_rho_t.detach().contiguous().to(torch.float64)
+        if x_t.numel() != projection_size(p) or g_t.numel() != p.nv ** 3:
+            raise ValueError("wrong tensor sizes")
+        out = torch.empty(x_t.shape, dtype=torch.float64, device=x_t.device)
+        st = torch.cuda.current_stream(x_t.device).cuda_stream
+        self._check(self.lib.phx_project_adjoint_dev(self.h, byref(p), c_void_p(x_t.data_ptr()),
+                                                     c_void_p(g_t.data_ptr()), c_void_p(out.data_ptr()),
+                                                     c_void_p(st)))
+        return out

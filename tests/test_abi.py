@@ -115,3 +115,13 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stderr
     assert out.stdout.startswith("1 "), out.stdout
+
+
+def test_projection_size_counts_design_variables():
+    assert phx.projection_size(phx.projection(32, 2, 2.8, 1.0, False)) == 16 ** 3
+    assert phx.projection_size(phx.projection(32, 2, 2.8, 1.0, True)) == 8 ** 3
+    assert phx.projection_size(phx.projection(20, 1, 1.5, 1.0, False)) == 20 ** 3
+    with pytest.raises(phx.PhxError):
+        phx.projection_size(phx.projection(15, 2, 2.8, 1.0, False))
+    with pytest.raises(phx.PhxError):
+        phx.projection_size(phx.projection(18, 2, 2.8, 1.0, True))
