@@ -133,7 +133,7 @@ def main():
     value = units / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "solve_fwd", "solve_bwd", "sbinv",
+    classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "solve_upd", "solve_diag", "sbinv",
                "assemble", "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"]
     prof = {c: {k: ctx.stat(f"prof.{c}.{k}") for k in ("ms", "flops", "bytes", "count")} for c in classes}
     # Classes that are exactly one kernel, each launch timed by HIP events that the launch
@@ -143,12 +143,13 @@ def main():
     fp_chol = "float" if args.precision == "mixed" else "double"
     fpn = "fp32" if fp_chol == "float" else "fp64"
     nbk = 1 if min(21, nb + max(8, nb)) <= 16 else 2
-    bwd = (f"phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
+    # the block-column steps of the preconditioner solves (both directions); in FP64 the
+    # backward diagonal-block steps run the same kernel outside the class
+    upd = (f"phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
            else f"phx::nrhs_kernel<double, 1, {nbk}, 1>")
     single = {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", fpn, "mfma"),
               "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 2>", "fp64", "mfma"),
-              "solve_fwd": (f"phx::nrhs_kernel<{fp_chol}, 0, {nbk}, 1>", fpn, "hbm"),
-              "solve_bwd": (bwd, fpn, "hbm")}
+              "solve_upd": (upd, fpn, "hbm")}
     # The library counts the work of the padded problem (Np = 64 ceil(N / 64) waves per
     # displacement component); the algorithmic work is that of the N-wave problem: the
     # Cholesky update scales as the cube of the size, the operator products as the square.

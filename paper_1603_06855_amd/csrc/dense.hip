@@ -472,8 +472,9 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.csplit > 0) return (int)hipErrorInvalidValue;  // split output only in the tall-skinny kernel
   if (g.amap && g.ksplit > 1) return (int)hipErrorInvalidValue;
   // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
-  // FP32 A^H the LDS-staged 128 x 32 tiles below read A faster).
-  if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 && (opa == 0 || sizeof(R) == 8)) {
+  // FP32 A^H with more than 256 rows the LDS-staged 128 x 32 tiles below read A faster).
+  if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 &&
+      (opa == 0 || sizeof(R) == 8 || g.M <= 256)) {
     constexpr int X = 1;
     dim3 grid2((unsigned)((g.M + 64 * X - 1) / (64 * X)), (unsigned)g.batch);
     if (opa == 0) {
@@ -824,19 +825,47 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long 
 // (WS x WS blocks, ld WS, nsb = ceil(n / WS) per matrix, batch stride nsb WS^2): one
 // launch of the super-block kernel in inverse mode.  With them every step of a narrow
 // solve is a GEMM (no sequential dependency inside a super-block).
+// The block columns below each diagonal super-block copied, conjugate-transposed, into
+// the (otherwise unused) upper triangle: A[c][r] = conj(L[r][c]) for c in super-block J
+// and r >= the end of J.  The forward solve then reads them as the backward solve reads
+// the factor's row blocks, one contiguous column of the copy per output row.
+template <typename R, int WS>
+__global__ __launch_bounds__(256) void sb_transpose_kernel(C_t<R>* L, int n, long lda, long sL) {
+  typedef C_t<R> C;
+  __shared__ C tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int lim = min(n, (c0 / WS + 1) * WS);  // first row below the super-block of column c0
+  if (r0 < lim || r0 >= n || c0 >= n) return;
+  C* A = L + (long)blockIdx.z * sL;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + tx, c = c0 + k;
+    tile[k][tx] = (r < n && c < n) ? A[r + (long)c * lda] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + tx, r = r0 + k;
+    if (r < n && c < n) {
+      const C v = tile[tx][k];
+      A[c + (long)r * lda] = mk<R>(v.x, -v.y);
+    }
+  }
+}
+
 template <typename R>
-int sb_inverse_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+int sb_inverse_batched(C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                        C_t<R>* SBinv, hipStream_t st) {
   constexpr int WS = sizeof(R) == 4 ? 256 : 128;
   const int nsb = (n + WS - 1) / WS;
-  hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch, nsb, WS / 32), dim3(1024), 0, st, L, lda, sL,
-                     Dinv, sD, (const C_t<R>*)nullptr, 0L, 0L, SBinv, (long)WS, (long)nsb * WS * WS, 0, 0, 0, n);
+  hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch, nsb, WS / 32), dim3(1024), 0, st,
+                     (const C_t<R>*)L, lda, sL, Dinv, sD, (const C_t<R>*)nullptr, 0L, 0L, SBinv, (long)WS,
+                     (long)nsb * WS * WS, 0, 0, 0, n);
+  const unsigned nt = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL((sb_transpose_kernel<R, WS>), dim3(nt, nt, batch), dim3(256), 0, st, L, n, lda, sL);
   return (int)hipGetLastError();
 }
-template int sb_inverse_batched<double>(const double2*, int, long, long, int, const double2*, long, double2*,
-                                        hipStream_t);
-template int sb_inverse_batched<float>(const float2*, int, long, long, int, const float2*, long, float2*,
-                                       hipStream_t);
+template int sb_inverse_batched<double>(double2*, int, long, long, int, const double2*, long, double2*, hipStream_t);
+template int sb_inverse_batched<float>(float2*, int, long, long, int, const float2*, long, float2*, hipStream_t);
 
 // Narrow solve with the super-block inverses: per super-block one GEMM with the inverse
 // (or its conjugate transpose) and one GEMM for the rows beyond it.
@@ -859,7 +888,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z + J0; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      PHX_HOOK_KEV(PROF_SOLVE_FWD, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
+      PHX_HOOK_KEV(PROF_SOLVE_DIAG, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
       e = zgemm<R>(g, 0, 0, st);
       if (e) return e;
     }
@@ -867,12 +896,13 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
     if (rem > 0) {
       GemmArgs<R> g{};
       g.M = rem; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
-      g.A = L + (J0 + w) + (long)J0 * lda; g.lda = lda; g.sA = sL; g.amap = fmap;
+      // the conjugate-transposed copy of the block column (rows J0..J0+w, columns beyond)
+      g.A = L + J0 + (long)(J0 + w) * lda; g.lda = lda; g.sA = sL; g.amap = fmap;
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      PHX_HOOK_KEV(PROF_SOLVE_FWD, na * 8.0 * rem * w * nc, na * cb * ((double)rem * w + 2.0 * rem * nc), g);
-      e = zgemm<R>(g, 0, 0, st);
+      PHX_HOOK_KEV(PROF_SOLVE_UPD, na * 8.0 * rem * w * nc, na * cb * ((double)rem * w + 2.0 * rem * nc), g);
+      e = zgemm<R>(g, 1, 0, st);
       if (e) return e;
     }
   }
@@ -885,7 +915,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
-      PHX_HOOK_KEV(PROF_SOLVE_BWD, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
+      PHX_HOOK_KEV(PROF_SOLVE_DIAG, na * 8.0 * w * (w + 64) / 2.0 * nc, na * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc), g);
       e = zgemm<R>(g, 1, 0, st);
       if (e) return e;
     }
@@ -896,7 +926,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
-      PHX_HOOK_KEV(PROF_SOLVE_BWD, na * 8.0 * J0 * w * nc, na * cb * ((double)J0 * w + 2.0 * J0 * nc), g);
+      PHX_HOOK_KEV(PROF_SOLVE_UPD, na * 8.0 * J0 * w * nc, na * cb * ((double)J0 * w + 2.0 * J0 * nc), g);
       e = zgemm<R>(g, 1, 0, st);
       if (e) return e;
     }

@@ -40,8 +40,8 @@ enum ProfClass {
   PROF_HERK,
   PROF_TRSM_DIAG,
   PROF_TRSM_UPDATE,
-  PROF_SOLVE_FWD,  // forward steps of the super-block solves (one kernel)
-  PROF_SOLVE_BWD,  // backward steps of the super-block solves (one kernel)
+  PROF_SOLVE_UPD,   // block-column / row-block steps of the super-block solves (one kernel)
+  PROF_SOLVE_DIAG,  // inverse-diagonal-block steps of the super-block solves
   PROF_SBINV,      // inverses of the factor's diagonal super-blocks
   PROF_NCLASS_DENSE
 };
@@ -75,9 +75,11 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
                   const int* fmap = nullptr, int nacc = 0);
 
 // Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
-// Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS).
+// Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS); and the block
+// columns below the super-blocks copied, conjugate-transposed, into the upper triangle of L
+// (which the factorisation leaves unused), as the super-block solves read them.
 template <typename R>
-int sb_inverse_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
+int sb_inverse_batched(C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
                        C_t<R>* SBinv, hipStream_t st);
 
 }  // namespace phx

@@ -82,8 +82,8 @@ enum RtClass {
   PROF_ADJOINT,
   PROF_NCLASS
 };
-const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",    "herk",  "trsm_diag", "trsm_update",
-                                             "solve_fwd",  "solve_bwd", "sbinv", "assemble",  "apply",
+const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",      "herk",  "trsm_diag", "trsm_update",
+                                             "solve_upd",  "solve_diag", "sbinv", "assemble",  "apply",
                                              "op_gemm",    "gram",      "small", "update",    "residual",
                                              "adjoint"};
 
@@ -763,7 +763,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     const long nsb = (n3 + WS - 1) / WS;
     sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nkf * nsb * WS * WS);
     PROF_BEGIN(PROF_SBINV);
-    KCHK(sb_inverse_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
+    KCHK(sb_inverse_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
                                (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, st));
     PROF_END(PROF_SBINV, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
   }

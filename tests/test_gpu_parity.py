@@ -451,7 +451,7 @@ def test_kernel_class_timing(ctx):
     ctx.set_option("profile", 1)
     ctx.bands(cell, rho, q, wl.nbands, "mixed")
     ctx.set_option("profile", 0)
-    for c in ("herk", "op_gemm", "solve_fwd", "solve_bwd"):
+    for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
         n, ms = ctx.stat(f"prof.{c}.count"), ctx.stat(f"prof.{c}.ms")
         fl, by = ctx.stat(f"prof.{c}.flops"), ctx.stat(f"prof.{c}.bytes")
         log(c, n, ms, fl, by)
