@@ -473,7 +473,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.amap && g.ksplit > 1) return (int)hipErrorInvalidValue;
   // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
   // FP32 A^H with more than 256 rows the LDS-staged 128 x 32 tiles below read A faster).
-  if (!g.tri && !g.op && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 &&
+  if (!g.tri && !g.op && !g.tiled && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 &&
       (opa == 0 || sizeof(R) == 8 || g.M <= 256)) {
     constexpr int X = 1;
     dim3 grid2((unsigned)((g.M + 64 * X - 1) / (64 * X)), (unsigned)g.batch);
@@ -898,6 +898,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       g.M = rem; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       // the conjugate-transposed copy of the block column (rows J0..J0+w, columns beyond)
       g.A = L + J0 + (long)(J0 + w) * lda; g.lda = lda; g.sA = sL; g.amap = fmap;
+      g.tiled = sizeof(R) == 4;  // every FP32 update step on the one tiled A^H kernel
       g.B = Z + J0; g.ldb = ldz; g.sB = sZ;
       g.Cm = B + J0 + w; g.ldc = ldb; g.sC = sB;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
@@ -923,6 +924,7 @@ int potrs_sbinv(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t<
       GemmArgs<R> g{};
       g.M = J0; g.N = nc; g.K = w; g.batch = batch; g.kact = kact;
       g.A = L + J0; g.lda = lda; g.sA = sL; g.amap = fmap;  // rows J0..J0+w, cols 0..J0-1; op = C
+      g.tiled = sizeof(R) == 4;
       g.B = B + J0; g.ldb = ldb; g.sB = sB;
       g.Cm = Z; g.ldc = ldz; g.sC = sZ;
       g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);

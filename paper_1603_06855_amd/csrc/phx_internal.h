@@ -28,6 +28,7 @@ struct GemmArgs {
   int csplit, cgap;  // tall-skinny only: output column j >= csplit (if > 0) is stored at j + cgap
   const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
   hipEvent_t ev0, ev1;  // optional: recorded at the start and the end of the (single) kernel's execution
+  int tiled;            // 1: always the LDS-tiled kernel, never the streaming few-RHS one
 };
 
 template <typename R>
