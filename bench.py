@@ -108,8 +108,11 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # Timed steps: only the launches of the single-kernel classes record events (their
+    # kernel's start and end); the stage intervals of the breakdown come from one more,
+    # untimed step afterwards (their events on every stage would slow the timed steps).
     ctx.set_option("profile_reset", 1)
-    ctx.set_option("profile", 1)
+    ctx.set_option("profile", 2)
     torch.cuda.synchronize()
     w0 = time.monotonic_ns()
     t0 = time.perf_counter()
@@ -136,6 +139,13 @@ def main():
     classes = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "solve_upd", "solve_diag", "sbinv",
                "assemble", "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"]
     prof = {c: {k: ctx.stat(f"prof.{c}.{k}") for k in ("ms", "flops", "bytes", "count")} for c in classes}
+    # the untimed, fully profiled step of the per-stage breakdown
+    ctx.set_option("profile_reset", 1)
+    ctx.set_option("profile", 1)
+    step()
+    torch.cuda.synchronize()
+    ctx.set_option("profile", 0)
+    stage_ms = {c: round(ctx.stat(f"prof.{c}.ms"), 3) for c in classes}
     # Classes that are exactly one kernel, each launch timed by HIP events that the launch
     # itself records at the kernel's start and end (hipExtLaunchKernelGGL, on the library
     # stream the kernel runs on): the roofline entry is the one of them that took the most
@@ -179,7 +189,7 @@ def main():
     order = sorted(single, key=lambda c: -prof[c]["ms"])
     roof = entry(order[0])
     roof["others"] = [entry(c) for c in order[1:]]
-    breakdown = {c: round(prof[c]["ms"] / args.steps, 3) for c in classes}
+    breakdown = stage_ms
 
     cpu = None
     if not args.no_cpu:

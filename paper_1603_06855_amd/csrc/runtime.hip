@@ -100,6 +100,7 @@ struct ProfAcc {
 
 struct Profiler {
   bool on = false;
+  bool stages = true;  // false: only the launches that record their own kernel events
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   struct Pend {
@@ -121,7 +122,7 @@ struct Profiler {
     return e;
   }
   void begin(int cls) {
-    if (!on) return;
+    if (!on || !stages) return;
     open = get();
     if (open) (void)hipEventRecord(open, st);
   }
@@ -1087,7 +1088,11 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
   else if (k == "kshare_dist") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_dist = v; }
   else if (k == "kshare_rel") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_rel = v; }
-  else if (k == "profile") { ctx->prof.on = (v != 0); }
+  else if (k == "profile") {
+    if (!(v == 0 || v == 1 || v == 2)) return bad();
+    ctx->prof.on = v != 0;
+    ctx->prof.stages = v != 2;
+  }
   else if (k == "profile_reset") { ctx->prof.reset(); }
   else { ctx->err = "unknown option " + k; return PHX_EINVAL; }
   return PHX_OK;
@@ -1465,6 +1470,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
     for (int i = 0; i < nw; ++i) {
       ctx->workers[i]->opt = ctx->opt;
       ctx->workers[i]->prof.on = ctx->prof.on;
+      ctx->workers[i]->prof.stages = ctx->prof.stages;
       ctx->workers[i]->trace = ctx->trace;
     }
     // most expensive designs first: the per-k cost grows like (3N)^3

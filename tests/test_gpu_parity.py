@@ -443,16 +443,25 @@ def test_small_rr_generalised(ctx, m, s, ndep):
 
 def test_kernel_class_timing(ctx):
     """The single-kernel timing classes (each launch records events at its kernel's start
-    and end) see every launch, with positive durations and work."""
+    and end) see every launch, with positive durations and work, with the stage timers
+    on (profile 1) or off (profile 2)."""
     wl = synth.config2()
     cell, rho = wl.cells[0], wl.designs[0]
     q = phx.kpath(cell.lattice, wl.nk, wl.path)
-    ctx.set_option("profile_reset", 1)
-    ctx.set_option("profile", 1)
-    ctx.bands(cell, rho, q, wl.nbands, "mixed")
-    ctx.set_option("profile", 0)
+    counts = {}
+    for mode in (1, 2):
+        ctx.set_option("profile_reset", 1)
+        ctx.set_option("profile", mode)
+        ctx.bands(cell, rho, q, wl.nbands, "mixed")
+        ctx.set_option("profile", 0)
+        for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
+            n, ms = ctx.stat(f"prof.{c}.count"), ctx.stat(f"prof.{c}.ms")
+            fl, by = ctx.stat(f"prof.{c}.flops"), ctx.stat(f"prof.{c}.bytes")
+            log(mode, c, n, ms, fl, by)
+            assert n > 0 and ms > 0 and fl > 0 and by > 0
+            counts[mode, c] = n
+        # mode 2 times only the launches that record their own events
+        stage = ctx.stat("prof.gram.count")
+        assert (stage > 0) if mode == 1 else (stage == 0)
     for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
-        n, ms = ctx.stat(f"prof.{c}.count"), ctx.stat(f"prof.{c}.ms")
-        fl, by = ctx.stat(f"prof.{c}.flops"), ctx.stat(f"prof.{c}.bytes")
-        log(c, n, ms, fl, by)
-        assert n > 0 and ms > 0 and fl > 0 and by > 0
+        assert counts[1, c] == counts[2, c]
