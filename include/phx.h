@@ -120,7 +120,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * stage intervals on the library stream and, for the classes herk, op_gemm,
  * solve_upd and solve_diag, events that each launch records at its kernel's start
  * and end; 2: only the latter, which disturbs concurrent streams least),
- * "profile_reset" (any value: clears the class timers).
+ * "profile_reset" (any value: clears the class timers),
+ * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
+ * blocking-sync event, leaving the core to the threads of concurrent design
+ * streams; 1: it spins in hipStreamSynchronize).
  * Returns PHX_EINVAL for an unknown key or an out-of-range value. */
 int phx_set_option(phx_ctx* ctx, const char* key, double value);
 /* Statistics of the last solve: "iters" (eigensolver iterations of the

@@ -60,6 +60,7 @@ struct Opts {
   int kshare = 2;            // at most this many consecutive k-points share one preconditioner factor
   double kshare_dist = 0.15; // ... if within this Cartesian distance (cycles per a) of the group's first
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
+  int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
 };
 
 struct Stats {
@@ -192,6 +193,9 @@ struct phx_ctx {
   bool trace = false;
   Profiler prof;
   PendKernel pk{0, 0, 0, false};  // timing request for the next GEMM launch
+  hipEvent_t wait_ev = nullptr;   // blocking-sync event of the per-iteration host wait
+  void* hpin = nullptr;           // pinned host staging of the per-iteration read-backs
+  size_t hpin_bytes = 0;
   std::vector<phx_ctx*> workers;  // contexts (own stream and workspaces) of the batched call
   phx::ProfHook hook{hook_begin, hook_end, hook_kev, nullptr};
   const phx::ProfHook* hk() {
@@ -252,6 +256,34 @@ T* dbuf(phx_ctx* ctx, const std::string& name, size_t count) {
     b.bytes = need;
   }
   return (T*)b.p;
+}
+
+// Pinned host staging area of at least `bytes` (grow-only, one per context).
+void* hbuf(phx_ctx* ctx, size_t bytes) {
+  if (ctx->hpin_bytes < bytes) {
+    if (ctx->hpin) HIPCHK(hipHostFree(ctx->hpin));
+    ctx->hpin = nullptr;
+    ctx->hpin_bytes = 0;
+    if (hipHostMalloc(&ctx->hpin, bytes, hipHostMallocDefault) != hipSuccess) {
+      ctx->hpin = nullptr;
+      ctx->err = "hipHostMalloc(" + std::to_string(bytes) + " bytes) failed";
+      throw Fail{PHX_ENOMEM};
+    }
+    ctx->hpin_bytes = bytes;
+  }
+  return ctx->hpin;
+}
+
+// Host wait for everything queued on st: a blocking-sync event, so that the waiting
+// thread sleeps instead of spinning on a core the other design streams' threads need
+// to launch their work (option spin_wait = 1: hipStreamSynchronize).
+void wait_stream(phx_ctx* ctx, hipStream_t st) {
+  if (ctx->opt.spin_wait) {
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
+  HIPCHK(hipEventRecord(ctx->wait_ev, st));
+  HIPCHK(hipEventSynchronize(ctx->wait_ev));
 }
 
 void prim_rows(int lattice, double A[3][3]) {
@@ -821,16 +853,25 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
                        sv.rn, sv.rnorm, st, sv.kact);
     PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * sv.nact + (double)sizeof(C_t<R>) * 3.0 * d.N * s * sv.nact);
     KCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(rn_h.data(), sv.rn, rn_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(sw_h.data(), sv.sweeps, sw_h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    // residual norms, Jacobi sweep counts and (first iteration) the factorisation flag,
+    // through pinned memory on this stream, then one host wait
+    {
+      const size_t nrn = rn_h.size() * sizeof(double), nsw = sw_h.size() * sizeof(int);
+      char* hp = (char*)hbuf(ctx, nrn + nsw + sizeof(int));
+      HIPCHK(hipMemcpyAsync(hp, sv.rn, nrn, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hp + nrn, sv.sweeps, nsw, hipMemcpyDeviceToHost, st));
+      if (it == 0) HIPCHK(hipMemcpyAsync(hp + nrn + nsw, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+      wait_stream(ctx, st);
+      memcpy(rn_h.data(), hp, nrn);
+      memcpy(sw_h.data(), hp + nrn, nsw);
+      if (it == 0) {
+        int flag = 0;
+        memcpy(&flag, hp + nrn + nsw, sizeof(int));
+        if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
+      }
+    }
     for (int v : sw_h) ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, v);
     ctx->prof.flush();
-    if (it == 0) {
-      int flag = 0;
-      HIPCHK(hipMemcpy(&flag, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost));
-      if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
-    }
     double worst = 0;
     for (int k = 0; k < nk; ++k) {
       double wk = 0;
@@ -1040,7 +1081,10 @@ int phx_create(phx_ctx** out, int hip_device) {
   const char* tr = getenv("PHX_TRACE");
   c->trace = tr && tr[0] && tr[0] != '0';
   if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
-      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) {
+      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->wait_ev, hipEventBlockingSync | hipEventDisableTiming) != hipSuccess) {
+    if (c->dflag) (void)hipFree(c->dflag);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return PHX_EHIP;
   }
@@ -1058,6 +1102,8 @@ int phx_destroy(phx_ctx* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->dflag) (void)hipFree(ctx->dflag);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+  if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
   if (ctx->stream && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return PHX_OK;
@@ -1088,6 +1134,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
   else if (k == "kshare_dist") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_dist = v; }
   else if (k == "kshare_rel") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_rel = v; }
+  else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "profile") {
     if (!(v == 0 || v == 1 || v == 2)) return bad();
     ctx->prof.on = v != 0;

@@ -67,7 +67,7 @@ def test_zgemm_tall_skinny(ctx, prec, tol, m, n, k, batch):
 
 @pytest.mark.parametrize("sbinv", [0, 1])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 5e-4)])
-@pytest.mark.parametrize("n,nrhs,batch", [(64, 3, 1), (192, 21, 2), (320, 7, 3), (576, 32, 2)])
+@pytest.mark.parametrize("n,nrhs,batch", [(64, 3, 1), (192, 21, 2), (320, 7, 3), (576, 32, 2), (960, 21, 2)])
 def test_zposv(ctx, prec, tol, n, nrhs, batch, sbinv):
     log("zposv", prec, n, nrhs, batch, "sbinv", sbinv)
     ctx.set_option("sbinv", sbinv)
