@@ -90,3 +90,50 @@ def test_fcc_uneven_m_batch(ctx):
         err = _rel(oms[d].cpu().numpy()[[k]], ref)
         log("design", d, "M=3 mixed vs oracle at k", k, err.max())
         assert err.max() <= 1e-6
+
+
+def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
+    """The benchmark's timed configuration: 16 FCC 32^3 designs at M=5, 60 k-points, 12
+    bands and the adjoint of bands 6/7 in mixed precision through one batched call on 16
+    library streams, with the benchmark's factor sharing (up to 8 k-points per factor
+    within 1.0 cycles/a).  Design 0 at two k-points against the FP64 oracle: every
+    frequency within 1e-6 relative and both sensitivity fields within 1e-4 of their
+    largest entry (bands 6 and 7 are checked to be non-degenerate there)."""
+    import torch
+    from oracle import adjoint, geometry
+    wl = synth.config4(all_m5=True, ndesign=16)
+    q = phx.kpath("FCC", wl.nk)
+    rhos = [torch.from_numpy(np.ascontiguousarray(d.reshape(-1))).to("cuda:0") for d in wl.designs]
+    ctx.set_option("streams", 16)
+    ctx.set_option("kshare", 8)
+    ctx.set_option("kshare_dist", 1.0)
+    try:
+        t = time.time()
+        oms, dws = ctx.sens_batch_dev(wl.cells, rhos, q, wl.nbands, wl.sens_bands, "mixed")
+        torch.cuda.synchronize()
+        log("FCC 32^3 M=5 x16, 60 k, benchmark configuration:", round(time.time() - t, 2), "s; factors",
+            ctx.stat("factors"), "iters", ctx.stat("iters"))
+    finally:
+        ctx.set_option("streams", 4)
+        ctx.set_option("kshare", 2)
+        ctx.set_option("kshare_dist", 0.15)
+    for d in range(16):
+        assert torch.isfinite(oms[d]).all() and torch.isfinite(dws[d]).all()
+    ks = [3, 23]  # bands 6 and 7 at least 1.5e-3 (relative) from their neighbours here
+    Q = geometry.kpath("FCC", wl.nk)[ks]
+    t = time.time()
+    om_ref, dw_ref = adjoint.sensitivities(wl.cells[0], wl.designs[0], Q, wl.nbands, wl.sens_bands)
+    log("oracle M=5, 2 k-points:", round(time.time() - t, 1), "s")
+    om = oms[0].cpu().numpy()[ks]
+    dw = dws[0].cpu().numpy()[ks]
+    err = _rel(om, om_ref)
+    log("mixed vs oracle, max rel omega error", err.max())
+    assert err.max() <= 1e-6
+    for i in range(len(ks)):
+        w = om_ref[i]
+        for j, b in enumerate(wl.sens_bands):
+            gaps = [abs(w[b - 1] - w[b - 2]), abs(w[b] - w[b - 1])]
+            assert min(gaps) > 1e-3 * w[b - 1], (ks[i], b, gaps)
+            e = np.abs(dw[i, j] - dw_ref[i, j]).max() / np.abs(dw_ref[i, j]).max()
+            log("k", ks[i], "band", b, "sensitivity error", e)
+            assert e <= 1e-4
