@@ -178,22 +178,38 @@ def main():
     breakdown = stage_ms
 
     # Accuracy gate (untimed, after the timed steps): the last timed step's own mixed-precision
-    # results for design 0 at a subset of its k-points against FP64 solves (tolerance 1e-10)
-    # of the same design at those k-points.
+    # results for every design at a subset of its k-points against FP64 solves (tolerance
+    # 1e-10) of the same designs at those k-points, one batched call.  Frequencies: relative
+    # error, bands below 1e-3 of the largest frequency (the acoustic bands near Gamma)
+    # excluded; sensitivities: norm-relative per (design, k, band), bands closer than 1e-4
+    # (relative) to a neighbour excluded (their per-vector sensitivity is not unique).
     gate = None
     if not args.no_gate:
         sub_idx = np.arange(0, args.nk, max(1, args.nk // 8))
-        om32 = res[0][0].cpu().numpy()[sub_idx]
-        dw32 = res[1][0].cpu().numpy()[sub_idx]
         ctx.set_option("tol_fp64", 1e-10)
-        om64, dw64 = ctx.sens(cells[0], wl.designs[0], q[sub_idx], nb, bands, "fp64")
+        o64, d64 = ctx.sens_batch_dev(cells, rho_dev, q[sub_idx], nb, bands, "fp64")
+        torch.cuda.synchronize()
         ctx.set_option("tol_fp64", 1e-8)
-        scale = om64.max()
-        rel = np.where(om64 > 1e-3 * scale, np.abs(om32 - om64) / np.maximum(om64, 1e-300), 0.0)
-        sens_err = float(max(np.abs(dw32[k, j] - dw64[k, j]).max() / max(np.abs(dw64[k, j]).max(), 1e-300)
-                             for k in range(len(sub_idx)) for j in range(len(bands)) if om64[k, bands[j] - 1] > 0))
-        gate = {"k_points": int(len(sub_idx)), "source": "timed step, design 0",
-                "max_rel_omega_err": float(rel.max()), "max_sens_err": sens_err, "pass": bool(rel.max() <= 1e-6)}
+        om_err, sens_err, skipped = 0.0, 0.0, 0
+        for d in range(args.designs):
+            om32 = res[0][d].cpu().numpy()[sub_idx]
+            dw32 = res[1][d].cpu().numpy()[sub_idx]
+            om64, dw64 = o64[d].cpu().numpy(), d64[d].cpu().numpy()
+            rel = np.where(om64 > 1e-3 * om64.max(), np.abs(om32 - om64) / np.maximum(om64, 1e-300), 0.0)
+            om_err = max(om_err, float(rel.max()))
+            for k in range(len(sub_idx)):
+                w = om64[k]
+                for j, b in enumerate(bands):
+                    i = b - 1
+                    gap = min(abs(w[i] - w[i - 1]), abs(w[i + 1] - w[i]) if i + 1 < nb else np.inf)
+                    if w[i] <= 0 or gap < 1e-4 * w[i]:
+                        skipped += 1
+                        continue
+                    e = np.abs(dw32[k, j] - dw64[k, j]).max() / max(np.abs(dw64[k, j]).max(), 1e-300)
+                    sens_err = max(sens_err, float(e))
+        gate = {"designs": args.designs, "k_points": int(len(sub_idx)), "source": "timed step",
+                "max_rel_omega_err": om_err, "max_sens_err": sens_err, "sens_skipped_degenerate": skipped,
+                "pass": bool(om_err <= 1e-6 and sens_err <= 1e-6)}
 
     cpu = None
     if not args.no_cpu:
