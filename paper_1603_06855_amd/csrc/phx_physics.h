@@ -32,8 +32,6 @@ void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np
                    double2* tr, hipStream_t st, const int* kact = nullptr);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
                   double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr);
-void launch_copy_inactive(const double2* src, double2* dst, long n, long stride, int nk, const int* kact,
-                          hipStream_t st);
 void launch_zero(double2* X, long n, hipStream_t st);
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
 void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,

@@ -486,21 +486,6 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
                      ldk, sK, kact);
 }
 
-// For the k-points with kact[k] == 0: n values at src + k stride -> dst + k stride (the
-// basis of a converged k-point follows the double-buffer swap unchanged).
-__global__ void copy_inactive_kernel(const double2* src, double2* dst, long n, long stride, const int* kact) {
-  const int k = blockIdx.y;
-  if (kact[k]) return;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-    dst[(long)k * stride + e] = src[(long)k * stride + e];
-}
-
-void launch_copy_inactive(const double2* src, double2* dst, long n, long stride, int nk, const int* kact,
-                          hipStream_t st) {
-  unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 1024);
-  hipLaunchKernelGGL(copy_inactive_kernel, dim3(nb, nk), dim3(256), 0, st, src, dst, n, stride, kact);
-}
-
 void launch_zero(double2* X, long n, hipStream_t st) {
   unsigned nb = (unsigned)std::min<long>(nblk(n, 256), 8192);
   if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, st, X, n);

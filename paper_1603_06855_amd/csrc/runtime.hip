@@ -483,7 +483,7 @@ struct Solver {
   Design* d;
   int nk, nb, s, m, prec;
   long n3, sBig;
-  double2 *Big, *Big2;
+  double2* Big;
   double* Kv;
   double* sigma_d;
   double2 *Y, *Tr, *Zy, *Zt;
@@ -578,6 +578,24 @@ void gram(Solver& sv, double2* Big, int block) {
   PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nact, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nact);
 }
 
+// Basis update in place, for every k and each of the blocks S, KS, Omega S (batch 3 nk,
+// the k-point's coefficients shared by its three blocks): columns c0 .. c0 + ncol - 1 of
+// the new block are the old block's columns a0 .. a0 + K - 1 times the K x ncol
+// coefficients C, written from column c0 (with split > 0: output columns split .. are
+// written split further right, the tall-skinny kernel's split store).  Every output row
+// depends only on the same row of the old block, and every kernel this product can run
+// on (N <= 64: the tall-skinny kernel, the few-right-hand-side kernel or one column tile
+// of the tiled kernel) reads a row's whole K range before it writes that row, and no two
+// workgroups share a row, so reading and writing the same array is safe.  Frozen
+// k-points are skipped and keep their basis.
+void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, long sC, long c0, int split) {
+  phx_ctx* ctx = sv.ctx;
+  const long n3 = sv.n3, m = sv.m;
+  if (ncol > 64 || K > 64) fail(ctx, PHX_EINVAL, "in-place basis update needs at most 64 columns");
+  gemm<double>(ctx, 0, 0, n3, ncol, K, 3 * sv.nk, sv.Big + a0 * n3, n3, n3 * m, 1, C, m, sC, 3, sv.Big + c0 * n3, n3,
+               n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3, split, split);
+}
+
 void cholqr(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
@@ -587,12 +605,10 @@ void cholqr(Solver& sv) {
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
+  // (in place: see update_in_place)
   PROF_BEGIN(PROF_UPDATE);
-  gemm<double>(ctx, 0, 0, n3, m, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.C0, m, m * m, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO, 1, nullptr, 0, sv.kact, 3);
-  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
+  update_in_place(sv, 0, m, m, sv.C0, m * m, 0, 0);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nact, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nact);
-  std::swap(sv.Big, sv.Big2);
 }
 
 void rayleigh_ritz(Solver& sv) {
@@ -605,14 +621,12 @@ void rayleigh_ritz(Solver& sv) {
   KCHK(hipGetLastError());
   // X <- [S] Cr ; P <- [W P] Cr[s:m]
   PROF_BEGIN(PROF_UPDATE);
-  gemm<double>(ctx, 0, 0, n3, s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cr, m, m * s, 3, sv.Big2, n3, n3 * m, ONE,
-               ZERO, 1, nullptr, 0, sv.kact, 3);
-  gemm<double>(ctx, 0, 0, n3, s, m - s, 3 * sv.nk, sv.Big + s * n3, n3, n3 * m, 1, sv.Cr + s, m, m * s, 3,
-               sv.Big2 + 2 * s * n3, n3, n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3);
-  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
+  // In place (see update_in_place), X first: it reads the whole old basis and writes only
+  // X, which the product for P does not read; P then reads W and the old P and writes P.
+  update_in_place(sv, 0, s, m, sv.Cr, m * s, 0, 0);
+  update_in_place(sv, s, s, m - s, sv.Cr + s, m * s, 2 * s, 0);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nact,
            16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
-  std::swap(sv.Big, sv.Big2);
 }
 
 // Rayleigh-Ritz on the once-orthonormalised basis: both Gram matrices S^H [KS | Omega S]
@@ -634,11 +648,8 @@ void rayleigh_ritz_fused(Solver& sv) {
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
-  gemm<double>(ctx, 0, 0, n3, 2 * s, m, 3 * sv.nk, sv.Big, n3, n3 * m, 1, sv.Cp, m, 2 * m * s, 3, sv.Big2, n3, n3 * m,
-               ONE, ZERO, 1, nullptr, 0, sv.kact, 3, (int)s, (int)s);
-  launch_copy_inactive(sv.Big, sv.Big2, sv.sBig, sv.sBig, sv.nk, sv.kact, ctx->stream);
+  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nact, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
-  std::swap(sv.Big, sv.Big2);
 }
 
 template <typename R>
@@ -663,7 +674,7 @@ long per_k_bytes(const Design& d, int s, int prec) {
   const long n3 = d.n3, m = 3 * s;
   const long pc = prec == PHX_FP64 ? 16 : 8;
   const long ws = prec == PHX_FP64 ? 128 : 256;
-  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc + 2L * 3 * n3 * m * 16 +
+  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc + 3L * n3 * m * 16 +
          2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
 }
 
@@ -680,7 +691,6 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.n3 = n3;
   sv.sBig = 3 * n3 * m;
   sv.Big = dbuf<double2>(ctx, "Big", (long)nk * sv.sBig);
-  sv.Big2 = dbuf<double2>(ctx, "Big2", (long)nk * sv.sBig);
   sv.Kv = dbuf<double>(ctx, "Kv", (long)nk * d.Np * 3);
   sv.sigma_d = dbuf<double>(ctx, "sigma", nk);
   sv.Y = dbuf<double2>(ctx, "Y", (long)nk * d.Np * 6 * s);
