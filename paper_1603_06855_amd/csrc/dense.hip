@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256, 3) void nrhs_kernel(GemmArgs<R> g) {
   // row pitch: lanes 16..31 read the next k row (OPA = 0) or the row four further
   // (OPA = 1); the pitch puts them on the other 16 of 32 banks
   constexpr int LDB = OPA == 0 ? 48 : (NC == 16 ? 20 : 36);
-  __shared__ R Br[KC][LDB], Bi[KC][LDB], Bs[K3 ? KC : 1][LDB];
+  __shared__ R Br[KC][LDB], Bi[KC][LDB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int b = blockIdx.y;
@@ -353,7 +353,6 @@ __global__ __launch_bounds__(256, 3) void nrhs_kernel(GemmArgs<R> g) {
       if (k0 + k < g.K && j < g.N) v = Bm[k0 + k + (long)j * g.ldb];
       Br[k][j] = v.x;
       Bi[k][j] = v.y;
-      if (K3) Bs[k][j] = v.x + v.y;
     }
   };
   auto mult = [&](const C (&v)[X][4], int kl) {
@@ -373,7 +372,7 @@ __global__ __launch_bounds__(256, 3) void nrhs_kernel(GemmArgs<R> g) {
 #pragma unroll
         for (int x = 0; x < X; ++x) {
           if (K3) {
-            const R bs = Bs[k][16 * y + li];
+            const R bs = br + bi;  // in registers: a third LDS array would cost residency
             t1[x][y] = mfma16(br, ar[x], t1[x][y]);
             t2[x][y] = mfma16(bi, ai[x], t2[x][y]);
             t3[x][y] = mfma16(bs, as[x], t3[x][y]);
