@@ -121,6 +121,9 @@ const char* phx_last_error(const phx_ctx* ctx);
  * solve_upd and solve_diag, events that each launch records at its kernel's start
  * and end; 2: only the latter, which disturbs concurrent streams least),
  * "profile_reset" (any value: clears the class timers),
+ * "gram_split" (0..16; 0, default: min(16, 3Np / 256)): the eigensolver's Gram
+ * products S^H [K S | Omega S] are split over this many parts of their long
+ * dimension (partial products summed by a second kernel; 1: one kernel),
  * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
  * blocking-sync event, leaving the core to the threads of concurrent design
  * streams; 1: it spins in hipStreamSynchronize).

@@ -61,6 +61,7 @@ struct Opts {
   double kshare_dist = 0.15; // ... if within this Cartesian distance (cycles per a) of the group's first
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
+  int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
 };
 
 struct Stats {
@@ -697,7 +698,8 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.Tr = dbuf<double2>(ctx, "Tr", (long)nk * d.Np * s);
   sv.Zy = dbuf<double2>(ctx, "Zy", (long)nk * d.Np * 6 * s);
   sv.Zt = dbuf<double2>(ctx, "Zt", (long)nk * d.Np * s);
-  sv.ksplit = (int)std::max<long>(1, std::min<long>(16, n3 / 256));
+  sv.ksplit = ctx->opt.gram_split > 0 ? ctx->opt.gram_split
+                                      : (int)std::max<long>(1, std::min<long>(16, n3 / 256));
   sv.G = dbuf<double2>(ctx, "G", (long)nk * m * m);
   sv.Gpart = dbuf<double2>(ctx, "Gpart", (long)sv.ksplit * nk * m * m);
   sv.C0 = dbuf<double2>(ctx, "C0", (long)nk * m * m);
@@ -1144,6 +1146,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
   else if (k == "kshare_dist") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_dist = v; }
   else if (k == "kshare_rel") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_rel = v; }
+  else if (k == "gram_split") { if (!(v >= 0 && v <= 16 && v == (int)v)) return bad(); ctx->opt.gram_split = (int)v; }
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "profile") {
     if (!(v == 0 || v == 1 || v == 2)) return bad();
