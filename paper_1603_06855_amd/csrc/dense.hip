@@ -693,14 +693,10 @@ template int potrf_batched<float>(float2*, int, long, long, int, float2*, long, 
 // the operand is read down columns (coalesced over rows), k = 16 (lane/16) + ks
 // when it is read along columns of L (each lane walks contiguous memory).
 // ---------------------------------------------------------------------------
-// inv_n > 0 selects the inverse mode (LOWER only): the right-hand side is the identity,
-// the workgroup (b, J, c) solves columns 32c .. 32c + 31 of L_JJ^{-1} for the diagonal
-// super-block J0 = J WS of a matrix of order inv_n, and writes them to
-// X + b sX + J WS^2 (a WS x WS column-major block, ld WS).
 template <typename R, bool LOWER, int WS>
 __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long lda, long sL, const C_t<R>* Dinv,
                                                          long sD, const C_t<R>* Bin, long ldb, long sB, C_t<R>* X,
-                                                         long ldx, long sX, int J0, int T, int nc, int inv_n) {
+                                                         long ldx, long sX, int J0, int T, int nc) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
   __shared__ R Sr[WS][32], Si[WS][32];
@@ -713,21 +709,11 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long 
   const C* Lb = L + b * sL;
   const C* Db = Dinv + b * sD;
   C* Xb = X + b * sX;
-  int c0 = 0;
-  if (inv_n > 0) {
-    J0 = blockIdx.y * WS;
-    T = min(WS, inv_n - J0) / 64;
-    c0 = blockIdx.z * 32;
-    if (c0 >= 64 * T) return;  // the whole workgroup: columns beyond the block
-    nc = 32;
-    Xb += (long)blockIdx.y * WS * WS - J0 + (long)c0 * ldx;  // row J0 + r of the solution -> row r
-  }
   const int rows = 64 * T;
   for (int e = tid; e < rows * 32; e += 1024) {
     const int r = e % rows, c = e / rows;
     C v = mk<R>(0, 0);
-    if (inv_n > 0) v = mk<R>(r == c0 + c ? (R)1 : (R)0, 0);
-    else if (c < nc) v = Bin[b * sB + (J0 + r) + (long)c * ldb];
+    if (c < nc) v = Bin[b * sB + (J0 + r) + (long)c * ldb];
     Sr[r][SW(r, c)] = v.x;
     Si[r][SW(r, c)] = v.y;
   }
@@ -823,10 +809,6 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const C_t<R>* L, long 
 #undef SW
 }
 
-// Explicit inverses of the diagonal super-blocks of a batch of Cholesky factors
-// (WS x WS blocks, ld WS, nsb = ceil(n / WS) per matrix, batch stride nsb WS^2): one
-// launch of the super-block kernel in inverse mode.  With them every step of a narrow
-// solve is a GEMM (no sequential dependency inside a super-block).
 // The block columns below each diagonal super-block copied, conjugate-transposed, into
 // the (otherwise unused) upper triangle: A[c][r] = conj(L[r][c]) for c in super-block J
 // and r >= the end of J.  The forward solve then reads them as the backward solve reads
@@ -854,20 +836,80 @@ __global__ __launch_bounds__(256) void sb_transpose_kernel(C_t<R>* L, int n, lon
   }
 }
 
+// Seeds of the super-block inversion, one workgroup row per (matrix, super-block) item
+// b = f nsb + J: T_b = the lower triangle of the diagonal super-block L_JJ (zero above
+// the diagonal and beyond the matrix), X_b = the inverted 64 x 64 diagonal blocks from
+// the factorisation on its diagonal, zero elsewhere.  Both WS x WS, ld WS, stride WS^2.
+template <typename R, int WS>
+__global__ __launch_bounds__(256) void sb_seed_kernel(const C_t<R>* L, int n, long lda, long sL, int nsb,
+                                                      const C_t<R>* Dinv, long sD, C_t<R>* T, C_t<R>* X) {
+  typedef C_t<R> C;
+  const long e = blockIdx.x * 256L + threadIdx.x;  // element r + c WS of the block
+  const int b = blockIdx.y, f = b / nsb, J0 = (b % nsb) * WS;
+  const int r = (int)(e % WS), c = (int)(e / WS);
+  C tv = mk<R>(0, 0), xv = mk<R>(0, 0);
+  if (J0 + r < n && J0 + c < n) {
+    if (r >= c) tv = L[(long)f * sL + (J0 + r) + (long)(J0 + c) * lda];
+    if (r / 64 == c / 64) xv = Dinv[(long)f * sD + (long)((J0 + r) / 64) * 4096 + (r % 64) + (c % 64) * 64];
+  }
+  T[(long)b * WS * WS + e] = tv;
+  X[(long)b * WS * WS + e] = xv;
+}
+
+// Explicit inverses of the diagonal super-blocks of a batch of Cholesky factors
+// (WS x WS blocks, ld WS, nsb = ceil(n / WS) per matrix, batch stride nsb WS^2), by
+// recursive doubling from the factorisation's inverted 64 x 64 diagonal blocks: for a
+// lower-triangular [[L11, 0], [L21, L22]] the inverse is [[X11, 0], [-X22 L21 X11, X22]]
+// with X11, X22 the inverses of the halves.  Every (h, t) step (halves of order h = 64,
+// 128, ..; pair t of the super-block) is two GEMMs batched over all super-blocks of all
+// matrices, so the inversion runs on the matrix cores in large launches.  With the
+// inverses every step of a narrow solve is a GEMM (no sequential dependency inside a
+// super-block).  work: batch nsb (WS^2 + WS^2 / 4) elements.
 template <typename R>
 int sb_inverse_batched(C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
-                       C_t<R>* SBinv, hipStream_t st) {
+                       C_t<R>* SBinv, C_t<R>* work, hipStream_t st) {
   constexpr int WS = sizeof(R) == 4 ? 256 : 128;
   const int nsb = (n + WS - 1) / WS;
-  hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch, nsb, WS / 32), dim3(1024), 0, st,
-                     (const C_t<R>*)L, lda, sL, Dinv, sD, (const C_t<R>*)nullptr, 0L, 0L, SBinv, (long)WS,
-                     (long)nsb * WS * WS, 0, 0, 0, n);
+  const int B = batch * nsb;
+  const long S2 = (long)WS * WS;
+  C_t<R>* T = work;
+  C_t<R>* W = work + (long)B * S2;
+  hipLaunchKernelGGL((sb_seed_kernel<R, WS>), dim3((unsigned)(S2 / 256), (unsigned)B), dim3(256), 0, st,
+                     (const C_t<R>*)L, n, lda, sL, nsb, Dinv, sD, T, SBinv);
+  int e = (int)hipGetLastError();
+  if (e) return e;
+  for (int h = 64; h < WS; h *= 2)
+    for (int t = 0; t < WS / (2 * h); ++t) {
+      const long o11 = (long)(2 * t * h) * (WS + 1);  // top-left of the pair's first half
+      const long o21 = o11 + h;                       // its block below
+      const long o22 = o11 + (long)h * (WS + 1);      // the second half
+      {  // W = L21 X11
+        GemmArgs<R> g{};
+        g.M = h; g.N = h; g.K = h; g.batch = B;
+        g.A = T + o21; g.lda = WS; g.sA = S2;
+        g.B = SBinv + o11; g.ldb = WS; g.sB = S2;
+        g.Cm = W; g.ldc = h; g.sC = (long)h * h;
+        g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+        if ((e = zgemm<R>(g, 0, 0, st))) return e;
+      }
+      {  // X21 = -X22 W
+        GemmArgs<R> g{};
+        g.M = h; g.N = h; g.K = h; g.batch = B;
+        g.A = SBinv + o22; g.lda = WS; g.sA = S2;
+        g.B = W; g.ldb = h; g.sB = (long)h * h;
+        g.Cm = SBinv + o21; g.ldc = WS; g.sC = S2;
+        g.alpha = mk<R>(-1, 0); g.beta = mk<R>(0, 0);
+        if ((e = zgemm<R>(g, 0, 0, st))) return e;
+      }
+    }
   const unsigned nt = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL((sb_transpose_kernel<R, WS>), dim3(nt, nt, batch), dim3(256), 0, st, L, n, lda, sL);
   return (int)hipGetLastError();
 }
-template int sb_inverse_batched<double>(double2*, int, long, long, int, const double2*, long, double2*, hipStream_t);
-template int sb_inverse_batched<float>(float2*, int, long, long, int, const float2*, long, float2*, hipStream_t);
+template int sb_inverse_batched<double>(double2*, int, long, long, int, const double2*, long, double2*, double2*,
+                                        hipStream_t);
+template int sb_inverse_batched<float>(float2*, int, long, long, int, const float2*, long, float2*, float2*,
+                                       hipStream_t);
 
 // Narrow solve with the super-block inverses: per super-block one GEMM with the inverse
 // (or its conjugate transpose) and one GEMM for the rows beyond it.
@@ -950,7 +992,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
     hipLaunchKernelGGL((trsv_block_kernel<R, true, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, B,
-                       ldb, sB, Z, ldz, sZ, J0, T, nc, 0);
+                       ldb, sB, Z, ldz, sZ, J0, T, nc);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;
     const int rem = n - J0 - w;
@@ -971,7 +1013,7 @@ int potrs_narrow(const C_t<R>* L, int n, long lda, long sL, int batch, const C_t
     const int J0 = sbi * WS, w = std::min(WS, n - J0), T = w / 64;
     PHX_HOOK_BEGIN(PROF_TRSM_DIAG);
     hipLaunchKernelGGL((trsv_block_kernel<R, false, WS>), dim3(batch), dim3(1024), 0, st, L, lda, sL, Dinv, sD, Z,
-                       ldz, sZ, B, ldb, sB, J0, T, nc, 0);
+                       ldz, sZ, B, ldb, sB, J0, T, nc);
     PHX_HOOK_END(PROF_TRSM_DIAG, batch * 8.0 * w * (w + 64) / 2.0 * nc, batch * cb * (w * (w + 64) / 2.0 + 2.0 * w * nc));
     if ((e = (int)hipGetLastError())) return e;
     if (J0 > 0) {

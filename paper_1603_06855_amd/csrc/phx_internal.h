@@ -78,9 +78,11 @@ int potrs_batched(const C_t<R>* L, int n, long lda, long sL, int batch, const C_
 // Inverses of the diagonal super-blocks (256 wide in FP32, 128 in FP64) of a batch of
 // Cholesky factors: nsb = ceil(n / WS) blocks of WS x WS per matrix (ld WS); and the block
 // columns below the super-blocks copied, conjugate-transposed, into the upper triangle of L
-// (which the factorisation leaves unused), as the super-block solves read them.
+// (which the factorisation leaves unused), as the super-block solves read them.  Dinv: the
+// factorisation's inverted 64 x 64 diagonal blocks; n a multiple of 64; work: device
+// scratch of batch nsb (WS^2 + WS^2 / 4) elements.
 template <typename R>
 int sb_inverse_batched(C_t<R>* L, int n, long lda, long sL, int batch, const C_t<R>* Dinv, long sD,
-                       C_t<R>* SBinv, hipStream_t st);
+                       C_t<R>* SBinv, C_t<R>* work, hipStream_t st);
 
 }  // namespace phx

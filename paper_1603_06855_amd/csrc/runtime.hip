@@ -807,9 +807,10 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     constexpr int WS = sizeof(R) == 4 ? 256 : 128;
     const long nsb = (n3 + WS - 1) / WS;
     sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nkf * nsb * WS * WS);
+    C_t<R>* sbw = dbuf<C_t<R>>(ctx, "SBwork", (long)nkf * nsb * (WS * WS + WS * WS / 4));
     PROF_BEGIN(PROF_SBINV);
     KCHK(sb_inverse_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
-                               (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, st));
+                               (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, sbw, st));
     PROF_END(PROF_SBINV, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
   }
 
@@ -1725,7 +1726,8 @@ int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, cons
       if (ctx->opt.sbinv) {
         const long ws = sizeof(R) == 4 ? 256 : 128;
         sbi = dbuf<Cx>(ctx, "tS", (long)batch * ((n + ws - 1) / ws) * ws * ws);
-        KCHK(sb_inverse_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, sbi, st));
+        Cx* sbw = dbuf<Cx>(ctx, "tW", (long)batch * ((n + ws - 1) / ws) * (ws * ws + ws * ws / 4));
+        KCHK(sb_inverse_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, sbi, sbw, st));
       }
       KCHK(potrs_batched<R>(da, n, n, (long)n * n, batch, dinv, (long)(n / 64) * 4096, db, n, (long)n * nrhs, dz, n,
                             (long)n * nrhs, nrhs, st, nullptr, sbi));
