@@ -465,3 +465,27 @@ def test_kernel_class_timing(ctx):
         assert (stage > 0) if mode == 1 else (stage == 0)
     for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
         assert counts[1, c] == counts[2, c]
+
+
+@pytest.mark.parametrize("key,bad,good", [
+    ("tol_fp64", (0.0, 1.0), (1e-9,)),
+    ("block", (1, 22), (0, 21)),
+    ("drop", (0.0, 0.1), (1e-8,)),
+    ("kshare", (0, 9, 2.5), (1, 8)),
+    ("kshare_dist", (-0.1, 1.5), (0.0, 1.0)),
+    ("streams", (0, 17), (1, 16)),
+    ("profile", (3, -1), (0, 1, 2)),
+    ("spin_wait", (2,), (0, 1)),
+    ("gram_split", (-1, 17, 2.5), (0, 1, 16)),
+    ("no_such_option", (1.0,), ()),
+])
+def test_option_ranges(key, bad, good):
+    """phx_set_option rejects out-of-range values and unknown keys with PHX_EINVAL (on a
+    context of its own, so no other test sees the values set here)."""
+    with phx.Context(0) as c:
+        for v in bad:
+            with pytest.raises(phx.PhxError) as e:
+                c.set_option(key, v)
+            assert e.value.code == phx.EINVAL, (key, v)
+        for v in good:
+            c.set_option(key, v)
