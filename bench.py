@@ -36,7 +36,7 @@ def main():
     ap.add_argument("--nk", type=int, default=60)
     ap.add_argument("--M", type=int, default=5)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--streams", type=int, default=16, help="designs solved concurrently (library option)")
+    ap.add_argument("--streams", type=int, default=12, help="designs solved concurrently (library option)")
     ap.add_argument("--coarse-tol", type=float, default=None, help="library option coarse_tol")
     ap.add_argument("--shift", type=float, default=None, help="library option shift")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",

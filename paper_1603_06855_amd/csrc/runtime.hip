@@ -182,6 +182,19 @@ void hook_kev(void* u, int cls, double f, double b, hipEvent_t* e0, hipEvent_t* 
 
 }  // namespace
 
+// Statistics of several solves: the largest of the per-solve maxima, the sums of counts.
+void merge_stats(Stats& into, const Stats& s) {
+  into.iters = std::max(into.iters, s.iters);
+  into.rr_sweeps = std::max(into.rr_sweeps, s.rr_sweeps);
+  into.coarse_iters = std::max(into.coarse_iters, s.coarse_iters);
+  into.k_conv_iters += s.k_conv_iters;
+  into.factors += s.factors;
+  into.k_count += s.k_count;
+  into.chunks += s.chunks;
+  into.block = std::max(into.block, s.block);
+  into.kchunk = std::max(into.kchunk, s.kchunk);
+}
+
 struct phx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -1542,6 +1555,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
     std::vector<int> rcs(ndesign, PHX_OK);
     std::vector<std::string> errs(ndesign);
     auto work = [&](phx_ctx* w) {
+      Stats total;  // every design this worker solves (each solve resets w->stats)
       for (;;) {
         const int i = next.fetch_add(1);
         if (i >= ndesign) break;
@@ -1551,7 +1565,9 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
                           nsens > 0 ? domega_dev[d] : nullptr, nullptr, nullptr, nullptr);
         });
         if (rcs[d] != PHX_OK) errs[d] = w->err;
+        merge_stats(total, w->stats);
       }
+      w->stats = total;
     };
     if (nw == 1) {
       work(ctx->workers[0]);
@@ -1570,15 +1586,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
         ctx->prof.acc[c].count += w->prof.acc[c].count;
       }
       w->prof.reset();
-      ctx->stats.iters = std::max(ctx->stats.iters, w->stats.iters);
-      ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, w->stats.rr_sweeps);
-      ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, w->stats.coarse_iters);
-      ctx->stats.k_conv_iters += w->stats.k_conv_iters;
-      ctx->stats.factors += w->stats.factors;
-      ctx->stats.k_count += w->stats.k_count;
-      ctx->stats.chunks += w->stats.chunks;
-      ctx->stats.block = std::max(ctx->stats.block, w->stats.block);
-      ctx->stats.kchunk = std::max(ctx->stats.kchunk, w->stats.kchunk);
+      merge_stats(ctx->stats, w->stats);
     }
     int worst = PHX_OK;
     for (int d = 0; d < ndesign; ++d) {

@@ -94,7 +94,7 @@ def test_fcc_uneven_m_batch(ctx):
 
 def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
     """The benchmark's timed configuration: 16 FCC 32^3 designs at M=5, 60 k-points, 12
-    bands and the adjoint of bands 6/7 in mixed precision through one batched call on 16
+    bands and the adjoint of bands 6/7 in mixed precision through one batched call on 12
     library streams, with the benchmark's factor sharing (up to 8 k-points per factor
     within 1.0 cycles/a).  Design 0 at two k-points against the FP64 oracle: every
     frequency within 1e-6 relative and both sensitivity fields within 1e-4 of their
@@ -104,15 +104,22 @@ def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
     wl = synth.config4(all_m5=True, ndesign=16)
     q = phx.kpath("FCC", wl.nk)
     rhos = [torch.from_numpy(np.ascontiguousarray(d.reshape(-1))).to("cuda:0") for d in wl.designs]
-    ctx.set_option("streams", 16)
+    ctx.set_option("streams", 12)
     ctx.set_option("kshare", 8)
     ctx.set_option("kshare_dist", 1.0)
     try:
         t = time.time()
         oms, dws = ctx.sens_batch_dev(wl.cells, rhos, q, wl.nbands, wl.sens_bands, "mixed")
         torch.cuda.synchronize()
+        nf_batch = ctx.stat("factors")
         log("FCC 32^3 M=5 x16, 60 k, benchmark configuration:", round(time.time() - t, 2), "s; factors",
-            ctx.stat("factors"), "iters", ctx.stat("iters"))
+            nf_batch, "iters", ctx.stat("iters"))
+        # the same design alone: identical results, and the batch counts every design's
+        # factorisations (16 designs on 12 streams: workers solve several designs each)
+        om0, dw0 = ctx.sens_dev(wl.cells[0], rhos[0], q, wl.nbands, wl.sens_bands, "mixed")
+        nf_one = ctx.stat("factors")
+        assert torch.equal(oms[0], om0) and torch.equal(dws[0], dw0)
+        assert nf_batch == 16 * nf_one, (nf_batch, nf_one)
     finally:
         ctx.set_option("streams", 4)
         ctx.set_option("kshare", 2)
