@@ -612,7 +612,7 @@ void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, l
 
 void cholqr(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
-  const long n3 = sv.n3, m = sv.m;
+  const long m = sv.m;
   gram(sv, sv.Big, 2);
   PROF_BEGIN(PROF_SMALL);
   launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream, sv.kact);
@@ -627,7 +627,7 @@ void cholqr(Solver& sv) {
 
 void rayleigh_ritz(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
-  const long n3 = sv.n3, m = sv.m, s = sv.s;
+  const long m = sv.m, s = sv.s;
   gram(sv, sv.Big, 1);
   PROF_BEGIN(PROF_SMALL);
   launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream, sv.kact);
