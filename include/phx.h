@@ -121,6 +121,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * solve_upd and solve_diag, events that each launch records at its kernel's start
  * and end; 2: only the latter, which disturbs concurrent streams least),
  * "profile_reset" (any value: clears the class timers),
+ * "kstreams" (1..16, default 1): phx_bands_dev, phx_sens_dev and phx_adjoint_dev
+ * split the k-points into this many consecutive ranges solved concurrently on worker
+ * streams (one design alone leaves most of the GPU idle); each range has its own
+ * preconditioner factors and coarse start,
  * "gram_split" (0..16; 0, default: min(16, 3Np / 256)): the eigensolver's Gram
  * products S^H [K S | Omega S] are split over this many parts of their long
  * dimension (partial products summed by a second kernel; 1: one kernel),

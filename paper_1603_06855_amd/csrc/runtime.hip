@@ -62,6 +62,7 @@ struct Opts {
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
   int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
+  int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
 };
 
 struct Stats {
@@ -1160,6 +1161,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
   else if (k == "kshare_dist") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_dist = v; }
   else if (k == "kshare_rel") { if (!(v >= 0 && v <= 1)) return bad(); ctx->opt.kshare_rel = v; }
+  else if (k == "kstreams") { if (!(v >= 1 && v <= 16 && v == (int)v)) return bad(); ctx->opt.kstreams = (int)v; }
   else if (k == "gram_split") { if (!(v >= 0 && v <= 16 && v == (int)v)) return bad(); ctx->opt.gram_split = (int)v; }
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "profile") {
@@ -1488,12 +1490,103 @@ static int dev_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, i
   return rc;
 }
 
+// Worker contexts (own stream and workspaces) for concurrent solves, with the caller's
+// options and profiling settings.
+static void prepare_workers(phx_ctx* ctx, int nw) {
+  while ((int)ctx->workers.size() < nw) {
+    phx_ctx* w = nullptr;
+    if (phx_create(&w, ctx->device) != PHX_OK) fail(ctx, PHX_EHIP, "could not create a worker stream");
+    ctx->workers.push_back(w);
+  }
+  for (int i = 0; i < nw; ++i) {
+    ctx->workers[i]->opt = ctx->opt;
+    ctx->workers[i]->prof.on = ctx->prof.on;
+    ctx->workers[i]->prof.stages = ctx->prof.stages;
+    ctx->workers[i]->trace = ctx->trace;
+  }
+}
+
+// The workers' timers and statistics into the caller's.
+static void merge_workers(phx_ctx* ctx, int nw) {
+  ctx->stats = Stats();
+  for (int i = 0; i < nw; ++i) {
+    phx_ctx* w = ctx->workers[i];
+    for (int c = 0; c < PROF_NCLASS; ++c) {
+      ctx->prof.acc[c].ms += w->prof.acc[c].ms;
+      ctx->prof.acc[c].flops += w->prof.acc[c].flops;
+      ctx->prof.acc[c].bytes += w->prof.acc[c].bytes;
+      ctx->prof.acc[c].count += w->prof.acc[c].count;
+    }
+    w->prof.reset();
+    merge_stats(ctx->stats, w->stats);
+  }
+}
+
+// One design's k-points in ctx->opt.kstreams consecutive ranges, solved concurrently on
+// worker streams (a single design leaves most of the GPU idle on one stream).  Each range
+// writes its own rows of omega and of the sensitivities; for the weighted adjoint each
+// range's gradient goes to a slice of a scratch array, summed into grad_dev afterwards.
+static int dev_entry(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
+                     int nbands, phx_precision prec, int nsens, const int* band_no, double* omega_dev,
+                     double* domega_dev, const double* weight_dev, double* grad_dev, void* stream) {
+  const int np = std::min(ctx->opt.kstreams, nk);
+  if (np <= 1)
+    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, domega_dev, weight_dev,
+                    grad_dev, stream);
+  check_cell(ctx, cell);
+  check_q(ctx, q_host, nk);
+  if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const long nvox = (long)cell->nv * cell->nv * cell->nv;
+  double* parts = grad_dev ? dbuf<double>(ctx, "gparts", (long)np * nvox) : nullptr;
+  prepare_workers(ctx, np);
+  std::vector<int> rcs(np, PHX_OK);
+  std::vector<std::string> errs(np);
+  std::vector<std::thread> th;
+  for (int p = 0; p < np; ++p)
+    th.emplace_back([&, p]() {
+      phx_ctx* w = ctx->workers[p];
+      const int k0 = (int)((long)nk * p / np), k1 = (int)((long)nk * (p + 1) / np);
+      rcs[p] = guard(w, [&]() {
+        return dev_impl(w, cell, rho_dev, k1 - k0, q_host + 3L * k0, nbands, prec, nsens, band_no,
+                        omega_dev ? omega_dev + (long)k0 * nbands : nullptr,
+                        domega_dev ? domega_dev + (long)k0 * nsens * nvox : nullptr,
+                        weight_dev ? weight_dev + (long)k0 * nsens : nullptr,
+                        parts ? parts + (long)p * nvox : nullptr, nullptr);
+      });
+      if (rcs[p] != PHX_OK) errs[p] = w->err;
+    });
+  for (auto& t : th) t.join();
+  merge_workers(ctx, np);
+  int worst = PHX_OK;
+  for (int p = 0; p < np; ++p) {
+    if (rcs[p] < 0 && rcs[p] != PHX_ENOCONV) {
+      ctx->err = "k range " + std::to_string(p) + ": " + errs[p];
+      return rcs[p];
+    }
+    if (rcs[p] == PHX_ENOCONV) {
+      worst = PHX_ENOCONV;
+      ctx->err = "k range " + std::to_string(p) + ": " + errs[p];
+    }
+  }
+  if (grad_dev) {  // the workers' streams are done (each synchronised before its thread ended)
+    std::vector<double> ones(np, 1.0);
+    double* od = dbuf<double>(ctx, "gones", np);
+    HIPCHK(hipMemcpyAsync(od, ones.data(), np * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(grad_dev, 0, nvox * sizeof(double), ctx->stream));
+    launch_weighted_sum(parts, od, np, nvox, grad_dev, ctx->stream);
+    KCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return worst;
+}
+
 int phx_bands_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int nk, const double* q_host,
                   int nbands, phx_precision prec, double* omega_dev, void* stream) {
   return guard(ctx, [&]() {
     if (!omega_dev) fail(ctx, PHX_EINVAL, "omega_dev is NULL");
-    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, 0, nullptr, omega_dev, nullptr, nullptr, nullptr,
-                    stream);
+    return dev_entry(ctx, cell, rho_dev, nk, q_host, nbands, prec, 0, nullptr, omega_dev, nullptr, nullptr, nullptr,
+                     stream);
   });
 }
 
@@ -1503,8 +1596,8 @@ int phx_sens_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, int 
   return guard(ctx, [&]() {
     if (!omega_dev) fail(ctx, PHX_EINVAL, "omega_dev is NULL");
     if (nsens > 0 && !domega_dev) fail(ctx, PHX_EINVAL, "domega_dev is NULL");
-    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, domega_dev, nullptr,
-                    nullptr, stream);
+    return dev_entry(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, domega_dev, nullptr,
+                     nullptr, stream);
   });
 }
 
@@ -1514,8 +1607,8 @@ int phx_adjoint_dev(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, i
   return guard(ctx, [&]() {
     if (!weight_dev || !grad_dev) fail(ctx, PHX_EINVAL, "weight_dev or grad_dev is NULL");
     if (nsens < 1) fail(ctx, PHX_EINVAL, "nsens must be at least 1");
-    return dev_impl(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, nullptr, weight_dev,
-                    grad_dev, stream);
+    return dev_entry(ctx, cell, rho_dev, nk, q_host, nbands, prec, nsens, band_no, omega_dev, nullptr, weight_dev,
+                     grad_dev, stream);
   });
 }
 
@@ -1536,17 +1629,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
     if (stream) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     const int nw = std::min(ctx->opt.streams, ndesign);
-    while ((int)ctx->workers.size() < nw) {
-      phx_ctx* w = nullptr;
-      if (phx_create(&w, ctx->device) != PHX_OK) fail(ctx, PHX_EHIP, "could not create a worker stream");
-      ctx->workers.push_back(w);
-    }
-    for (int i = 0; i < nw; ++i) {
-      ctx->workers[i]->opt = ctx->opt;
-      ctx->workers[i]->prof.on = ctx->prof.on;
-      ctx->workers[i]->prof.stages = ctx->prof.stages;
-      ctx->workers[i]->trace = ctx->trace;
-    }
+    prepare_workers(ctx, nw);
     // most expensive designs first: the per-k cost grows like (3N)^3
     std::vector<int> order(ndesign);
     std::iota(order.begin(), order.end(), 0);
@@ -1576,18 +1659,7 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
       for (int i = 0; i < nw; ++i) th.emplace_back(work, ctx->workers[i]);
       for (auto& t : th) t.join();
     }
-    ctx->stats = Stats();
-    for (int i = 0; i < nw; ++i) {
-      phx_ctx* w = ctx->workers[i];
-      for (int c = 0; c < PROF_NCLASS; ++c) {
-        ctx->prof.acc[c].ms += w->prof.acc[c].ms;
-        ctx->prof.acc[c].flops += w->prof.acc[c].flops;
-        ctx->prof.acc[c].bytes += w->prof.acc[c].bytes;
-        ctx->prof.acc[c].count += w->prof.acc[c].count;
-      }
-      w->prof.reset();
-      merge_stats(ctx->stats, w->stats);
-    }
+    merge_workers(ctx, nw);
     int worst = PHX_OK;
     for (int d = 0; d < ndesign; ++d) {
       if (rcs[d] < 0 && rcs[d] != PHX_ENOCONV) {

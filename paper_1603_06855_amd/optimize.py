@@ -180,12 +180,18 @@ def main(argv=None):
     ap.add_argument("--beta-max", type=float, default=64.0)
     ap.add_argument("--final-M", type=int, default=None,
                     help="re-evaluate the final design at this plane-wave order (default M + 1)")
+    ap.add_argument("--kstreams", type=int, default=1,
+                    help="k-point ranges of each band solve on concurrent library streams (1..16)")
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--resume", action="store_true")
     a = ap.parse_args(argv)
+    if a.kstreams > 1:
+        # one hardware queue per stream (read when the HIP runtime starts: before any GPU use)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, a.kstreams + 1))))
     cell = synth.Cell(a.lattice, 1.0, a.nv, a.M)
     rho0 = synth.box_smoothed_uniform(a.nv, a.seed)
     ctx = phx.Context(0)
+    ctx.set_option("kstreams", a.kstreams)
     q = phx.kpath(a.lattice, a.nk)
     hpm = HPM(a.spacing, a.proj_radius, a.octant, 1.0, a.beta_max, a.beta_every) if a.hpm else None
     opt = GapOptimizer(ctx, cell, q, a.nbands, a.t, rho0, a.precision, hpm=hpm)

@@ -144,3 +144,38 @@ def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
             e = np.abs(dw[i, j] - dw_ref[i, j]).max() / np.abs(dw_ref[i, j]).max()
             log("k", ks[i], "band", b, "sensitivity error", e)
             assert e <= 1e-4
+
+
+def test_single_design_k_streams(ctx):
+    """Option kstreams: one design's k-points in three ranges on concurrent worker streams
+    (SC 16^3, M=3, 30 k-points; and FCC 32^3 at M=4, whose coarse start runs per range)
+    give the frequencies, sensitivities and weighted adjoint gradient of one stream, to
+    the mixed-precision tolerance."""
+    import torch
+    for wl, M in ((synth.config2(), None), (synth.config4(all_m5=False, ndesign=2), 4)):
+        cell = wl.cells[0] if M is None else synth.Cell("FCC", 1.0, 32, M)
+        rho = torch.from_numpy(np.ascontiguousarray(wl.designs[0].reshape(-1))).to("cuda:0")
+        q = phx.kpath(cell.lattice, 30)
+        bands = (3, 4) if M is None else (6, 7)
+        w = torch.from_numpy(np.random.default_rng(3).random((30, 2))).to("cuda:0")
+        res = {}
+        try:
+            for ks in (1, 3):
+                ctx.set_option("kstreams", ks)
+                om, dw = ctx.sens_dev(cell, rho, q, wl.nbands, bands, "mixed")
+                g = ctx.adjoint_dev(cell, rho, q, wl.nbands, bands, w, "mixed")
+                res[ks] = (om.cpu().numpy(), dw.cpu().numpy(), g.cpu().numpy())
+        finally:
+            ctx.set_option("kstreams", 1)
+        err = _rel(res[3][0], res[1][0])
+        gerr = np.abs(res[3][2] - res[1][2]).max() / np.abs(res[1][2]).max()
+        log(cell.lattice, "M", cell.M, "kstreams 3 vs 1: omega", err.max(), "gradient", gerr)
+        assert err.max() <= 1e-6 and gerr <= 1e-4
+        for k in range(30):
+            for j, b in enumerate(bands):
+                wk = res[1][0][k]
+                i = b - 1
+                if wk[i] < 1e-6 * wk.max() or min(wk[i] - wk[i - 1], wk[i + 1] - wk[i]) < 1e-4 * wk[i]:
+                    continue
+                ref = res[1][1][k, j]
+                assert np.abs(res[3][1][k, j] - ref).max() <= 1e-4 * np.abs(ref).max(), (k, b)
