@@ -86,6 +86,7 @@ def test_validate_accepts_a_good_problem():
     ({}, np.full(512, np.nan), None, 0, (), "rho"),
     ({}, np.full(512, -0.1), None, 0, (), "rho"),
     ({}, None, np.full((2, 3), np.inf), 0, (), "finite"),
+    ({}, None, np.zeros((0, 3)), 0, (), "nk must be positive"),
     ({}, None, None, 17, (), "nbands"),
     ({}, None, None, 8, (9,), "band_no"),
 ])
