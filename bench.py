@@ -43,6 +43,7 @@ def main():
                     help="any other library option (phx_set_option), repeatable")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gate", action="store_true", help="skip the mixed-vs-FP64 accuracy gate")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-copy (PCIe-inclusive) rate")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -211,6 +212,40 @@ def main():
                 "max_rel_omega_err": om_err, "max_sens_err": sens_err, "sens_skipped_degenerate": skipped,
                 "pass": bool(om_err <= 1e-6 and sens_err <= 1e-6)}
 
+    # PCIe-inclusive rate (untimed for `value`): the same steps with every design's density
+    # copied in from pinned host memory before the step and all frequencies and
+    # sensitivities copied back to pinned host memory after it.
+    host = None
+    if not args.no_host and res[1] is not None:
+        rho_h = [r.cpu().pin_memory() for r in rho_dev]
+        om_h = [torch.empty(o.shape, dtype=o.dtype, pin_memory=True) for o in res[0]]
+        dw_h = [torch.empty(d.shape, dtype=d.dtype, pin_memory=True) for d in res[1]]
+        nbytes = sum(r.numel() for r in rho_h) * 8 + sum(o.numel() for o in om_h) * 8 + sum(d.numel() for d in dw_h) * 8
+        torch.cuda.synchronize()
+        th0 = time.perf_counter()
+        for _ in range(args.steps):
+            for r_d, r_h in zip(rho_dev, rho_h):
+                r_d.copy_(r_h, non_blocking=True)
+            oms, dws = step()
+            for o_h, o in zip(om_h, oms):
+                o_h.copy_(o, non_blocking=True)
+            for d_h, d in zip(dw_h, dws):
+                d_h.copy_(d, non_blocking=True)
+            torch.cuda.synchronize()
+        th = (time.perf_counter() - th0) / args.steps
+        # the copies alone (same buffers, no solve), for their own cost
+        tc0 = time.perf_counter()
+        for r_d, r_h in zip(rho_dev, rho_h):
+            r_d.copy_(r_h, non_blocking=True)
+        for o_h, o in zip(om_h, oms):
+            o_h.copy_(o, non_blocking=True)
+        for d_h, d in zip(dw_h, dws):
+            d_h.copy_(d, non_blocking=True)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc0
+        host = {"value": args.designs * args.nk / th, "unit": "k-solves/s", "ms_per_step": 1e3 * th,
+                "bytes_per_step": nbytes, "copies_alone_ms": 1e3 * tc, "copy_GB_per_s": nbytes / tc / 1e9}
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.M)
@@ -241,6 +276,7 @@ def main():
         "accuracy_gate": gate,
         "timed_window_monotonic_ns": [w0, w1],
         "cpu_baseline": cpu,
+        "host_copies": host,
     }
     print(json.dumps(line), flush=True)
 
