@@ -46,6 +46,10 @@ extern "C" {
 #define PHX_EHIP (-3)    /* a HIP runtime call failed, or no device */
 #define PHX_ENOCONV (-4) /* eigensolver hit its iteration cap; outputs hold the last iterate */
 #define PHX_ENOTPD (-5)  /* a matrix that must be positive definite failed its Cholesky */
+/* Warning (outputs complete and valid): a band whose sensitivity was requested lies in a
+ * degenerate cluster (see phx_sens).  Eq. (15) defines d lambda / d rho_e for a simple
+ * eigenvalue only; the paper does not discuss repeated eigenvalues. */
+#define PHX_WDEGEN 1
 
 typedef struct phx_ctx phx_ctx;
 
@@ -79,7 +83,7 @@ typedef struct {
  * Returns PHX_EHIP if the device is missing. */
 int phx_create(phx_ctx** out, int hip_device);
 int phx_destroy(phx_ctx* ctx);
-/* Message of the last failed call on ctx (valid until the next call). */
+/* Message of the last call on ctx that did not return PHX_OK (valid until the next call). */
 const char* phx_last_error(const phx_ctx* ctx);
 
 /* Solver options.  Keys: "tol_fp64", "tol_mixed" (relative residual
@@ -104,13 +108,19 @@ const char* phx_last_error(const phx_ctx* ctx);
  * "kskip" (1, default: a k-point whose wanted bands all meet the tolerance is
  * frozen, its vectors, eigenvalues and residuals kept, and the remaining
  * iterations of its chunk skip it; 0: every k-point of a chunk iterates until the
- * slowest converges),
+ * slowest converges; every per-k decision of the eigensolver is taken per k-point,
+ * so with kshare = 1 a k-point's results depend neither on the other k-points of its
+ * chunk nor on the chunk size),
  * "rr_fused" (1, default: one Omega-orthonormalisation of the search basis,
  * the second folded into the Rayleigh-Ritz step in the small m x m space, except
- * in the last iterations of a solve whose residual is below 1e-13/tolerance; 0:
+ * for a k-point whose residual is below 1e-13/tolerance (the last iterations of an FP64
+ * solve), whose basis is orthonormalised twice explicitly; 0:
  * always two explicit orthonormalisations of the basis before Rayleigh-Ritz),
- * "mem_gb" (device memory budget for one k-chunk, default 64; per worker
- * context of phx_sens_batch_dev), "streams" (1..16, see phx_sens_batch_dev),
+ * "mem_gb" (device memory budget that sets the k-chunk size, default 64; per worker
+ * context of phx_sens_batch_dev), "mem_limit_gb" (hard cap on the device workspace one
+ * context, or each worker context of a batched call, may hold; 0, default: none; a
+ * workspace that would exceed it fails like a failed allocation), "streams" (1..16, see
+ * phx_sens_batch_dev),
  * "coarse" (1:
  * for M >= 4 every k-chunk is first solved at order M-2 to the residual
  * "coarse_tol", default 1e-3, and its Ritz vectors, embedded in the order-M
@@ -130,7 +140,13 @@ const char* phx_last_error(const phx_ctx* ctx);
  * dimension (partial products summed by a second kernel; 1: one kernel),
  * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
  * blocking-sync event, leaving the core to the threads of concurrent design
- * streams; 1: it spins in hipStreamSynchronize).
+ * streams; 1: it spins in hipStreamSynchronize),
+ * "degen_tol" (default 1e-8; 0 disables): consecutive frequencies of one k-point whose
+ * relative gap (omega_{i+1} - omega_i) / omega_{i+1} is below this form a degenerate
+ * cluster (see phx_sens).
+ * A k-chunk whose workspaces cannot be allocated (or would exceed mem_limit_gb) is
+ * freed and solved again with half as many k-points, down to one, before PHX_ENOMEM is
+ * returned.
  * Returns PHX_EINVAL for an unknown key or an out-of-range value. */
 int phx_set_option(phx_ctx* ctx, const char* key, double value);
 /* Statistics of the last solve: "iters" (eigensolver iterations of the
@@ -138,7 +154,9 @@ int phx_set_option(phx_ctx* ctx, const char* key, double value);
  * one Rayleigh-Ritz step needed at any k), "coarse_iters" (iterations of the
  * coarse start), "iters_mean_k" (mean over k-points of the iteration at which
  * each met the tolerance), "factors" (preconditioner factorisations of the
- * order-M solves).  "prof.<class>.<ms|flops|bytes|count>"
+ * order-M solves), "degen" (requested (k, band) entries inside a degenerate cluster),
+ * "enomem_retries" (k-chunks solved again with fewer k-points), "mem_bytes" (device
+ * workspace the context holds).  "prof.<class>.<ms|flops|bytes|count>"
  * reads the kernel-class timers (enabled with the option "profile"). */
 int phx_get_stat(const phx_ctx* ctx, const char* key, double* value);
 
@@ -195,14 +213,23 @@ int phx_bands(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, con
 /* Bands plus d omega_b / d rho_e (Eq. 15 with Eqs. 20-21) for the nsens bands
  * band_no[0..nsens) (1-based, each <= nbands), at every k-point.
  * domega_drho: nk * nsens * nv^3, order [k][sens][e].  A band with omega = 0
- * (acoustic bands at Gamma) gets a zero derivative. */
+ * (acoustic bands at Gamma) gets a zero derivative.
+ * Degenerate clusters: Eq. (15) needs a simple eigenvalue.  Where the requested band b
+ * and its neighbours form a cluster (option "degen_tol"; clusters are formed among the
+ * solver's Ritz pairs, which extend past nbands by its guard vectors), the per-vector
+ * derivatives depend on which orthonormal basis of the cluster's eigenspace the solver
+ * returned, but their sum over the cluster does not; band b then receives the mean of
+ * d omega_i / d rho_e over every member i of its cluster (basis-independent, and equal to
+ * the derivative of the cluster's mean frequency), and the call returns PHX_WDEGEN
+ * (after PHX_ENOCONV in precedence) with the outputs complete. */
 int phx_sens(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
              phx_precision prec, int nsens, const int* band_no, double* omega, double* domega_drho);
 
 /* Weighted adjoint: grad_e = sum_{k, j} weight[k * nsens + j] d omega_{band_no[j]}(k) / d rho_e,
  * i.e. the gradient of any objective of the band frequencies given its
  * partial derivatives (Eq. 15 followed by the chain rule through Eq. 10).
- * omega: nk * nbands (may be NULL); grad: nv^3. */
+ * omega: nk * nbands (may be NULL); grad: nv^3.  Derivatives inside degenerate
+ * clusters follow phx_sens (cluster means; PHX_WDEGEN). */
 int phx_adjoint(phx_ctx* ctx, const phx_cell* cell, const double* rho, int nk, const double* q, int nbands,
                 phx_precision prec, int nsens, const int* band_no, const double* weight, double* omega,
                 double* grad);

@@ -3,12 +3,18 @@
 ``BandFrequencies.apply(rho, problem)`` returns omega (nk, nbands) on the
 device; its backward is the adjoint of Eq. (15) (Methods, "Topology
 optimization formulation") evaluated in field-energy form by the HIP
-library (``phx_adjoint_dev``): for every (k, band) entry that carries a
-non-zero incoming gradient, d omega / d rho_e is reduced on the device into
+library (``phx_adjoint_dev``): d omega / d rho_e is reduced on the device into
 one weighted gradient.  Nothing is kept between forward and backward: the
 eigenvectors of the k-points that the backward needs are recomputed, which
-at large M costs less memory than storing 3N x nbands vectors per k, and for
-the hard min/max of Eq. (10) touches only two k-points.
+at large M costs less memory than storing 3N x nbands vectors per k.  Two
+ways to pick what the backward recomputes:
+
+* ``Problem.backward_bands`` given (the KS objective, whose weights touch every
+  k): those bands at every k-point, the incoming gradient's columns passed as
+  device weights with no copy to the host;
+* otherwise only the (k, band) entries with a non-zero incoming gradient,
+  found on the host (one small device-to-host copy): the hard min/max of
+  Eq. (10) touches two k-points.
 
 ``normalized_gap`` is Eq. (10) on frequencies (every gap the paper reports is
 a frequency ratio); ``ks_gap`` replaces its min/max over k by
@@ -19,7 +25,7 @@ derivatives and the library supplies d omega / d rho.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Optional
+from typing import Optional, Tuple
 
 import numpy as np
 import torch
@@ -35,6 +41,7 @@ class Problem:
     q: np.ndarray           # (nk, 3) reciprocal coordinates
     nbands: int
     precision: str = "fp64"
+    backward_bands: Optional[Tuple[int, ...]] = None  # 1-based; see the module docstring
 
 
 class BandFrequencies(torch.autograd.Function):
@@ -51,6 +58,12 @@ class BandFrequencies(torch.autograd.Function):
     def backward(ctx, g: torch.Tensor):
         (rho,) = ctx.saved_tensors
         prob: Problem = ctx.prob
+        if prob.backward_bands is not None:
+            cols = torch.tensor([b - 1 for b in prob.backward_bands], device=g.device)
+            w = g.detach().to(torch.float64).index_select(1, cols).contiguous()
+            grad = prob.ctx.adjoint_dev(prob.cell, rho.reshape(-1), prob.q, prob.nbands, prob.backward_bands, w,
+                                        prob.precision)
+            return grad.reshape(rho.shape).to(rho.dtype), None
         gh = g.detach().to("cpu", torch.float64).numpy()
         ks = np.nonzero(np.any(gh != 0, axis=1))[0]
         bs = np.nonzero(np.any(gh != 0, axis=0))[0]

@@ -51,6 +51,9 @@ void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, dou
 void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rho, const MaterialND& mat, double v,
                    double c2, const double* lam_nd, double lscale, double* out, hipStream_t st);
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st);
+// out[(k nsel + j)][e] = sum_t coef[(k nsel + j) next + t] in[(k next + t)][e], for k < nk, j < nsel.
+void launch_combine_cols(const double* in, int next, const double* coef, int nsel, int nk, long nvox, double* out,
+                         hipStream_t st);
 
 // design.hip: Heaviside projection of a (reduced, optionally octant-mirrored) design field.
 void launch_project(int nv, int sp, double r, double beta, int oct, const double* x, double* rho, hipStream_t st);

@@ -426,6 +426,21 @@ __global__ void weighted_sum_kernel(const double* sens, const double* wgt, int n
   grad[e] = acc;
 }
 
+// out[row][e] = sum_t coef[row][t] in[k next + t][e] with k = row / nsel: each requested
+// (k, band) entry as a fixed combination of the computed columns of its k-point (the mean
+// over a degenerate cluster); terms in column order, zero coefficients skipped.
+__global__ void combine_cols_kernel(const double* in, int next, const double* coef, int nsel, long nvox, double* out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= nvox) return;
+  const int row = blockIdx.y, k = row / nsel;
+  double acc = 0;
+  for (int t = 0; t < next; ++t) {
+    const double c = coef[(long)row * next + t];
+    if (c != 0) acc += c * in[((long)k * next + t) * nvox + e];
+  }
+  out[(long)row * nvox + e] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -575,6 +590,12 @@ void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rh
 
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st) {
   hipLaunchKernelGGL(weighted_sum_kernel, dim3(nblk(nvox, 256)), dim3(256), 0, st, sens, wgt, ncols, nvox, grad);
+}
+
+void launch_combine_cols(const double* in, int next, const double* coef, int nsel, int nk, long nvox, double* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(combine_cols_kernel, dim3(nblk(nvox, 256), (unsigned)(nk * nsel)), dim3(256), 0, st, in, next,
+                     coef, nsel, nvox, out);
 }
 
 }  // namespace phx

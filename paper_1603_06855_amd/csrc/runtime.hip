@@ -63,6 +63,8 @@ struct Opts {
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
   int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
   int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
+  double degen_tol = 1e-8;   // bands closer than this (relative, in omega) form one degenerate cluster
+  double mem_limit_gb = 0;   // cap on the device workspace a context may hold (0: none)
 };
 
 struct Stats {
@@ -71,6 +73,8 @@ struct Stats {
   int coarse_iters = 0;  // eigensolver iterations of the coarse start (slowest chunk)
   long k_conv_iters = 0, k_count = 0;  // sum over k of the iteration at which k converged
   long factors = 0;                     // preconditioner factorisations (order M solves)
+  long degen = 0;                       // (k, requested band) entries inside a degenerate cluster
+  int enomem_retries = 0;               // k-chunks retried with half as many k-points after ENOMEM
 };
 
 // Kernel-class timing with HIP events recorded on the context stream.
@@ -194,6 +198,8 @@ void merge_stats(Stats& into, const Stats& s) {
   into.chunks += s.chunks;
   into.block = std::max(into.block, s.block);
   into.kchunk = std::max(into.kchunk, s.kchunk);
+  into.degen += s.degen;
+  into.enomem_retries += s.enomem_retries;
 }
 
 struct phx_ctx {
@@ -202,6 +208,7 @@ struct phx_ctx {
   bool own_stream = true;
   std::string err;
   std::map<std::string, DevBuf> bufs;
+  size_t mem_used = 0;  // bytes held in bufs
   int* dflag = nullptr;
   Opts opt;
   Stats stats;
@@ -259,7 +266,13 @@ T* dbuf(phx_ctx* ctx, const std::string& name, size_t count) {
   DevBuf& b = ctx->bufs[name];
   const size_t need = std::max<size_t>(count * sizeof(T), 256);
   if (b.bytes < need) {
+    const double lim = ctx->opt.mem_limit_gb * 1073741824.0;
+    if (lim > 0 && (double)(ctx->mem_used - b.bytes + need) > lim) {
+      ctx->err = "workspace " + name + " (" + std::to_string(need) + " bytes) would exceed mem_limit_gb";
+      throw Fail{PHX_ENOMEM};
+    }
     if (b.p) HIPCHK(hipFree(b.p));
+    ctx->mem_used -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
     hipError_t e = hipMalloc(&b.p, need);
@@ -269,8 +282,26 @@ T* dbuf(phx_ctx* ctx, const std::string& name, size_t count) {
       throw Fail{PHX_ENOMEM};
     }
     b.bytes = need;
+    ctx->mem_used += need;
   }
   return (T*)b.p;
+}
+
+// Frees every workspace except the per-design data (names with a design tag) and the
+// sensitivity output of the call in progress; after a device wait, so no queued kernel
+// still reads them.
+void release_workspaces(phx_ctx* ctx) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (auto it = ctx->bufs.begin(); it != ctx->bufs.end();) {
+    const std::string& n = it->first;
+    if (n.rfind("d0:", 0) == 0 || n.rfind("c0:", 0) == 0 || n == "sens") {
+      ++it;
+      continue;
+    }
+    if (it->second.p) HIPCHK(hipFree(it->second.p));
+    ctx->mem_used -= it->second.bytes;
+    it = ctx->bufs.erase(it);
+  }
 }
 
 // Pinned host staging area of at least `bytes` (grow-only, one per context).
@@ -511,8 +542,11 @@ struct Solver {
   void* Dinv;  // nk x n3/64 x 4096 (prec)
   void* SBinv; // nk x nsb x WS^2 inverses of the factor's diagonal super-blocks, or NULL
   int* kact;   // per k: 1 while a wanted band of that k-point has not met the tolerance
+  int* kfar;   // per k: active and not yet near convergence (folded Rayleigh-Ritz)
+  int* knear;  // per k: active and near convergence (explicit re-orthonormalisation, images recomputed)
   int* fmap;   // per k: index of its preconditioner factor (NULL: its own)
   int nact;    // active k-points (host count of kact)
+  int nfar, nnear;
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -548,15 +582,20 @@ const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
 // starting at column c0; results to the same columns of the KS and OS blocks.
 // The strain blocks Y (Np x 6 ncol per k) and traces t (Np x ncol per k) of all k
 // are contiguous, so the two compliance products are single GEMMs over every k.
-void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
+// msk (device, per k; NULL: sv.kact) selects the k-points, nm counts them.
+void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = nullptr, int nm = -1) {
   phx_ctx* ctx = sv.ctx;
   Design& d = *sv.d;
   hipStream_t st = ctx->stream;
   const long n3 = sv.n3, m = sv.m;
+  if (!msk) {
+    msk = sv.kact;
+    nm = sv.nact;
+  }
   double2* X = Big + c0 * n3;
-  const double Np = d.Np, nk = sv.nact;  // algorithmic work counts the active k-points only
+  const double Np = d.Np, nk = nm;  // algorithmic work counts the selected k-points only
   PROF_BEGIN(PROF_APPLY);
-  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, sv.kact);
+  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
   // algorithmic flops of an operator product: 8 Np^2 per column; the operator is read
@@ -569,28 +608,34 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol) {
   const long sy = (long)d.Np * ny;
   PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * ny * nk, 16.0 * (Np * Np + 2.0 * Np * ny * nk));
   gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
-               nullptr, 1, sv.kact, 1);
+               nullptr, 1, msk, 1);
   PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
   gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
                nullptr, 1);
   PROF_BEGIN(PROF_APPLY);
-  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, sv.kact);
+  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
   PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
   gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
-               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1, sv.kact, 1);
+               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1, msk, 1);
 }
 
-void gram(Solver& sv, double2* Big, int block) {
+// The k-point selection of one eigensolver step: a device mask and its host count.
+struct Sel {
+  const int* d;
+  int n;
+};
+
+void gram(Solver& sv, double2* Big, int block, Sel k) {
   // G_k = S_k^H (block_k), block 1 = KS, 2 = OS
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
-               m * m, ONE, ZERO, sv.ksplit, sv.Gpart, 0, sv.kact, 1);
-  PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * sv.nact, 16.0 * 2 * m * 3.0 * sv.d->N * sv.nact);
+               m * m, ONE, ZERO, sv.ksplit, sv.Gpart, 0, k.d, 1);
+  PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * k.n, 16.0 * 2 * m * 3.0 * sv.d->N * k.n);
 }
 
 // Basis update in place, for every k and each of the blocks S, KS, Omega S (batch 3 nk,
@@ -603,68 +648,69 @@ void gram(Solver& sv, double2* Big, int block) {
 // of the tiled kernel) reads a row's whole K range before it writes that row, and no two
 // workgroups share a row, so reading and writing the same array is safe.  Frozen
 // k-points are skipped and keep their basis.
-void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, long sC, long c0, int split) {
+void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, long sC, long c0, int split,
+                     const int* msk) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
   if (ncol > 64 || K > 64) fail(ctx, PHX_EINVAL, "in-place basis update needs at most 64 columns");
   gemm<double>(ctx, 0, 0, n3, ncol, K, 3 * sv.nk, sv.Big + a0 * n3, n3, n3 * m, 1, C, m, sC, 3, sv.Big + c0 * n3, n3,
-               n3 * m, ONE, ZERO, 1, nullptr, 0, sv.kact, 3, split, split);
+               n3 * m, ONE, ZERO, 1, nullptr, 0, msk, 3, split, split);
 }
 
-void cholqr(Solver& sv) {
+void cholqr(Solver& sv, Sel k) {
   phx_ctx* ctx = sv.ctx;
   const long m = sv.m;
-  gram(sv, sv.Big, 2);
+  gram(sv, sv.Big, 2, k);
   PROF_BEGIN(PROF_SMALL);
-  launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream, sv.kact);
+  launch_chol_drop(sv.G, m, sv.nk, ctx->opt.drop, sv.C0, sv.keep, ctx->stream, k.d);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
   // (in place: see update_in_place)
   PROF_BEGIN(PROF_UPDATE);
-  update_in_place(sv, 0, m, m, sv.C0, m * m, 0, 0);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * sv.nact, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * sv.nact);
+  update_in_place(sv, 0, m, m, sv.C0, m * m, 0, 0, k.d);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * k.n, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * k.n);
 }
 
-void rayleigh_ritz(Solver& sv) {
+void rayleigh_ritz(Solver& sv, Sel k) {
   phx_ctx* ctx = sv.ctx;
   const long m = sv.m, s = sv.s;
-  gram(sv, sv.Big, 1);
+  gram(sv, sv.Big, 1, k);
   PROF_BEGIN(PROF_SMALL);
-  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream, sv.kact);
+  launch_rr_eig(sv.G, sv.keep, m, s, sv.nk, sv.Cr, sv.theta, sv.sweeps, ctx->stream, k.d);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   // X <- [S] Cr ; P <- [W P] Cr[s:m]
   PROF_BEGIN(PROF_UPDATE);
   // In place (see update_in_place), X first: it reads the whole old basis and writes only
   // X, which the product for P does not read; P then reads W and the old P and writes P.
-  update_in_place(sv, 0, s, m, sv.Cr, m * s, 0, 0);
-  update_in_place(sv, s, s, m - s, sv.Cr + s, m * s, 2 * s, 0);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * sv.nact,
-           16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
+  update_in_place(sv, 0, s, m, sv.Cr, m * s, 0, 0, k.d);
+  update_in_place(sv, s, s, m - s, sv.Cr + s, m * s, 2 * s, 0, k.d);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * k.n,
+           16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * k.n);
 }
 
 // Rayleigh-Ritz on the once-orthonormalised basis: both Gram matrices S^H [KS | Omega S]
 // in one GEMM, the small kernel re-orthonormalises in the m x m space and solves the
 // projected problem, and the Ritz vectors X and previous directions P are formed from
 // the whole basis with the combined coefficients.
-void rayleigh_ritz_fused(Solver& sv) {
+void rayleigh_ritz_fused(Solver& sv, Sel k) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
-               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, sv.kact, 1);
-  PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * sv.nact, 16.0 * 3 * m * 3.0 * sv.d->N * sv.nact);
+               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, k.d, 1);
+  PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * k.n, 16.0 * 3 * m * 3.0 * sv.d->N * k.n);
   PROF_BEGIN(PROF_SMALL);
   // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
   // the basis produces both: columns 0..s-1 -> X, s..2s-1 -> P (basis columns 2s..3s-1)
   launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cp, sv.Cp + m * s, sv.theta, sv.sweeps,
-                ctx->stream, sv.kact, 2 * m * s);
+                ctx->stream, k.d, 2 * m * s);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
-  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s);
-  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * sv.nact, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * sv.nact);
+  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s, k.d);
+  PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * k.n, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * k.n);
 }
 
 template <typename R>
@@ -830,10 +876,18 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
 
   // Per-k activity: every k-point starts active; one whose wanted bands all meet the
   // tolerance is frozen (its basis, Ritz values and residual norms stay as they were)
-  // and the remaining iterations skip it.
-  std::vector<int> act_h(nk, 1);
+  // and the remaining iterations skip it.  An active k-point is "far" until its own
+  // residual falls below 1e-13/tol, then "near" (see the loop).  Every choice is made per
+  // k-point, so a k-point's iterates do not depend on which other k-points share its chunk.
+  std::vector<int> act_h(nk, 1), far_h(nk, 1), near_h(nk, 0);
+  std::vector<char> near_k(nk, 0);
+  sv.kfar = dbuf<int>(ctx, "kfar", nk);
+  sv.knear = dbuf<int>(ctx, "knear", nk);
   HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
-  sv.nact = nk;
+  HIPCHK(hipMemcpyAsync(sv.kfar, far_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  sv.nact = sv.nfar = nk;
+  sv.nnear = 0;
 
   // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
@@ -852,28 +906,32 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   std::vector<char> kdone(nk, 0);
   out.converged = false;
   int it = 0;
-  bool near = false;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
-    cholqr(sv);
+    const Sel all{sv.kact, sv.nact}, far{sv.kfar, sv.nfar}, nearsel{sv.knear, sv.nnear};
+    cholqr(sv, all);
     // The folded form multiplies the Gram matrix of K by the second orthonormalisation's
     // coefficients in the small space, which amplifies its rounding when the basis is
-    // nearly dependent; near convergence (the same test as for recomputing the images)
+    // nearly dependent; near convergence (a k-point whose residual is below 1e-13/tol)
     // the second orthonormalisation is applied to the basis explicitly.
-    if (ctx->opt.rr_fused && !near) {
-      rayleigh_ritz_fused(sv);
+    if (ctx->opt.rr_fused) {
+      if (sv.nfar > 0) rayleigh_ritz_fused(sv, far);
+      if (sv.nnear > 0) {
+        cholqr(sv, nearsel);
+        rayleigh_ritz(sv, nearsel);
+      }
     } else {
-      cholqr(sv);
-      rayleigh_ritz(sv);
+      cholqr(sv, all);
+      rayleigh_ritz(sv, all);
     }
     // The images K X, Omega X (and those of the previous direction P) follow the basis
     // through the same coefficient updates.  Their rounding drift grows like the unit
-    // roundoff over the size of P, which shrinks with the residual, so once the residual
-    // is small enough for that drift to reach the tolerance they are recomputed from
-    // the Ritz vectors every iteration (with FP64 unit roundoff: residual below 1e-13/tol,
-    // i.e. only the last iterations of an FP64-tolerance solve).
-    if (it > 0 && near) {
-      apply_ops(sv, sv.Big, 0, s);
-      apply_ops(sv, sv.Big, 2 * s, s);
+    // roundoff over the size of P, which shrinks with the residual, so once a k-point's
+    // residual is small enough for that drift to reach the tolerance its images are
+    // recomputed from the vectors every iteration (with FP64 unit roundoff: residual below
+    // 1e-13/tol, i.e. only the last iterations of an FP64-tolerance solve).
+    if (sv.nnear > 0) {
+      apply_ops(sv, sv.Big, 0, s, sv.knear, sv.nnear);
+      apply_ops(sv, sv.Big, 2 * s, s, sv.knear, sv.nnear);
     }
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
@@ -911,11 +969,9 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
           ctx->stats.k_count += 1;
         }
       }
+      if (!(wk == wk)) fail(ctx, PHX_EHIP, "eigensolver produced a non-finite residual");
+      if (wk < 1e-13 / tol) near_k[k] = 1;
       worst = std::max(worst, wk);
-    }
-    if (ctx->opt.kskip && worst > tol) {
-      HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
-      sv.nact = (int)std::count(act_h.begin(), act_h.end(), 1);
     }
     if (ctx->trace) {
       std::vector<int> kh((size_t)nk * m);
@@ -932,13 +988,33 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       for (int j = 0; j < std::min(s, 6); ++j) fprintf(stderr, " %.2e", rn_h[j]);
       fprintf(stderr, "\n");
     }
-    if (!(worst == worst)) fail(ctx, PHX_EHIP, "eigensolver produced a non-finite residual");
     if (worst <= tol) {
       out.converged = true;
       break;
     }
-    near = near || worst < 1e-13 / tol;
     if (it == ctx->opt.maxit) break;
+    // masks for the next iteration
+    {
+      int na = 0, nf = 0, nn = 0;
+      bool chg = false;
+      for (int k = 0; k < nk; ++k) {
+        const int f = act_h[k] && !near_k[k], n = act_h[k] && near_k[k];
+        chg = chg || f != far_h[k] || n != near_h[k];
+        far_h[k] = f;
+        near_h[k] = n;
+        na += act_h[k];
+        nf += f;
+        nn += n;
+      }
+      if (chg) {
+        HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sv.kfar, far_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+      }
+      sv.nact = na;
+      sv.nfar = nf;
+      sv.nnear = nn;
+    }
     precondition<R>(sv);
     apply_ops(sv, sv.Big, s, s);
   }
@@ -991,44 +1067,114 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
   KCHK(hipGetLastError());
 }
 
+// Sensitivities of the requested bands sel (0-based) of every k of a converged chunk into
+// out (device, (nk * nsel) x nvox), with the degenerate-cluster convention: the Ritz values
+// theta (host, nk x s) are grouped into clusters of consecutive frequencies whose relative
+// gap is below degen_tol, and a requested band inside a cluster of two or more receives the
+// mean of the per-vector derivatives of all the cluster's members.  Eq. (15) holds for a
+// simple eigenvalue only; inside a cluster any orthonormal basis of the eigenspace is as
+// good as another and the per-vector values depend on it, while their sum (and so the mean)
+// does not.  Returns the number of requested (k, band) entries that lie in a cluster.
+long chunk_sensitivities(Solver& sv, const std::vector<double>& theta, const std::vector<int>& sel, double* out) {
+  phx_ctx* ctx = sv.ctx;
+  const int nk = sv.nk, s = sv.s, nsel = (int)sel.size();
+  const double dtol = ctx->opt.degen_tol;
+  std::vector<int> lo((size_t)nk * nsel), hi((size_t)nk * nsel);
+  std::vector<char> use(s, 0);
+  for (int b : sel) use[b] = 1;
+  auto om = [&](int k, int i) { return sqrt(std::max(theta[(size_t)k * s + i], 0.0)); };
+  long ndeg = 0;
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nsel; ++j) {
+      int l = sel[j], h = sel[j];
+      if (dtol > 0 && theta[(size_t)k * s + sel[j]] > 0) {
+        while (l > 0 && om(k, l) - om(k, l - 1) < dtol * om(k, l)) --l;
+        while (h + 1 < s && om(k, h + 1) - om(k, h) < dtol * om(k, h + 1)) ++h;
+      }
+      lo[(size_t)k * nsel + j] = l;
+      hi[(size_t)k * nsel + j] = h;
+      if (h > l) {
+        ++ndeg;
+        for (int i = l; i <= h; ++i) use[i] = 1;
+      }
+    }
+  if (ndeg == 0) {
+    adjoint_chunk(sv, sel, out);
+    return 0;
+  }
+  std::vector<int> ext;
+  for (int i = 0; i < s; ++i)
+    if (use[i]) ext.push_back(i);
+  const int next = (int)ext.size();
+  const long nvox = sv.d->nvox;
+  double* tmp = dbuf<double>(ctx, "sens_ext", (long)nk * next * nvox);
+  adjoint_chunk(sv, ext, tmp);
+  std::vector<double> coef((size_t)nk * nsel * next, 0.0);
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nsel; ++j) {
+      const int l = lo[(size_t)k * nsel + j], h = hi[(size_t)k * nsel + j];
+      for (int t = 0; t < next; ++t)
+        if (ext[t] >= l && ext[t] <= h) coef[((size_t)k * nsel + j) * next + t] = 1.0 / (h - l + 1);
+    }
+  double* cd = dbuf<double>(ctx, "sens_coef", (long)coef.size());
+  HIPCHK(hipMemcpyAsync(cd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  launch_combine_cols(tmp, next, cd, nsel, nk, nvox, out, ctx->stream);
+  KCHK(hipGetLastError());
+  // the host coefficients must outlive the copy
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ndeg;
+}
+
 // Runs the eigensolver over k-chunks; fills omega (+ err bounds) and, when sel is
 // non-empty, the per-(k, band) sensitivities into sens_dev (device).
 // dc (may be NULL): the same design at a lower plane-wave order; each chunk is then
 // first solved there to a loose tolerance and its Ritz vectors start the full solve.
+// A chunk whose workspaces do not fit (PHX_ENOMEM: a failed allocation, or the option
+// mem_limit_gb) is retried with half as many k-points, down to one.
+// Returns PHX_OK, PHX_ENOCONV, or PHX_WDEGEN when a requested band lies in a cluster.
 int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int prec, double* omega, double* ebound,
                const std::vector<int>& sel, double* sens_dev, Design* dc = nullptr) {
   const int s = choose_block(ctx, nb, d.N);
   const long per = per_k_bytes(d, s, prec);
   int kc = (int)std::max<long>(1, std::min<long>(nk, (long)(ctx->opt.mem_gb * 1073741824.0) / per));
+  ctx->stats = Stats();
   ctx->stats.block = s;
   ctx->stats.kchunk = kc;
-  ctx->stats.chunks = 0;
-  ctx->stats.iters = 0;
-  ctx->stats.rr_sweeps = 0;
-  ctx->stats.coarse_iters = 0;
-  ctx->stats.k_conv_iters = 0;
-  ctx->stats.factors = 0;
-  ctx->stats.k_count = 0;
   bool conv = true;
-  for (int k0 = 0; k0 < nk; k0 += kc) {
+  for (int k0 = 0; k0 < nk;) {
     const int nkc = std::min(kc, nk - k0);
+    const Stats before = ctx->stats;
     ChunkOut co;
     Solver sv{};
-    const double2* init = nullptr;
-    if (dc) {
-      ChunkOut cc;
-      Solver svc{};
-      if (prec == PHX_FP64) solve_chunk<double>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
-      else solve_chunk<float>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
-      ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, cc.iters);
-      double2* xi = dbuf<double2>(ctx, "Xinit", (long)nkc * d.n3 * s);
-      launch_zero(xi, (long)nkc * d.n3 * s, ctx->stream);
-      launch_prolong(svc.Big, dc->n3, svc.sBig, dc->M, dc->Np, xi, d.n3, d.n3 * s, d.M, d.Np, s, nkc, ctx->stream);
-      KCHK(hipGetLastError());
-      init = xi;
+    try {
+      const double2* init = nullptr;
+      if (dc) {
+        ChunkOut cc;
+        Solver svc{};
+        if (prec == PHX_FP64) solve_chunk<double>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
+        else solve_chunk<float>(ctx, *dc, q + 3L * k0, nkc, nb, cc, svc, nullptr, ctx->opt.coarse_tol);
+        ctx->stats.coarse_iters = std::max(ctx->stats.coarse_iters, cc.iters);
+        double2* xi = dbuf<double2>(ctx, "Xinit", (long)nkc * d.n3 * s);
+        launch_zero(xi, (long)nkc * d.n3 * s, ctx->stream);
+        launch_prolong(svc.Big, dc->n3, svc.sBig, dc->M, dc->Np, xi, d.n3, d.n3 * s, d.M, d.Np, s, nkc, ctx->stream);
+        KCHK(hipGetLastError());
+        init = xi;
+      }
+      if (prec == PHX_FP64) solve_chunk<double>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
+      else solve_chunk<float>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
+      if (!sel.empty())
+        ctx->stats.degen += chunk_sensitivities(sv, co.theta, sel, sens_dev + (long)k0 * sel.size() * d.nvox);
+    } catch (const Fail& f) {
+      if (f.code != PHX_ENOMEM || kc == 1) throw;
+      const std::string why = ctx->err;
+      release_workspaces(ctx);
+      ctx->stats = before;
+      kc = std::max(1, kc / 2);
+      ctx->stats.kchunk = kc;
+      ctx->stats.enomem_retries++;
+      if (ctx->trace) fprintf(stderr, "[phx] %s: retrying with %d k-points per chunk\n", why.c_str(), kc);
+      continue;
     }
-    if (prec == PHX_FP64) solve_chunk<double>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
-    else solve_chunk<float>(ctx, d, q + 3L * k0, nkc, nb, co, sv, init);
     ctx->stats.chunks++;
     ctx->stats.iters = std::max(ctx->stats.iters, co.iters);
     conv = conv && co.converged;
@@ -1042,13 +1188,18 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
           ebound[(size_t)(k0 + k) * nb + j] = om > 0 ? std::min(bl / om, sqrt(bl)) : sqrt(bl);
         }
       }
-    if (!sel.empty()) adjoint_chunk(sv, sel, sens_dev + (long)k0 * sel.size() * d.nvox);
+    k0 += nkc;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->prof.flush();
   if (!conv) {
     ctx->err = "eigensolver reached maxit before every band met the tolerance";
     return PHX_ENOCONV;
+  }
+  if (ctx->stats.degen > 0) {
+    ctx->err = std::to_string(ctx->stats.degen) +
+               " requested (k, band) entries lie in degenerate clusters; their sensitivities are cluster means";
+    return PHX_WDEGEN;
   }
   return PHX_OK;
 }
@@ -1061,6 +1212,13 @@ Design* coarse_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host
   cc.M = cell.M - 2;
   setup_design(ctx, cc, rho_host, rho_dev, dc, "c0:");
   return &dc;
+}
+
+// Status of several solves: the first error wins (caller's business), then PHX_ENOCONV,
+// then the warning PHX_WDEGEN, then PHX_OK.
+int worse_status(int a, int b) {
+  auto rank = [](int r) { return r == PHX_ENOCONV ? 2 : (r == PHX_WDEGEN ? 1 : 0); };
+  return rank(b) > rank(a) ? b : a;
 }
 
 int guard(phx_ctx* ctx, const std::function<int()>& f) {
@@ -1084,6 +1242,8 @@ int guard(phx_ctx* ctx, const std::function<int()>& f) {
 void check_bands(phx_ctx* ctx, const phx_cell* cell, int nb, int nsens, const int* band_no) {
   const int L = 2 * cell->M + 1;
   if (nb < 1 || nb > 16 || nb > 3 * L * L * L) fail(ctx, PHX_EINVAL, "nbands must be in [1, min(16, 3N)]");
+  if (ctx->opt.block > 0 && ctx->opt.block <= nb && ctx->opt.block < 3 * L * L * L)
+    fail(ctx, PHX_EINVAL, "option block must exceed nbands (the search block holds the wanted bands and guards)");
   if (nsens < 0) fail(ctx, PHX_EINVAL, "nsens must be non-negative");
   if (nsens > 0 && !band_no) fail(ctx, PHX_EINVAL, "band_no is NULL");
   for (int j = 0; j < nsens; ++j)
@@ -1164,6 +1324,8 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kstreams") { if (!(v >= 1 && v <= 16 && v == (int)v)) return bad(); ctx->opt.kstreams = (int)v; }
   else if (k == "gram_split") { if (!(v >= 0 && v <= 16 && v == (int)v)) return bad(); ctx->opt.gram_split = (int)v; }
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
+  else if (k == "degen_tol") { if (!(v >= 0 && v < 1e-2)) return bad(); ctx->opt.degen_tol = v; }
+  else if (k == "mem_limit_gb") { if (!(v >= 0 && v < 1e6)) return bad(); ctx->opt.mem_limit_gb = v; }
   else if (k == "profile") {
     if (!(v == 0 || v == 1 || v == 2)) return bad();
     ctx->prof.on = v != 0;
@@ -1185,6 +1347,9 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "coarse_iters") *value = ctx->stats.coarse_iters;
   else if (k == "factors") *value = (double)ctx->stats.factors;
   else if (k == "iters_mean_k") *value = ctx->stats.k_count ? (double)ctx->stats.k_conv_iters / ctx->stats.k_count : 0;
+  else if (k == "degen") *value = (double)ctx->stats.degen;
+  else if (k == "enomem_retries") *value = ctx->stats.enomem_retries;
+  else if (k == "mem_bytes") *value = (double)ctx->mem_used;
   else if (k.rfind("prof.", 0) == 0) {
     const size_t dot = k.rfind('.');
     const std::string cls = k.substr(5, dot - 5), f = k.substr(dot + 1);
@@ -1387,7 +1552,6 @@ static int bands_impl(phx_ctx* ctx, const phx_cell* cell, const double* rho, int
   Design dcs;
   Design* dc = coarse_design(ctx, *cell, rho, nullptr, dcs);
   int rc = run_design(ctx, d, q, nk, nbands, prec, omega, ebound, sel, sens, dc);
-  if (rc != PHX_OK && rc != PHX_ENOCONV) return rc;
   hipStream_t st = ctx->stream;
   if (nsens > 0 && domega) {
     HIPCHK(hipMemcpyAsync(domega, sens, (long)nk * nsens * nvox * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1441,13 +1605,18 @@ int phx_bands_batch(phx_ctx* ctx, int ndesign, const phx_cell* cells, const doub
   return guard(ctx, [&]() {
     if (ndesign < 1 || !cells || !rho || !omega) fail(ctx, PHX_EINVAL, "ndesign, cells, rho and omega are required");
     int worst = PHX_OK;
+    std::string msg, wmsg;
     for (int i = 0; i < ndesign; ++i) {
       if (!omega[i]) fail(ctx, PHX_EINVAL, "omega[d] is NULL");
       const int rc = bands_impl(ctx, &cells[i], rho[i], nk, q, nbands, prec, (domega && domega[i]) ? nsens : 0,
                                 band_no, omega[i], nullptr, domega ? domega[i] : nullptr, nullptr, nullptr);
-      if (rc < 0 && rc != PHX_ENOCONV) return rc;
-      if (rc == PHX_ENOCONV) worst = rc;
+      if (rc != PHX_OK) msg = "design " + std::to_string(i) + ": " + ctx->err;
+      if (worse_status(worst, rc) != worst) {
+        worst = rc;
+        wmsg = msg;
+      }
     }
+    ctx->err = wmsg;
     return worst;
   });
 }
@@ -1564,8 +1733,8 @@ static int dev_entry(phx_ctx* ctx, const phx_cell* cell, const double* rho_dev, 
       ctx->err = "k range " + std::to_string(p) + ": " + errs[p];
       return rcs[p];
     }
-    if (rcs[p] == PHX_ENOCONV) {
-      worst = PHX_ENOCONV;
+    if (worse_status(worst, rcs[p]) != worst) {
+      worst = rcs[p];
       ctx->err = "k range " + std::to_string(p) + ": " + errs[p];
     }
   }
@@ -1666,8 +1835,8 @@ int phx_sens_batch_dev(phx_ctx* ctx, int ndesign, const phx_cell* cells, const d
         ctx->err = "design " + std::to_string(d) + ": " + errs[d];
         return rcs[d];
       }
-      if (rcs[d] == PHX_ENOCONV) {
-        worst = PHX_ENOCONV;
+      if (worse_status(worst, rcs[d]) != worst) {
+        worst = rcs[d];
         ctx->err = "design " + std::to_string(d) + ": " + errs[d];
       }
     }

@@ -80,7 +80,10 @@ class GapOptimizer:
     def __init__(self, ctx: "phx.Context", cell, q: np.ndarray, nbands: int, t: int, rho0: np.ndarray,
                  precision: str = "mixed", beta: float = 100.0, radius: float = 1.5, step: float = 0.05,
                  device: str = "cuda:0", hpm: Optional[HPM] = None):
-        self.prob = autograd.Problem(ctx, cell, np.ascontiguousarray(q, dtype=np.float64), nbands, precision)
+        # the KS aggregate weights bands t and t+1 at every k: the backward takes those two
+        # bands at all k-points straight from the device gradient
+        self.prob = autograd.Problem(ctx, cell, np.ascontiguousarray(q, dtype=np.float64), nbands, precision,
+                                     backward_bands=(t, t + 1))
         self.t = t
         self.beta = beta
         self.step_size = step
@@ -98,6 +101,7 @@ class GapOptimizer:
                 r0 = np.ascontiguousarray(r0[: nn // 2, : nn // 2, : nn // 2])
         self.x = torch.from_numpy(np.ascontiguousarray(r0)).to(device)
         self.it = 0
+        self.last_grad: Optional[torch.Tensor] = None  # d(KS gap)/dx of the last step
         self.omega_ref: Optional[float] = None
         self.hist = History()
 
@@ -123,6 +127,7 @@ class GapOptimizer:
         f = autograd.ks_gap(om, self.t, self.beta, self.omega_ref)
         f.backward()
         g = x.grad.detach()
+        self.last_grad = g
         gmax = float(g.abs().max())
         with torch.no_grad():
             if gmax > 0:

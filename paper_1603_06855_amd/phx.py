@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libphx.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENOTPD = 0, -1, -2, -3, -4, -5
+WDEGEN = 1  # warning: a requested band lies in a degenerate cluster (its sensitivity is the cluster mean)
 LATTICE = {"SC": 0, "BCC": 1, "FCC": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
@@ -168,6 +169,8 @@ class Context:
         if rc != OK:
             raise PhxError(rc, "phx_create failed (no HIP device?)")
         self.h = h
+        self.last_status = OK
+        self.last_message = ""
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -189,16 +192,24 @@ class Context:
         self.close()
 
     def _check(self, rc: int, allow=()):
-        if rc != OK and rc not in allow:
-            raise PhxError(rc, self.lib.phx_last_error(self.h).decode())
+        """Raise on an error; warnings (PHX_WDEGEN) and the codes in `allow` are recorded in
+        last_status / last_message instead."""
+        self.last_status = rc
+        self.last_message = self.lib.phx_last_error(self.h).decode() if rc != OK else ""
+        if rc < 0 and rc not in allow:
+            raise PhxError(rc, self.last_message)
         return rc
 
     def set_option(self, key: str, value: float):
-        self._check(self.lib.phx_set_option(self.h, key.encode(), float(value)))
+        rc = self.lib.phx_set_option(self.h, key.encode(), float(value))
+        if rc != OK:
+            raise PhxError(rc, self.lib.phx_last_error(self.h).decode())
 
     def stat(self, key: str) -> float:
+        """A statistic of the last solve (does not change last_status)."""
         v = c_double()
-        self._check(self.lib.phx_get_stat(self.h, key.encode(), byref(v)))
+        if self.lib.phx_get_stat(self.h, key.encode(), byref(v)) != OK:
+            raise PhxError(EINVAL, f"unknown statistic {key}")
         return v.value
 
     # -------------------------------------------------------------- stages

@@ -56,6 +56,23 @@ def test_kpath_matches_oracle(lat, nk):
         assert np.allclose(phx.kpath(lat, 10, "GXMGR"), geometry.kpath(lat, 10, "GXMGR"), atol=1e-15)
 
 
+@pytest.mark.parametrize("lat", ["SC", "BCC", "FCC"])
+def test_library_kpath_vertices_lie_on_the_brillouin_zone_boundary(lat):
+    """The library's own vertex table and conversion to reciprocal coordinates, pinned like
+    the oracle's: each non-Gamma vertex it emits is on the first Brillouin-zone boundary."""
+    from oracle import geometry
+    from tests.test_oracle import bz_boundary_defect
+    path = geometry.DEFAULT_PATHS[lat]
+    verts = path.replace("|", "")
+    Q = phx.kpath(lat, len(verts))
+    B = np.linalg.inv(geometry.primitive_vectors(lat, 1.0)).T
+    for v, q in zip(verts, Q):
+        if v == "G":
+            continue
+        on, inside = bz_boundary_defect(lat, q @ B)
+        assert abs(on) < 1e-12 and inside > -1e-12, (lat, v)
+
+
 def test_kpath_rejects_bad_arguments():
     lib = phx.load()
     q = np.zeros(300)

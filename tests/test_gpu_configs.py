@@ -97,8 +97,9 @@ def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
     bands and the adjoint of bands 6/7 in mixed precision through one batched call on 12
     library streams, with the benchmark's factor sharing (up to 8 k-points per factor
     within 1.0 cycles/a).  Design 0 at two k-points against the FP64 oracle: every
-    frequency within 1e-6 relative and both sensitivity fields within 1e-4 of their
-    largest entry (bands 6 and 7 are checked to be non-degenerate there)."""
+    frequency within 1e-6 relative and both sensitivity fields within 1e-6 of their
+    largest entry (bands 6 and 7 are checked to be non-degenerate there); and the FP64
+    path on the same design and k-points: frequencies within 1e-9, sensitivities 1e-6."""
     import torch
     from oracle import adjoint, geometry
     wl = synth.config4(all_m5=True, ndesign=16)
@@ -143,39 +144,92 @@ def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
             assert min(gaps) > 1e-3 * w[b - 1], (ks[i], b, gaps)
             e = np.abs(dw[i, j] - dw_ref[i, j]).max() / np.abs(dw_ref[i, j]).max()
             log("k", ks[i], "band", b, "sensitivity error", e)
-            assert e <= 1e-4
+            assert e <= 1e-6
+    # the FP64 path, same design and k-points
+    ctx.set_option("tol_fp64", 1e-10)
+    try:
+        t = time.time()
+        om64, dw64 = ctx.sens_dev(wl.cells[0], rhos[0], q[ks], wl.nbands, wl.sens_bands, "fp64")
+        log("FP64 path, 2 k-points:", round(time.time() - t, 2), "s")
+    finally:
+        ctx.set_option("tol_fp64", 1e-8)
+    om64, dw64 = om64.cpu().numpy(), dw64.cpu().numpy()
+    err64 = _rel(om64, om_ref)
+    log("fp64 vs oracle, max rel omega error", err64.max(), "per band",
+        " ".join(f"{e:.1e}" for e in err64.max(axis=0)))
+    assert err64.max() <= 1e-9
+    for i in range(len(ks)):
+        for j, b in enumerate(wl.sens_bands):
+            e = np.abs(dw64[i, j] - dw_ref[i, j]).max() / np.abs(dw_ref[i, j]).max()
+            log("fp64 k", ks[i], "band", b, "sensitivity error", e)
+            assert e <= 1e-6
+
+
+def _clusters(w, tol):
+    out, cur = [], [0]
+    for i in range(1, len(w)):
+        if w[i] - w[i - 1] < tol * w[i]:
+            cur.append(i)
+        else:
+            out.append(cur)
+            cur = [i]
+    out.append(cur)
+    return out
 
 
 def test_single_design_k_streams(ctx):
     """Option kstreams: one design's k-points in three ranges on concurrent worker streams
     (SC 16^3, M=3, 30 k-points; and FCC 32^3 at M=4, whose coarse start runs per range)
-    give the frequencies, sensitivities and weighted adjoint gradient of one stream, to
-    the mixed-precision tolerance."""
+    give the frequencies, sensitivities and weighted adjoint gradient of one stream.  The
+    ranges have their own preconditioner factors, so the iterates differ; with the
+    tolerance at 1e-9 every band is compared at 1e-6: frequencies one by one, the
+    sensitivities of every cluster of bands closer than 1e-4 (relative) by their sum
+    (inside a nearly degenerate pair the per-vector derivative depends on the basis the
+    solver picked; the sum does not), and the gradient with weights that are equal within
+    each such cluster."""
     import torch
-    for wl, M in ((synth.config2(), None), (synth.config4(all_m5=False, ndesign=2), 4)):
-        cell = wl.cells[0] if M is None else synth.Cell("FCC", 1.0, 32, M)
-        rho = torch.from_numpy(np.ascontiguousarray(wl.designs[0].reshape(-1))).to("cuda:0")
-        q = phx.kpath(cell.lattice, 30)
-        bands = (3, 4) if M is None else (6, 7)
-        w = torch.from_numpy(np.random.default_rng(3).random((30, 2))).to("cuda:0")
-        res = {}
-        try:
-            for ks in (1, 3):
-                ctx.set_option("kstreams", ks)
-                om, dw = ctx.sens_dev(cell, rho, q, wl.nbands, bands, "mixed")
-                g = ctx.adjoint_dev(cell, rho, q, wl.nbands, bands, w, "mixed")
-                res[ks] = (om.cpu().numpy(), dw.cpu().numpy(), g.cpu().numpy())
-        finally:
-            ctx.set_option("kstreams", 1)
-        err = _rel(res[3][0], res[1][0])
-        gerr = np.abs(res[3][2] - res[1][2]).max() / np.abs(res[1][2]).max()
-        log(cell.lattice, "M", cell.M, "kstreams 3 vs 1: omega", err.max(), "gradient", gerr)
-        assert err.max() <= 1e-6 and gerr <= 1e-4
-        for k in range(30):
-            for j, b in enumerate(bands):
-                wk = res[1][0][k]
-                i = b - 1
-                if wk[i] < 1e-6 * wk.max() or min(wk[i] - wk[i - 1], wk[i + 1] - wk[i]) < 1e-4 * wk[i]:
-                    continue
-                ref = res[1][1][k, j]
-                assert np.abs(res[3][1][k, j] - ref).max() <= 1e-4 * np.abs(ref).max(), (k, b)
+    ctx.set_option("tol_mixed", 1e-9)
+    try:
+        for wl, M in ((synth.config2(), None), (synth.config4(all_m5=False, ndesign=2), 4)):
+            cell = wl.cells[0] if M is None else synth.Cell("FCC", 1.0, 32, M)
+            rho = torch.from_numpy(np.ascontiguousarray(wl.designs[0].reshape(-1))).to("cuda:0")
+            q = phx.kpath(cell.lattice, 30)
+            nb = wl.nbands
+            bands = tuple(range(1, nb + 1))
+            res = {}
+            try:
+                for ks in (1, 3):
+                    ctx.set_option("kstreams", ks)
+                    om, dw = ctx.sens_dev(cell, rho, q, nb, bands, "mixed")
+                    res[ks] = (om.cpu().numpy(), dw.cpu().numpy())
+            finally:
+                ctx.set_option("kstreams", 1)
+            om1, dw1 = res[1]
+            # weights: random, equal within each cluster, zero on the acoustic modes at Gamma and
+            # on a cluster that reaches the last band (its partners may lie beyond it)
+            rng = np.random.default_rng(3)
+            w = np.zeros((30, nb))
+            ncl = 0
+            for k in range(30):
+                for cl in _clusters(om1[k], 1e-4):
+                    if om1[k, cl[0]] < 1e-6 * om1[k].max() or (cl[-1] == nb - 1 and len(cl) > 1):
+                        continue
+                    w[k, cl] = rng.standard_normal()
+                    ref = dw1[k, cl].sum(axis=0)
+                    e = np.abs(res[3][1][k, cl].sum(axis=0) - ref).max() / np.abs(ref).max()
+                    assert e <= 1e-6, (k, cl, e)
+                    ncl += 1
+            wt = torch.from_numpy(w).to("cuda:0")
+            g = {}
+            try:
+                for ks in (1, 3):
+                    ctx.set_option("kstreams", ks)
+                    g[ks] = ctx.adjoint_dev(cell, rho, q, nb, bands, wt, "mixed").cpu().numpy()
+            finally:
+                ctx.set_option("kstreams", 1)
+            err = _rel(res[3][0], om1)
+            gerr = np.abs(g[3] - g[1]).max() / np.abs(g[1]).max()
+            log(cell.lattice, "M", cell.M, "kstreams 3 vs 1: omega", err.max(), "gradient", gerr, "clusters", ncl)
+            assert err.max() <= 1e-6 and gerr <= 1e-6
+    finally:
+        ctx.set_option("tol_mixed", 1e-6)

@@ -259,31 +259,52 @@ def test_homogeneous_closed_form(ctx, lat, prec):
 
 @pytest.fixture(scope="module")
 def config2_ref():
+    """Config 2 at four k-points: the oracle's frequencies and per-vector sensitivities of
+    every band (so that every cluster of nearly equal frequencies is complete)."""
     from oracle import adjoint, geometry
     wl = synth.config2()
     cell, rho = wl.cells[0], wl.designs[0]
     Q = geometry.kpath(cell.lattice, wl.nk, wl.path)[[0, 3, 7, 16]]
+    bands = tuple(range(1, wl.nbands + 1))
     t = time.time()
-    om, dw = adjoint.sensitivities(cell, rho, Q, wl.nbands, wl.sens_bands)
+    om, dw = adjoint.sensitivities(cell, rho, Q, wl.nbands, bands)
     log("oracle config2 subset", time.time() - t)
-    return cell, rho, Q, wl.nbands, wl.sens_bands, om, dw
+    return cell, rho, Q, wl.nbands, bands, om, dw
 
 
-def _sens_compare(om_ref, dw_ref, om, dw, bands, tol):
+def _clusters(w, tol):
+    """Runs of consecutive bands (0-based) whose relative frequency gaps are below tol."""
+    out, cur = [], [0]
+    for i in range(1, len(w)):
+        if w[i] - w[i - 1] < tol * w[i]:
+            cur.append(i)
+        else:
+            out.append(cur)
+            cur = [i]
+    out.append(cur)
+    return out
+
+
+def _sens_compare(om_ref, dw_ref, om, dw, tol, gap=1e-4):
+    """Sensitivities of all bands against the oracle's.  Where bands lie closer than `gap`
+    (relative) the per-vector derivative depends on the basis the solver picked inside the
+    nearly degenerate pair (the mixing angle scales as the residual over the gap); the sum
+    over such a cluster does not, so clusters are compared by their sums (reading: Eq. (15)
+    needs a simple eigenvalue).  Acoustic bands at Gamma have the derivative 0.  A cluster
+    that reaches the last band may continue beyond the bands computed and is not formed."""
     checked = 0
+    nb = om_ref.shape[1]
     for k in range(om_ref.shape[0]):
-        for j, b in enumerate(bands):
-            w = om_ref[k]
-            i = b - 1
-            if w[i] < 1e-6 * w.max():
-                assert np.all(dw[k, j] == 0)
+        w = om_ref[k]
+        for cl in _clusters(w, gap):
+            if w[cl[0]] < 1e-6 * w.max():
+                for i in cl:
+                    assert np.all(dw[k, i] == 0)
                 continue
-            lo = (w[i] - w[i - 1]) / w[i] if i > 0 else 1.0
-            hi = (w[i + 1] - w[i]) / w[i] if i + 1 < len(w) else 1.0
-            if min(lo, hi) < 1e-4:
-                continue  # degenerate within the cluster: per-vector sensitivity is not unique
-            err = np.abs(dw[k, j] - dw_ref[k, j]).max() / np.abs(dw_ref[k, j]).max()
-            assert err <= tol, (k, b, err)
+            assert cl[-1] < nb - 1 or len(cl) == 1, (k, cl)
+            ref = dw_ref[k, cl].sum(axis=0)
+            err = np.abs(dw[k, cl].sum(axis=0) - ref).max() / np.abs(ref).max()
+            assert err <= tol, (k, cl, err)
             checked += 1
     return checked
 
@@ -296,9 +317,9 @@ def test_sens_fp64_config2(ctx, config2_ref):
     ctx.set_option("tol_fp64", 1e-8)
     log("sens fp64 config2 subset", time.time() - t, "iters", ctx.stat("iters"))
     assert _om_err(om, om_ref).max() <= 1e-9
-    n = _sens_compare(om_ref, dw_ref, om, dw, bands, 1e-6)
+    n = _sens_compare(om_ref, dw_ref, om, dw, 1e-6)
     log("compared", n)
-    assert n >= 6
+    assert n >= 30
 
 
 def test_sens_mixed_config2(ctx, config2_ref):
@@ -307,7 +328,7 @@ def test_sens_mixed_config2(ctx, config2_ref):
     om, dw = ctx.sens(cell, rho, Q, nb, bands, "mixed")
     ctx.set_option("tol_mixed", 1e-6)
     assert _om_err(om, om_ref).max() <= 1e-6
-    assert _sens_compare(om_ref, dw_ref, om, dw, bands, 1e-6) >= 6
+    assert _sens_compare(om_ref, dw_ref, om, dw, 1e-6) >= 30
 
 
 def test_adjoint_is_weighted_sum(ctx, config2_ref):

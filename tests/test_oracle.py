@@ -67,6 +67,52 @@ def test_kpath_vertices_and_counts(lat):
     assert np.allclose(Q[0], 0)
 
 
+def bz_boundary_defect(lat, kc):
+    """For a Cartesian wave vector kc (cycles per a): (|k|^2 - min_G |k - G|^2, min_G |k - G|^2 -
+    |k|^2 over the reciprocal lattice vectors G != 0), from B = A^{-T} built here.  A point on the
+    boundary of the first Brillouin zone (the Wigner-Seitz cell of the reciprocal lattice) has
+    the first value 0 (some G is as near as the origin) and the second >= 0 (none is nearer)."""
+    A = geometry.primitive_vectors(lat, 1.0)
+    B = np.linalg.inv(A).T
+    n = np.array([(i, j, l) for i in range(-3, 4) for j in range(-3, 4) for l in range(-3, 4)
+                  if (i, j, l) != (0, 0, 0)], float)
+    G = n @ B
+    d2 = np.sum((kc[None, :] - G) ** 2, axis=1).min()
+    k2 = float(kc @ kc)
+    return k2 - d2, d2 - k2
+
+
+@pytest.mark.parametrize("lat", ["SC", "BCC", "FCC"])
+def test_kpath_vertices_lie_on_the_brillouin_zone_boundary(lat):
+    """Every high-symmetry point other than Gamma is a corner, edge or face point of the
+    first Brillouin zone: it is as close to some reciprocal lattice vector G as to the
+    origin, and closer to none.  Checked on the k-points the oracle's path emits (reciprocal
+    coordinates Q turned back into Cartesian K = sum_j Q_j b_j), so a slip in the vertex
+    table (a fractional coordinate entered as Cartesian, a wrong point) or in the
+    conversion to Q moves some vertex off the boundary."""
+    path = geometry.DEFAULT_PATHS[lat]
+    verts = [v for v in path.replace("|", "")]
+    Q = geometry.kpath(lat, len(verts))  # vertices only
+    B = np.linalg.inv(geometry.primitive_vectors(lat, 1.0)).T
+    for v, q in zip(verts, Q):
+        kc = q @ B
+        if v == "G":
+            assert np.abs(kc).max() == 0
+            continue
+        on, inside = bz_boundary_defect(lat, kc)
+        assert abs(on) < 1e-12 and inside > -1e-12, (lat, v, kc, on, inside)
+
+
+def test_bz_boundary_check_rejects_plausible_slips():
+    """The check above fails for the slips it is meant to catch: BCC P at (1/4, 1/4, 1/4)
+    (half the true coordinate), FCC X at (0, 1/2, 0) (the SC value), FCC X entered as its
+    reciprocal coordinates (1/2, 0, 1/2) instead of Cartesian, and BCC H at (0, 0, 1/2)."""
+    bad = [("BCC", (0.25, 0.25, 0.25)), ("FCC", (0, 0.5, 0)), ("FCC", (0.5, 0, 0.5)), ("BCC", (0, 0, 0.5))]
+    for lat, kc in bad:
+        on, inside = bz_boundary_defect(lat, np.array(kc, float))
+        assert abs(on) > 1e-3 or inside < -1e-3, (lat, kc)
+
+
 def test_kpath_sc_coordinates():
     Q = geometry.kpath("SC", 5, "GXMGR")
     assert np.allclose(Q, [[0, 0, 0], [0, .5, 0], [.5, .5, 0], [0, 0, 0], [.5, .5, .5]])

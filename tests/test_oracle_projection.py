@@ -92,3 +92,48 @@ def test_adjoint_matches_central_differences(sp, octant, beta):
         fd = (g @ P.project(xp, nv, sp, r, beta, octant).reshape(-1)
               - g @ P.project(xm, nv, sp, r, beta, octant).reshape(-1)) / (2 * h)
         assert adj[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# ----------------------------------------------------------------------------- density filter
+
+@pytest.mark.parametrize("r", [0.7, 1.5, 2.2])
+def test_oracle_hat_filter_pins(r):
+    """The oracle's voxel filter: a constant field is unchanged, the mean is preserved, the
+    operator (built column by column on a 5^3 grid) is symmetric with unit row sums, a
+    radius below one voxel leaves the field as it is, and a single voxel spreads to weights
+    that fall linearly with distance and vanish at the radius."""
+    from oracle import filter as filt
+    rng = np.random.default_rng(5)
+    x = rng.random((7, 7, 7))
+    assert np.allclose(filt.hat_filter(np.full((7, 7, 7), 0.3), r), 0.3, atol=1e-15)
+    assert abs(filt.hat_filter(x, r).sum() - x.sum()) < 1e-12
+    n = 5
+    Fm = np.zeros((n ** 3, n ** 3))
+    for j in range(n ** 3):
+        e = np.zeros(n ** 3)
+        e[j] = 1
+        Fm[:, j] = filt.hat_filter(e.reshape(n, n, n), min(r, 2.0)).reshape(-1)
+    assert np.allclose(Fm, Fm.T, atol=1e-15) and np.allclose(Fm.sum(axis=1), 1, atol=1e-14)
+    if r < 1:
+        assert np.allclose(filt.hat_filter(x, r), x, atol=1e-15)
+    d = np.zeros((7, 7, 7))
+    d[3, 3, 3] = 1
+    y = filt.hat_filter(d, r)
+    # weights relative to the centre: (r - |offset|) / r along an axis, zero beyond r
+    for k in range(0, 3):
+        expect = max(0.0, r - k) / r
+        assert abs(y[3 + k, 3, 3] / y[3, 3, 3] - expect) < 1e-14
+
+
+def test_oracle_hat_filter_matches_the_library_kernel_on_the_cpu():
+    """The product path's filter (a torch convolution) and the oracle's sum agree; both are
+    CPU operations here, so this runs without a GPU."""
+    import torch
+
+    from oracle import filter as filt
+    from paper_1603_06855_amd import optimize
+    rng = np.random.default_rng(6)
+    x = rng.random((9, 9, 9))
+    for r in (1.5, 2.2):
+        got = optimize.density_filter(torch.from_numpy(x), optimize.hat_kernel(r)).numpy()
+        assert np.abs(got - filt.hat_filter(x, r)).max() < 1e-14
