@@ -1140,6 +1140,9 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
   ctx->stats = Stats();
   ctx->stats.block = s;
   ctx->stats.kchunk = kc;
+  // workspaces of earlier calls beyond the cap are given back first (they are grow-only)
+  if (ctx->opt.mem_limit_gb > 0 && (double)ctx->mem_used > ctx->opt.mem_limit_gb * 1073741824.0)
+    release_workspaces(ctx);
   bool conv = true;
   for (int k0 = 0; k0 < nk;) {
     const int nkc = std::min(kc, nk - k0);

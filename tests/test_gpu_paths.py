@@ -73,25 +73,26 @@ def config2():
 def test_k_chunks_equal_one_chunk(ctx, config2):
     cell, rho, q, nb, bands = config2
     res = {}
+    small = {"fp64": 0.3, "mixed": 0.18}  # about 10 k-points per chunk (FP32 factors are half the size)
     try:
         for kshare in (1, 2):
             ctx.set_option("kshare", kshare)
-            for mem in (64.0, 0.3):
-                ctx.set_option("mem_gb", mem)
-                for prec in ("fp64", "mixed"):
+            for prec in ("fp64", "mixed"):
+                for mem in ("all", "small"):
+                    ctx.set_option("mem_gb", 64.0 if mem == "all" else small[prec])
                     om, dw = ctx.sens(cell, rho, q, nb, bands, prec)
                     res[kshare, mem, prec] = (om, dw, ctx.stat("chunks"), ctx.stat("kchunk"))
-                    log("kshare", kshare, "mem_gb", mem, prec, "chunks", ctx.stat("chunks"), "kchunk",
+                    log("kshare", kshare, "mem", mem, prec, "chunks", ctx.stat("chunks"), "kchunk",
                         ctx.stat("kchunk"), "status", ctx.last_status)
     finally:
         ctx.set_option("kshare", 2)
         ctx.set_option("mem_gb", 64.0)
     for prec in ("fp64", "mixed"):
-        one, three = res[1, 64.0, prec], res[1, 0.3, prec]
+        one, three = res[1, "all", prec], res[1, "small", prec]
         assert one[2] == 1 and three[2] >= 3, (one[2], three[2])
         assert np.array_equal(one[0], three[0]) and np.array_equal(one[1], three[1]), prec
         # shared factors: the groups end at chunk boundaries, so the preconditioners differ
-        a, b = res[2, 64.0, prec], res[2, 0.3, prec]
+        a, b = res[2, "all", prec], res[2, "small", prec]
         assert b[2] >= 3
         tol = 1e-9 if prec == "fp64" else 1e-6
         assert _om_err(b[0], a[0]).max() <= tol
