@@ -350,6 +350,19 @@ int phx_project_adjoint(phx_ctx* ctx, const phx_projection* p, const double* x, 
                         double* grad_x);
 int phx_project_adjoint_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, const double* grad_rho_dev,
                             double* grad_x_dev, void* stream);
+/* The same backward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or optimisation loops, harnesses that forbid hipMalloc): the
+ * per-element scratch of the computation lives in a fixed device array of the library
+ * (nv^3 doubles, nv <= 64; one per GPU, held until the process ends), so this call makes
+ * no hipMalloc, hipFree or other allocating call.  x_dev, grad_rho_dev and grad_x_dev are
+ * the caller's device arrays as for phx_project_adjoint_dev.  The work is queued on
+ * `stream` (the context's stream if NULL) and the call returns without waiting for it.
+ * Every call on one GPU uses that GPU's one scratch array: calls that can run at the same
+ * time on one GPU (on different streams, or from different contexts) race and give wrong
+ * results; calls ordered on one stream do not.  PHX_EINVAL for an invalid projection or
+ * nv > 64. */
+int phx_project_adjoint_dev_noalloc(phx_ctx* ctx, const phx_projection* p, const double* x_dev,
+                                    const double* grad_rho_dev, double* grad_x_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -183,6 +184,32 @@ void hook_begin(void* u, int cls) { ((Profiler*)u)->begin(cls); }
 void hook_end(void* u, int cls, double f, double b) { ((Profiler*)u)->end(cls, f, b); }
 void hook_kev(void* u, int cls, double f, double b, hipEvent_t* e0, hipEvent_t* e1) {
   ((Profiler*)u)->kernel_events(cls, f, b, e0, e1);
+}
+
+// Device scratch of the allocation-free projection adjoint (phx_project_adjoint_dev_noalloc):
+// the per-element coefficients of one call, nv^3 doubles, nv <= 64 (2 MiB).  Every GPU the
+// library runs on holds its own copy until the process ends; host code reaches it only
+// through the per-device address taken at context creation (the array's name is a host
+// stand-in, not a device address).
+constexpr long NOALLOC_SCRATCH_DOUBLES = 64L * 64 * 64;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device -> address of its scratch
+
+// Takes the current device's address of the scratch array once per device.
+int scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return PHX_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PHX_EHIP;
+  g_scratch_addr[device] = (double*)ptr;
+  return PHX_OK;
+}
+
+double* scratch_addr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
 }
 
 }  // namespace
@@ -1270,8 +1297,8 @@ int phx_create(phx_ctx** out, int hip_device) {
   c->device = hip_device;
   const char* tr = getenv("PHX_TRACE");
   c->trace = tr && tr[0] && tr[0] != '0';
-  if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess ||
-      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess ||
+  if (hipSetDevice(hip_device) != hipSuccess || scratch_setup(hip_device) != PHX_OK ||
+      hipStreamCreate(&c->stream) != hipSuccess || hipMalloc(&c->dflag, sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&c->wait_ev, hipEventBlockingSync | hipEventDisableTiming) != hipSuccess) {
     if (c->dflag) (void)hipFree(c->dflag);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -2048,6 +2075,24 @@ int phx_project_adjoint_dev(phx_ctx* ctx, const phx_projection* p, const double*
                            ctx->stream);
     KCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PHX_OK;
+  });
+}
+
+int phx_project_adjoint_dev_noalloc(phx_ctx* ctx, const phx_projection* p, const double* x_dev,
+                                    const double* grad_rho_dev, double* grad_x_dev, void* stream) {
+  return guard(ctx, [&]() {
+    check_projection(ctx, p);
+    if (!x_dev || !grad_rho_dev || !grad_x_dev) fail(ctx, PHX_EINVAL, "a device pointer is NULL");
+    const long ne = (long)p->nv * p->nv * p->nv;
+    if (ne > NOALLOC_SCRATCH_DOUBLES)
+      fail(ctx, PHX_EINVAL, "nv^3 exceeds the allocation-free scratch (nv <= 64); use phx_project_adjoint_dev");
+    double* coef = scratch_addr(ctx->device);
+    if (!coef) fail(ctx, PHX_EHIP, "the device scratch of this GPU was not set up");
+    // every element's coefficient is written before the second kernel reads it: nothing to clear
+    launch_project_adjoint(p->nv, p->spacing, p->radius, p->beta, p->octant, x_dev, grad_rho_dev, coef, grad_x_dev,
+                           stream ? (hipStream_t)stream : ctx->stream);
+    KCHK(hipGetLastError());
     return PHX_OK;
   });
 }

@@ -93,6 +93,8 @@ def load():
         "phx_project_adjoint": (c_int, [P, POINTER(Projection), D, D, D]),
         "phx_project_dev": (c_int, [P, POINTER(Projection), c_void_p, c_void_p, c_void_p]),
         "phx_project_adjoint_dev": (c_int, [P, POINTER(Projection), c_void_p, c_void_p, c_void_p, c_void_p]),
+        "phx_project_adjoint_dev_noalloc": (c_int, [P, POINTER(Projection), c_void_p, c_void_p, c_void_p,
+                                                    c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -474,3 +476,20 @@ class Context:
                                                      c_void_p(g_t.data_ptr()), c_void_p(out.data_ptr()),
                                                      c_void_p(st)))
         return out
+
+    def project_adjoint_dev_noalloc(self, p: Projection, x_t, grad_rho_t, out_t):
+        """The backward of project_dev into the caller's tensor out_t (shaped like x_t), through
+        the library's fixed device scratch: neither the library nor this binding allocates.
+        All tensors must be contiguous float64 device tensors; the work is queued on torch's
+        current stream."""
+        import torch
+        for t in (x_t, grad_rho_t, out_t):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("contiguous float64 device tensors required")
+        if x_t.numel() != projection_size(p) or out_t.numel() != x_t.numel() or grad_rho_t.numel() != p.nv ** 3:
+            raise ValueError("wrong tensor sizes")
+        st = torch.cuda.current_stream(x_t.device).cuda_stream
+        self._check(self.lib.phx_project_adjoint_dev_noalloc(self.h, byref(p), c_void_p(x_t.data_ptr()),
+                                                             c_void_p(grad_rho_t.data_ptr()),
+                                                             c_void_p(out_t.data_ptr()), c_void_p(st)))
+        return out_t
