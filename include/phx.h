@@ -111,10 +111,11 @@ const char* phx_last_error(const phx_ctx* ctx);
  * slowest converges; every per-k decision of the eigensolver is taken per k-point,
  * so with kshare = 1 a k-point's results depend neither on the other k-points of its
  * chunk nor on the chunk size),
- * "rr_fused" (1, default: one Omega-orthonormalisation of the search basis,
- * the second folded into the Rayleigh-Ritz step in the small m x m space, except
- * for a k-point whose residual is below 1e-13/tolerance (the last iterations of an FP64
- * solve), whose basis is orthonormalised twice explicitly; 0:
+ * "rr_fused" (2, default: both Omega-orthonormalisations of the search basis folded
+ * into the Rayleigh-Ritz step in the small m x m space, so an iteration makes one Gram
+ * product and one basis update; 1: one explicit Omega-orthonormalisation of the basis,
+ * the second folded; with 1 and 2 a k-point whose residual is below 1e-13/tolerance (the
+ * last iterations of an FP64 solve) has its basis orthonormalised twice explicitly; 0:
  * always two explicit orthonormalisations of the basis before Rayleigh-Ritz),
  * "mem_gb" (device memory budget that sets the k-chunk size, default 64; per worker
  * context of phx_sens_batch_dev), "mem_limit_gb" (hard cap on the device workspace one
@@ -141,6 +142,15 @@ const char* phx_last_error(const phx_ctx* ctx);
  * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
  * blocking-sync event, leaving the core to the threads of concurrent design
  * streams; 1: it spins in hipStreamSynchronize),
+ * "precond" (the eigensolver's preconditioner; 0: the Cholesky factor of the shifted
+ * pencil K(k) + sigma Omega, assembled per k-point (or per group of k-points, see
+ * "kshare"); 1: block Jacobi, the 3 x 3 diagonal block of that pencil for each plane wave,
+ * built from the diagonals of the k-independent operators and the wave vectors, so K(k)
+ * is never formed or factored; converges as fast as the pencil on smooth designs and far
+ * slower on sharp high-contrast inclusions; 2, default: block Jacobi first, and a
+ * k-point whose residual has not fallen tenfold over the last "stall_its" iterations
+ * (default 8, 2..30), or that reaches iteration 30, gets its own pencil factor (shared
+ * with k-points that stall in the same iteration, as "kshare" allows) from then on),
  * "degen_tol" (default 1e-8; 0 disables): consecutive frequencies of one k-point whose
  * relative gap (omega_{i+1} - omega_i) / omega_{i+1} is below this form a degenerate
  * cluster (see phx_sens).
@@ -155,6 +165,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double value);
  * coarse start), "iters_mean_k" (mean over k-points of the iteration at which
  * each met the tolerance), "factors" (preconditioner factorisations of the
  * order-M solves), "degen" (requested (k, band) entries inside a degenerate cluster),
+ * "precond_switches" (solves that went from block Jacobi to the pencil factors),
  * "enomem_retries" (k-chunks solved again with fewer k-points), "mem_bytes" (device
  * workspace the context holds).  "prof.<class>.<ms|flops|bytes|count>"
  * reads the kernel-class timers (enabled with the option "profile"). */

@@ -43,6 +43,11 @@ void launch_residual(double2* Big, long n3, long mcols, long sBig, const double*
 template <typename R>
 void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st,
                   const int* kact = nullptr);
+// W = D(k)^{-1} R, D(k) the 3 x 3 per-wave diagonal blocks of K(k) + sigma Omega (block Jacobi).
+template <typename R>
+void launch_jacobi(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
+                   double c2, const double* sigma, const C_t<R>* Rp, long sR, int s, double2* W, long sW, int nk,
+                   hipStream_t st, const int* kact = nullptr);
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
                        int Np, int nk, double2* Fc, hipStream_t st);
 void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int nsel, long n, int nk, double2* Y,

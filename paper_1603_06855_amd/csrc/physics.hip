@@ -329,6 +329,68 @@ __global__ void widen_kernel(const C_t<R>* Rp, long sR, long n, double2* W, long
   }
 }
 
+// Block-Jacobi preconditioner: W = D(k)^{-1} R with D(k) the 3 x 3 diagonal blocks of the
+// pencil K(k) + sigma Omega, one per plane wave p (the p = q block of Eq. (4) in the sandwich
+// form, from the diagonals of the k-shared operators and the wave vector K_p: never from
+// K(k) itself).  Padding waves (p >= N) are identity.  R: n3 x s per k (k-stride sR,
+// precision R); W: n3 x s per k in FP64 (ld n3, k-stride sW).  One thread per (wave, k).
+template <typename R>
+__global__ __launch_bounds__(256) void jacobi_kernel(const double2* Dm, const double2* Bm, const double2* Os,
+                                                      const double* Kv, int N, int Np, double c2,
+                                                      const double* sigma, const C_t<R>* Rp, long sR, int s,
+                                                      double2* W, long sW, const int* kact) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (p >= Np || (kact && !kact[k])) return;
+  const long n3 = 3L * Np;
+  const C_t<R>* r = Rp + (long)k * sR + p;
+  double2* w = W + (long)k * sW + p;
+  if (p >= N) {
+    for (int j = 0; j < s; ++j)
+      for (int c = 0; c < 3; ++c) {
+        const C_t<R> v = r[j * n3 + c * Np];
+        w[j * n3 + c * Np] = make_double2((double)v.x, (double)v.y);
+      }
+    return;
+  }
+  // the diagonal entries of Hermitian operators are real
+  const double dm = Dm[p + (long)p * Np].x, bm = Bm[p + (long)p * Np].x, os = Os[p + (long)p * Np].x;
+  const double* kp = Kv + ((long)k * Np + p) * 3;
+  const double kk = kp[0] * kp[0] + kp[1] * kp[1] + kp[2] * kp[2];
+  double a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      a[i][j] = c2 * kp[i] * kp[j] * (dm / 3.0 + 0.5 * bm) + (i == j ? 0.5 * c2 * kk * bm + sigma[k] * os : 0.0);
+  // inverse of the symmetric positive definite 3 x 3 block by its adjugate
+  double inv[3][3];
+  inv[0][0] = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+  inv[0][1] = a[0][2] * a[2][1] - a[0][1] * a[2][2];
+  inv[0][2] = a[0][1] * a[1][2] - a[0][2] * a[1][1];
+  inv[1][0] = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+  inv[1][1] = a[0][0] * a[2][2] - a[0][2] * a[2][0];
+  inv[1][2] = a[0][2] * a[1][0] - a[0][0] * a[1][2];
+  inv[2][0] = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+  inv[2][1] = a[0][1] * a[2][0] - a[0][0] * a[2][1];
+  inv[2][2] = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+  const double det = a[0][0] * inv[0][0] + a[0][1] * inv[1][0] + a[0][2] * inv[2][0];
+  const double id = 1.0 / det;
+  for (int j = 0; j < s; ++j) {
+    double2 v[3];
+    for (int c = 0; c < 3; ++c) {
+      const C_t<R> x = r[j * n3 + c * Np];
+      v[c] = make_double2((double)x.x, (double)x.y);
+    }
+    for (int i = 0; i < 3; ++i) {
+      double2 o = make_double2(0, 0);
+      for (int c = 0; c < 3; ++c) {
+        o.x += inv[i][c] * v[c].x;
+        o.y += inv[i][c] * v[c].y;
+      }
+      w[j * n3 + i * Np] = make_double2(o.x * id, o.y * id);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a8: adjoint.  Coefficients of the displacement (3) and Mandel stress (6)
 // fields of selected Ritz vectors, on the (2M+1)^3 wave grid:
@@ -528,6 +590,20 @@ void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk
   hipLaunchKernelGGL((widen_kernel<R>), dim3(nb, nk), dim3(256), 0, st, Rp, sR, n, W, sW, kact);
 }
 template void launch_widen<double>(const double2*, long, long, double2*, long, int, hipStream_t, const int*);
+
+template <typename R>
+void launch_jacobi(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
+                   double c2, const double* sigma, const C_t<R>* Rp, long sR, int s, double2* W, long sW, int nk,
+                   hipStream_t st, const int* kact) {
+  hipLaunchKernelGGL((jacobi_kernel<R>), dim3(nblk(Np, 256), nk), dim3(256), 0, st, Dm, Bm, Os, Kv, N, Np, c2, sigma,
+                     Rp, sR, s, W, sW, kact);
+}
+template void launch_jacobi<double>(const double2*, const double2*, const double2*, const double*, int, int, double,
+                                    const double*, const double2*, long, int, double2*, long, int, hipStream_t,
+                                    const int*);
+template void launch_jacobi<float>(const double2*, const double2*, const double2*, const double*, int, int, double,
+                                   const double*, const float2*, long, int, double2*, long, int, hipStream_t,
+                                   const int*);
 template void launch_widen<float>(const float2*, long, long, double2*, long, int, hipStream_t, const int*);
 
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,

@@ -55,7 +55,7 @@ struct Opts {
   int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
   int streams = 4;           // designs solved concurrently by the batched call
-  int rr_fused = 1;          // 1: second orthonormalisation folded into Rayleigh-Ritz
+  int rr_fused = 2;          // 1: second orthonormalisation folded into Rayleigh-Ritz; 2: both
   int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
   int kskip = 1;             // 1: k-points whose wanted bands have converged skip later iterations
   int kshare = 2;            // at most this many consecutive k-points share one preconditioner factor
@@ -66,6 +66,9 @@ struct Opts {
   int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
   double degen_tol = 1e-8;   // bands closer than this (relative, in omega) form one degenerate cluster
   double mem_limit_gb = 0;   // cap on the device workspace a context may hold (0: none)
+  int precond = 2;           // 0: Cholesky of the pencil K + sigma Omega; 1: its 3 x 3 per-wave diagonal
+                             // blocks; 2: the blocks until they stall, then the pencil
+  int stall_its = 8;         // precond 2: a k-point stalls when its residual falls less than tenfold in this many iterations
 };
 
 struct Stats {
@@ -76,6 +79,7 @@ struct Stats {
   long factors = 0;                     // preconditioner factorisations (order M solves)
   long degen = 0;                       // (k, requested band) entries inside a degenerate cluster
   int enomem_retries = 0;               // k-chunks retried with half as many k-points after ENOMEM
+  int precond_switches = 0;             // k-points (of order-M and coarse solves) moved from Jacobi to the pencil
 };
 
 // Kernel-class timing with HIP events recorded on the context stream.
@@ -227,6 +231,7 @@ void merge_stats(Stats& into, const Stats& s) {
   into.kchunk = std::max(into.kchunk, s.kchunk);
   into.degen += s.degen;
   into.enomem_retries += s.enomem_retries;
+  into.precond_switches += s.precond_switches;
 }
 
 struct phx_ctx {
@@ -574,6 +579,10 @@ struct Solver {
   int* fmap;   // per k: index of its preconditioner factor (NULL: its own)
   int nact;    // active k-points (host count of kact)
   int nfar, nnear;
+  int* kjac;   // per k: active and preconditioned by block Jacobi
+  int* kpen;   // per k: active and preconditioned by its pencil factor
+  int njac, npen;
+  int nf, fcap;  // pencil factors built so far, and the capacity of the factor arrays
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
@@ -744,12 +753,22 @@ template <typename R>
 void precondition(Solver& sv) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3;
-  KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv, (n3 / 64) * 4096,
-                        (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s, ctx->stream, ctx->hk(),
-                        (const C_t<R>*)sv.SBinv, sv.kact, sv.fmap, sv.nact));
-  launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
-                  sv.kact);
-  KCHK(hipGetLastError());
+  if (sv.njac > 0) {  // block Jacobi: the per-wave 3 x 3 blocks, straight into W
+    Design& d = *sv.d;
+    PROF_BEGIN(PROF_APPLY);
+    launch_jacobi<R>(d.Dm, d.Bm, d.Os, sv.Kv, d.N, d.Np, d.c2, sv.sigma_d, (const C_t<R>*)sv.Rp, n3 * sv.s, sv.s,
+                     sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream, sv.kjac);
+    PROF_END(PROF_APPLY, 0, (double)sv.njac * 3.0 * d.N * sv.s * (sizeof(C_t<R>) + 16.0));
+    KCHK(hipGetLastError());
+  }
+  if (sv.npen > 0) {  // the pencil factors: forward and backward super-block solves
+    KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv,
+                          (n3 / 64) * 4096, (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s,
+                          ctx->stream, ctx->hk(), (const C_t<R>*)sv.SBinv, sv.kpen, sv.fmap, sv.npen));
+    launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
+                    sv.kpen);
+    KCHK(hipGetLastError());
+  }
 }
 
 int choose_block(phx_ctx* ctx, int nb, int N) {
@@ -758,12 +777,100 @@ int choose_block(phx_ctx* ctx, int nb, int N) {
   return s;
 }
 
-long per_k_bytes(const Design& d, int s, int prec) {
+long per_k_bytes(const Design& d, int s, int prec, int precond) {
   const long n3 = d.n3, m = 3 * s;
   const long pc = prec == PHX_FP64 ? 16 : 8;
   const long ws = prec == PHX_FP64 ? 128 : 256;
-  return n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc + 3L * n3 * m * 16 +
+  const long factor = precond == 1 ? 0 : n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc;
+  return factor + 3L * n3 * m * 16 +
          2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
+}
+
+// Pencil preconditioner: A = K + sigma Omega assembled and Cholesky-factored for the
+// k-points with which[k] != 0 (every k of the chunk at the start with precond 0; with
+// precond 2, the k-points whose block-Jacobi iteration stalled), appended after the sv.nf
+// factors built before; fmap_h (host, per k) receives each such k-point's factor index.
+// Consecutive k-points of `which` within kshare_dist of a group's first k-point, and within
+// kshare_rel of the shorter of the two wave vectors (at most kshare of them), share that
+// k-point's factor; the shared solves need the super-block inverses.  The relative bound
+// keeps Gamma, where K has the three rigid translations as null vectors and the factor is
+// far from that of any other k, on a factor of its own.  cap: the number of factors the
+// arrays hold (set by the first call of a solve).
+template <typename R>
+void build_factors(Solver& sv, const double* q, const std::vector<int>& which, std::vector<int>& fmap_h, int cap,
+                   bool coarse) {
+  phx_ctx* ctx = sv.ctx;
+  Design& d = *sv.d;
+  hipStream_t st = ctx->stream;
+  const int nk = sv.nk;
+  const long n3 = sv.n3;
+  std::vector<int> lead;
+  {
+    const int kmax = ctx->opt.sbinv ? ctx->opt.kshare : 1;
+    auto cart = [&](int k, int c) {
+      return q[3 * k] * d.rec.t[0][c] + q[3 * k + 1] * d.rec.t[1][c] + q[3 * k + 2] * d.rec.t[2][c];
+    };
+    for (int k = 0; k < nk; ++k) {
+      if (!which[k]) continue;
+      bool join = false;
+      if (!lead.empty()) {
+        const int l = lead.back();
+        double dd = 0, kk = 0, ll = 0;
+        for (int c = 0; c < 3; ++c) {
+          dd += (cart(k, c) - cart(l, c)) * (cart(k, c) - cart(l, c));
+          kk += cart(k, c) * cart(k, c);
+          ll += cart(l, c) * cart(l, c);
+        }
+        const double dist = sqrt(dd);
+        join = k - l < kmax && dist <= ctx->opt.kshare_dist &&
+               dist <= ctx->opt.kshare_rel * sqrt(std::min(kk, ll));
+      }
+      if (!join) lead.push_back(k);
+      fmap_h[k] = sv.nf + (int)lead.size() - 1;
+    }
+  }
+  const int nnew = (int)lead.size();
+  if (nnew == 0) return;
+  if (sv.nf == 0) sv.fcap = std::max(cap, nnew);
+  if (sv.nf + nnew > sv.fcap) fail(ctx, PHX_EHIP, "internal: pencil factor capacity exceeded");
+  if (!coarse) ctx->stats.factors += nnew;
+  constexpr int WS = sizeof(R) == 4 ? 256 : 128;
+  const long nsb = (n3 + WS - 1) / WS, f0 = sv.nf;
+  sv.A = dbuf<C_t<R>>(ctx, "A", (long)sv.fcap * n3 * n3);
+  sv.Dinv = dbuf<C_t<R>>(ctx, "Dinv", (long)sv.fcap * (n3 / 64) * 4096);
+  C_t<R>* A = (C_t<R>*)sv.A + f0 * n3 * n3;
+  C_t<R>* Dinv = (C_t<R>*)sv.Dinv + f0 * (n3 / 64) * 4096;
+  // identity map unless factors are shared or only some k-points have one
+  const bool ident = f0 == 0 && nnew == nk;
+  if (!ident) {
+    sv.fmap = dbuf<int>(ctx, "fmap", nk);
+    HIPCHK(hipMemcpyAsync(sv.fmap, fmap_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  PROF_BEGIN(PROF_ASSEMBLE);
+  const double* Kvf = sv.Kv;
+  if (!ident) {  // wave vectors of the new factors' k-points
+    double* kf = dbuf<double>(ctx, "Kvf", (long)sv.fcap * d.Np * 3);
+    for (int i = 0; i < nnew; ++i)
+      HIPCHK(hipMemcpyAsync(kf + (long)i * d.Np * 3, sv.Kv + (long)lead[i] * d.Np * 3, d.Np * 3 * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    Kvf = kf;
+  }
+  launch_assemble<R>(d.Dm, d.Bm, d.Os, Kvf, d.N, d.Np, nnew, d.c2, sv.sigma_d, A, n3 * n3, 0, st);
+  // algorithmic bytes: the lower triangle of every A(k) written once, the three N x N operators read once
+  PROF_END(PROF_ASSEMBLE, 0, (double)sizeof(C_t<R>) * nnew * (3.0 * d.N) * (3.0 * d.N + 1) / 2 + 48.0 * d.N * d.N);
+  KCHK(hipGetLastError());
+  KCHK(potrf_batched<R>(A, (int)n3, n3, n3 * n3, nnew, Dinv, (n3 / 64) * 4096, ctx->dflag, st, ctx->hk()));
+  if (ctx->opt.sbinv) {
+    sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)sv.fcap * nsb * WS * WS);
+    C_t<R>* sbw = dbuf<C_t<R>>(ctx, "SBwork", (long)sv.fcap * nsb * (WS * WS + WS * WS / 4));
+    PROF_BEGIN(PROF_SBINV);
+    KCHK(sb_inverse_batched<R>(A, (int)n3, n3, n3 * n3, nnew, Dinv, (n3 / 64) * 4096,
+                               (C_t<R>*)sv.SBinv + f0 * nsb * WS * WS, sbw, st));
+    PROF_END(PROF_SBINV, (double)nnew * 8.0 * n3 * WS * WS / 6.0, (double)nnew * sizeof(C_t<R>) * n3 * WS);
+  } else if (!ident) {
+    fail(ctx, PHX_EINVAL, "a partial or shared set of pencil factors needs option sbinv = 1");
+  }
+  sv.nf += nnew;
 }
 
 // init (may be NULL): nk blocks of s start vectors (n3 x s, k-stride n3 s) replacing
@@ -800,45 +907,6 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.theta = dbuf<double>(ctx, "theta", (long)nk * s);
   sv.rn = dbuf<double>(ctx, "rn", (long)nk * s);
   sv.rnorm = dbuf<double>(ctx, "rnorm", (long)nk * s);
-  // Preconditioner factors: consecutive k-points of the chunk within kshare_dist of a
-  // group's first k-point, and within kshare_rel of the shorter of the two wave vectors
-  // (at most kshare of them), share that k-point's factor; the shared solves need the
-  // super-block inverses.  The relative bound keeps Gamma, where K has the three rigid
-  // translations as null vectors and the factor is far from that of any other k, on a
-  // factor of its own.
-  std::vector<int> fmap_h(nk), lead;
-  {
-    const int kmax = ctx->opt.sbinv ? ctx->opt.kshare : 1;
-    auto cart = [&](int k, int c) {
-      return q[3 * k] * d.rec.t[0][c] + q[3 * k + 1] * d.rec.t[1][c] + q[3 * k + 2] * d.rec.t[2][c];
-    };
-    for (int k = 0; k < nk; ++k) {
-      bool join = false;
-      if (!lead.empty()) {
-        const int l = lead.back();
-        double dd = 0, kk = 0, ll = 0;
-        for (int c = 0; c < 3; ++c) {
-          dd += (cart(k, c) - cart(l, c)) * (cart(k, c) - cart(l, c));
-          kk += cart(k, c) * cart(k, c);
-          ll += cart(l, c) * cart(l, c);
-        }
-        const double dist = sqrt(dd);
-        join = k - l < kmax && dist <= ctx->opt.kshare_dist &&
-               dist <= ctx->opt.kshare_rel * sqrt(std::min(kk, ll));
-      }
-      if (!join) lead.push_back(k);
-      fmap_h[k] = (int)lead.size() - 1;
-    }
-  }
-  const int nkf = (int)lead.size();
-  if (!tol_override) ctx->stats.factors += nkf;
-  sv.fmap = nullptr;
-  if (nkf < nk) {
-    sv.fmap = dbuf<int>(ctx, "fmap", nk);
-    HIPCHK(hipMemcpyAsync(sv.fmap, fmap_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
-  }
-  sv.A = dbuf<C_t<R>>(ctx, "A", (long)nkf * n3 * n3);
-  sv.Dinv = dbuf<C_t<R>>(ctx, "Dinv", (long)nkf * (n3 / 64) * 4096);
   sv.Rp = dbuf<C_t<R>>(ctx, "Rp", (long)nk * n3 * s);
   sv.Zp = dbuf<C_t<R>>(ctx, "Zp", (long)nk * n3 * s);
   double* qd = dbuf<double>(ctx, "q", 3L * nk);
@@ -872,49 +940,38 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   }
   HIPCHK(hipMemcpyAsync(idx_d, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
 
-  // Pencil A = K + sigma Omega and its Cholesky factor.
-  PROF_BEGIN(PROF_ASSEMBLE);
-  const double* Kvf = sv.Kv;
-  if (nkf < nk) {  // wave vectors of the factors' k-points
-    double* kf = dbuf<double>(ctx, "Kvf", (long)nkf * d.Np * 3);
-    for (int i = 0; i < nkf; ++i)
-      HIPCHK(hipMemcpyAsync(kf + (long)i * d.Np * 3, sv.Kv + (long)lead[i] * d.Np * 3, d.Np * 3 * sizeof(double),
-                            hipMemcpyDeviceToDevice, st));
-    Kvf = kf;
-  }
-  launch_assemble<R>(d.Dm, d.Bm, d.Os, Kvf, d.N, d.Np, nkf, d.c2, sv.sigma_d, (C_t<R>*)sv.A, n3 * n3, 0, st);
-  // algorithmic bytes: the lower triangle of every A(k) written once, the three N x N operators read once
-  PROF_END(PROF_ASSEMBLE, 0, (double)sizeof(C_t<R>) * nkf * (3.0 * d.N) * (3.0 * d.N + 1) / 2 + 48.0 * d.N * d.N);
-  KCHK(hipGetLastError());
+  // The pencil preconditioner from the start (precond 0), or block Jacobi first (1, 2).
   HIPCHK(hipMemsetAsync(ctx->dflag, 0, sizeof(int), st));
-  KCHK(potrf_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (C_t<R>*)sv.Dinv, (n3 / 64) * 4096, ctx->dflag,
-                        st, ctx->hk()));
+  std::vector<int> fmap_h(nk, 0), pen_h(nk, ctx->opt.precond == 0 ? 1 : 0);
+  sv.nf = sv.fcap = 0;
+  sv.fmap = nullptr;
   sv.SBinv = nullptr;
-  if (ctx->opt.sbinv) {
-    constexpr int WS = sizeof(R) == 4 ? 256 : 128;
-    const long nsb = (n3 + WS - 1) / WS;
-    sv.SBinv = dbuf<C_t<R>>(ctx, "SBinv", (long)nkf * nsb * WS * WS);
-    C_t<R>* sbw = dbuf<C_t<R>>(ctx, "SBwork", (long)nkf * nsb * (WS * WS + WS * WS / 4));
-    PROF_BEGIN(PROF_SBINV);
-    KCHK(sb_inverse_batched<R>((C_t<R>*)sv.A, (int)n3, n3, n3 * n3, nkf, (const C_t<R>*)sv.Dinv,
-                               (n3 / 64) * 4096, (C_t<R>*)sv.SBinv, sbw, st));
-    PROF_END(PROF_SBINV, (double)nkf * 8.0 * n3 * WS * WS / 6.0, (double)nkf * sizeof(C_t<R>) * n3 * WS);
-  }
+  if (ctx->opt.precond == 0) build_factors<R>(sv, q, pen_h, fmap_h, nk, tol_override > 0);
 
   // Per-k activity: every k-point starts active; one whose wanted bands all meet the
   // tolerance is frozen (its basis, Ritz values and residual norms stay as they were)
   // and the remaining iterations skip it.  An active k-point is "far" until its own
   // residual falls below 1e-13/tol, then "near" (see the loop).  Every choice is made per
   // k-point, so a k-point's iterates do not depend on which other k-points share its chunk.
-  std::vector<int> act_h(nk, 1), far_h(nk, 1), near_h(nk, 0);
+  std::vector<int> act_h(nk, 1), far_h(nk, 1), near_h(nk, 0), jac_h(nk), penm_h(nk);
   std::vector<char> near_k(nk, 0);
   sv.kfar = dbuf<int>(ctx, "kfar", nk);
   sv.knear = dbuf<int>(ctx, "knear", nk);
+  sv.kjac = dbuf<int>(ctx, "kjac", nk);
+  sv.kpen = dbuf<int>(ctx, "kpen", nk);
+  for (int k = 0; k < nk; ++k) {
+    jac_h[k] = !pen_h[k];
+    penm_h[k] = pen_h[k];
+  }
   HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(sv.kfar, far_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(sv.kjac, jac_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(sv.kpen, penm_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
   sv.nact = sv.nfar = nk;
   sv.nnear = 0;
+  sv.njac = ctx->opt.precond == 0 ? 0 : nk;
+  sv.npen = nk - sv.njac;
 
   // Initial block: unit vectors of the smallest |K_p| (or the given start vectors); W = P = 0.
   launch_zero(sv.Big, (long)nk * sv.sBig, st);
@@ -931,11 +988,19 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
   std::vector<int> sw_h(nk);
   std::vector<char> kdone(nk, 0);
+  std::vector<double> whist;  // per iteration and k: the largest residual of the wanted bands
   out.converged = false;
   int it = 0;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
     const Sel all{sv.kact, sv.nact}, far{sv.kfar, sv.nfar}, nearsel{sv.knear, sv.nnear};
-    cholqr(sv, all);
+    // rr_fused 2: a k-point far from convergence takes both orthonormalisations in the small
+    // space (one Gram product and one basis update per iteration); otherwise one explicit
+    // Omega-CholQR of the basis first
+    if (ctx->opt.rr_fused == 2) {
+      if (sv.nnear > 0) cholqr(sv, nearsel);
+    } else {
+      cholqr(sv, all);
+    }
     // The folded form multiplies the Gram matrix of K by the second orthonormalisation's
     // coefficients in the small space, which amplifies its rounding when the basis is
     // nearly dependent; near convergence (a k-point whose residual is below 1e-13/tol)
@@ -972,15 +1037,13 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       char* hp = (char*)hbuf(ctx, nrn + nsw + sizeof(int));
       HIPCHK(hipMemcpyAsync(hp, sv.rn, nrn, hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hp + nrn, sv.sweeps, nsw, hipMemcpyDeviceToHost, st));
-      if (it == 0) HIPCHK(hipMemcpyAsync(hp + nrn + nsw, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hp + nrn + nsw, ctx->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
       wait_stream(ctx, st);
       memcpy(rn_h.data(), hp, nrn);
       memcpy(sw_h.data(), hp + nrn, nsw);
-      if (it == 0) {
-        int flag = 0;
-        memcpy(&flag, hp + nrn + nsw, sizeof(int));
-        if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
-      }
+      int flag = 0;
+      memcpy(&flag, hp + nrn + nsw, sizeof(int));
+      if (flag) fail(ctx, PHX_ENOTPD, "pencil K + sigma Omega failed its Cholesky factorisation");
     }
     for (int v : sw_h) ctx->stats.rr_sweeps = std::max(ctx->stats.rr_sweeps, v);
     ctx->prof.flush();
@@ -997,6 +1060,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
         }
       }
       if (!(wk == wk)) fail(ctx, PHX_EHIP, "eigensolver produced a non-finite residual");
+      whist.push_back(wk);
       if (wk < 1e-13 / tol) near_k[k] = 1;
       worst = std::max(worst, wk);
     }
@@ -1020,27 +1084,58 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       break;
     }
     if (it == ctx->opt.maxit) break;
+    // precond 2: block Jacobi while it converges; a k-point still iterating whose residual
+    // has not fallen tenfold over the last four iterations (or that reaches 30) gets its
+    // own pencil factor (shared with k-points that stall in the same iteration, as
+    // "kshare" allows) and is preconditioned by it from here on.  The decision is per
+    // k-point, like every other decision of the iteration.
+    if (ctx->opt.precond == 2) {
+      std::vector<int> stall(nk, 0);
+      int nst = 0;
+      for (int k = 0; k < nk; ++k) {
+        if (!act_h[k] || pen_h[k]) continue;
+        const int w = ctx->opt.stall_its;
+        stall[k] = it >= 30 || (it >= w && whist[(size_t)it * nk + k] > 0.1 * whist[(size_t)(it - w) * nk + k]);
+        nst += stall[k];
+      }
+      if (nst > 0) {
+        int cap = 0;  // the k-points that may still need a factor
+        for (int k = 0; k < nk; ++k) cap += act_h[k] && !pen_h[k];
+        build_factors<R>(sv, q, stall, fmap_h, cap, tol_override > 0);
+        for (int k = 0; k < nk; ++k) pen_h[k] = pen_h[k] || stall[k];
+        ctx->stats.precond_switches += nst;
+      }
+    }
     // masks for the next iteration
     {
-      int na = 0, nf = 0, nn = 0;
+      int na = 0, nf = 0, nn = 0, nj = 0, np = 0;
       bool chg = false;
       for (int k = 0; k < nk; ++k) {
         const int f = act_h[k] && !near_k[k], n = act_h[k] && near_k[k];
-        chg = chg || f != far_h[k] || n != near_h[k];
+        const int j = act_h[k] && !pen_h[k], pm = act_h[k] && pen_h[k];
+        chg = chg || f != far_h[k] || n != near_h[k] || j != jac_h[k] || pm != penm_h[k];
         far_h[k] = f;
         near_h[k] = n;
+        jac_h[k] = j;
+        penm_h[k] = pm;
         na += act_h[k];
         nf += f;
         nn += n;
+        nj += j;
+        np += pm;
       }
       if (chg) {
         HIPCHK(hipMemcpyAsync(sv.kact, act_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(sv.kfar, far_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sv.kjac, jac_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sv.kpen, penm_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
       }
       sv.nact = na;
       sv.nfar = nf;
       sv.nnear = nn;
+      sv.njac = nj;
+      sv.npen = np;
     }
     precondition<R>(sv);
     apply_ops(sv, sv.Big, s, s);
@@ -1162,7 +1257,7 @@ long chunk_sensitivities(Solver& sv, const std::vector<double>& theta, const std
 int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int prec, double* omega, double* ebound,
                const std::vector<int>& sel, double* sens_dev, Design* dc = nullptr) {
   const int s = choose_block(ctx, nb, d.N);
-  const long per = per_k_bytes(d, s, prec);
+  const long per = per_k_bytes(d, s, prec, ctx->opt.precond);
   int kc = (int)std::max<long>(1, std::min<long>(nk, (long)(ctx->opt.mem_gb * 1073741824.0) / per));
   ctx->stats = Stats();
   ctx->stats.block = s;
@@ -1345,7 +1440,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
   else if (k == "streams") { if (!(v >= 1 && v <= 16)) return bad(); ctx->opt.streams = (int)v; }
-  else if (k == "rr_fused") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.rr_fused = (int)v; }
+  else if (k == "rr_fused") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
   else if (k == "kskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.kskip = (int)v; }
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
@@ -1356,6 +1451,8 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "degen_tol") { if (!(v >= 0 && v < 1e-2)) return bad(); ctx->opt.degen_tol = v; }
   else if (k == "mem_limit_gb") { if (!(v >= 0 && v < 1e6)) return bad(); ctx->opt.mem_limit_gb = v; }
+  else if (k == "precond") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.precond = (int)v; }
+  else if (k == "stall_its") { if (!(v >= 2 && v <= 30 && v == (int)v)) return bad(); ctx->opt.stall_its = (int)v; }
   else if (k == "profile") {
     if (!(v == 0 || v == 1 || v == 2)) return bad();
     ctx->prof.on = v != 0;
@@ -1379,6 +1476,7 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   else if (k == "iters_mean_k") *value = ctx->stats.k_count ? (double)ctx->stats.k_conv_iters / ctx->stats.k_count : 0;
   else if (k == "degen") *value = (double)ctx->stats.degen;
   else if (k == "enomem_retries") *value = ctx->stats.enomem_retries;
+  else if (k == "precond_switches") *value = ctx->stats.precond_switches;
   else if (k == "mem_bytes") *value = (double)ctx->mem_used;
   else if (k.rfind("prof.", 0) == 0) {
     const size_t dot = k.rfind('.');

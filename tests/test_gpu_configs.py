@@ -95,11 +95,13 @@ def test_fcc_uneven_m_batch(ctx):
 def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
     """The benchmark's timed configuration: 16 FCC 32^3 designs at M=5, 60 k-points, 12
     bands and the adjoint of bands 6/7 in mixed precision through one batched call on 12
-    library streams, with the benchmark's factor sharing (up to 8 k-points per factor
-    within 1.0 cycles/a).  Design 0 at two k-points against the FP64 oracle: every
-    frequency within 1e-6 relative and both sensitivity fields within 1e-6 of their
-    largest entry (bands 6 and 7 are checked to be non-degenerate there); and the FP64
-    path on the same design and k-points: frequencies within 1e-9, sensitivities 1e-6."""
+    library streams, with the benchmark's options (the default preconditioner; factor
+    sharing up to 8 k-points per factor within 1.0 cycles/a should it switch to the
+    pencil).  Design 0 at two k-points against the FP64 oracle: every frequency within
+    1e-6 relative and both sensitivity fields within 1e-6 of their largest entry (bands 6
+    and 7 are checked to be non-degenerate there); and the FP64 path with the pencil
+    preconditioner (precond 0) on the same design and k-points: frequencies within 1e-9,
+    sensitivities 1e-6."""
     import torch
     from oracle import adjoint, geometry
     wl = synth.config4(all_m5=True, ndesign=16)
@@ -145,14 +147,17 @@ def test_fcc_m5_benchmark_configuration_vs_oracle(ctx):
             e = np.abs(dw[i, j] - dw_ref[i, j]).max() / np.abs(dw_ref[i, j]).max()
             log("k", ks[i], "band", b, "sensitivity error", e)
             assert e <= 1e-6
-    # the FP64 path, same design and k-points
+    # the FP64 path with the pencil preconditioner, same design and k-points
     ctx.set_option("tol_fp64", 1e-10)
+    ctx.set_option("precond", 0)
     try:
         t = time.time()
         om64, dw64 = ctx.sens_dev(wl.cells[0], rhos[0], q[ks], wl.nbands, wl.sens_bands, "fp64")
-        log("FP64 path, 2 k-points:", round(time.time() - t, 2), "s")
+        log("FP64 path, 2 k-points:", round(time.time() - t, 2), "s, factors", ctx.stat("factors"))
+        assert ctx.stat("factors") > 0
     finally:
         ctx.set_option("tol_fp64", 1e-8)
+        ctx.set_option("precond", 2)
     om64, dw64 = om64.cpu().numpy(), dw64.cpu().numpy()
     err64 = _rel(om64, om_ref)
     log("fp64 vs oracle, max rel omega error", err64.max(), "per band",

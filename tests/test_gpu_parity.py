@@ -173,18 +173,24 @@ def test_bands_mixed_config1(ctx, config1_ref):
     assert err.max() <= 1e-6
 
 
-@pytest.mark.parametrize("fused", [0, 1])
-def test_bands_fp64_config1_both_rayleigh_ritz_forms(ctx, config1_ref, fused):
-    """The Rayleigh-Ritz step with the second orthonormalisation folded into the small
-    problem and the one with two explicit orthonormalisations both meet the FP64 bar."""
+@pytest.mark.parametrize("fused", [0, 1, 2])
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_bands_config1_rayleigh_ritz_forms(ctx, config1_ref, fused, prec, bar):
+    """The Rayleigh-Ritz step with two explicit orthonormalisations (0), with the second
+    folded into the small problem (1) and with both folded while a k-point is far from
+    convergence (2) all meet the bar."""
     cell, rho, Q, ref = config1_ref
+    old = ctx.stat("iters")
     ctx.set_option("rr_fused", fused)
     ctx.set_option("tol_fp64", 1e-10)
-    om = ctx.bands(cell, rho, Q, ref.shape[1], "fp64")
-    log("rr_fused", fused, "iters", ctx.stat("iters"), "max rel err", _om_err(om, ref).max())
-    ctx.set_option("rr_fused", 1)
-    ctx.set_option("tol_fp64", 1e-8)
-    assert _om_err(om, ref).max() <= 1e-9
+    try:
+        om = ctx.bands(cell, rho, Q, ref.shape[1], prec)
+        log("rr_fused", fused, prec, "iters", ctx.stat("iters"), "mean", ctx.stat("iters_mean_k"), "max rel err",
+            _om_err(om, ref).max())
+    finally:
+        ctx.set_option("rr_fused", 2)
+        ctx.set_option("tol_fp64", 1e-8)
+    assert _om_err(om, ref).max() <= bar
 
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
@@ -213,22 +219,26 @@ def test_bands_config1_converged_k_points_frozen_or_not(ctx, config1_ref, prec, 
 
 @pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-10, 1e-9), ("mixed", 1e-6, 1e-6)])
 def test_bands_shared_preconditioner_factors(ctx, prec, tol, bar):
-    """Neighbouring k-points sharing one preconditioner factor (option kshare; SC 16^3,
-    M=3, 30 k-points about 0.13 apart) give the same bands as one factor per k-point,
-    with fewer factorisations."""
+    """Neighbouring k-points sharing one preconditioner factor of the pencil (precond 0,
+    option kshare; SC 16^3, M=3, 30 k-points about 0.13 apart) give the same bands as one
+    factor per k-point, with fewer factorisations."""
     wl = synth.config2()
     cell, rho = wl.cells[0], wl.designs[0]
     q = phx.kpath(cell.lattice, wl.nk, wl.path)
     key = "tol_fp64" if prec == "fp64" else "tol_mixed"
     ctx.set_option(key, tol)
+    ctx.set_option("precond", 0)
     res, nf = {}, {}
-    for ks in (1, 2):
-        ctx.set_option("kshare", ks)
-        res[ks] = ctx.bands(cell, rho, q, wl.nbands, prec)
-        nf[ks] = ctx.stat("factors")
-        log(prec, "kshare", ks, "factors", nf[ks], "iters", ctx.stat("iters"), "mean", ctx.stat("iters_mean_k"))
-    ctx.set_option("kshare", 2)
-    ctx.set_option(key, 1e-8 if prec == "fp64" else 1e-6)
+    try:
+        for ks in (1, 2):
+            ctx.set_option("kshare", ks)
+            res[ks] = ctx.bands(cell, rho, q, wl.nbands, prec)
+            nf[ks] = ctx.stat("factors")
+            log(prec, "kshare", ks, "factors", nf[ks], "iters", ctx.stat("iters"), "mean", ctx.stat("iters_mean_k"))
+    finally:
+        ctx.set_option("precond", 2)
+        ctx.set_option("kshare", 2)
+        ctx.set_option(key, 1e-8 if prec == "fp64" else 1e-6)
     assert nf[1] == wl.nk and nf[2] < wl.nk
     assert _om_err(res[2], res[1]).max() <= bar
 
@@ -329,6 +339,63 @@ def test_sens_mixed_config2(ctx, config2_ref):
     ctx.set_option("tol_mixed", 1e-6)
     assert _om_err(om, om_ref).max() <= 1e-6
     assert _sens_compare(om_ref, dw_ref, om, dw, 1e-6) >= 30
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_jacobi_preconditioner_matches_oracle(ctx, config2_ref, prec):
+    """Option precond = 1: the eigensolver preconditioned by the 3 x 3 per-wave diagonal
+    blocks of K(k) + sigma Omega, built from the diagonals of the k-shared operators, so no
+    K(k) is assembled or factored (no preconditioner factorisations counted).  Same bars as
+    the default preconditioner."""
+    cell, rho, Q, nb, bands, om_ref, dw_ref = config2_ref
+    ctx.set_option("precond", 1)
+    ctx.set_option("tol_fp64", 1e-10)
+    ctx.set_option("tol_mixed", 1e-9)
+    try:
+        om, dw = ctx.sens(cell, rho, Q, nb, bands, prec)
+        log("block Jacobi", prec, "iters", ctx.stat("iters"), "mean k iters", ctx.stat("iters_mean_k"),
+            "factors", ctx.stat("factors"))
+        assert ctx.stat("factors") == 0
+    finally:
+        ctx.set_option("precond", 2)
+        ctx.set_option("tol_fp64", 1e-8)
+        ctx.set_option("tol_mixed", 1e-6)
+    assert _om_err(om, om_ref).max() <= (1e-9 if prec == "fp64" else 1e-6)
+    assert _sens_compare(om_ref, dw_ref, om, dw, 1e-6) >= 30
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_preconditioner_choices_on_a_sharp_inclusion(ctx, prec):
+    """A sharp tungsten-carbide ball in epoxy (SC 12^3, M=3), where block Jacobi alone
+    converges slowly: the default (precond 2) moves the stalled k-points to pencil factors and
+    matches the oracle like the pencil from the start (precond 0); block Jacobi alone
+    (precond 1) also reaches the tolerance, in many more iterations."""
+    from oracle import geometry, solve
+    cell = synth.Cell("SC", 1.0, 12, 3)
+    rho = synth.sphere(12, "SC", 0.35)
+    Q = geometry.kpath("SC", 10, "GXMGR")[[2, 6]]
+    ref = solve.bands(cell, rho, Q, 10)
+    bar = 1e-9 if prec == "fp64" else 1e-6
+    ctx.set_option("tol_fp64", 1e-10)
+    its = {}
+    try:
+        for pc in (0, 1, 2):
+            ctx.set_option("precond", pc)
+            ctx.set_option("maxit", 3000 if pc == 1 else 60)
+            om = ctx.bands(cell, rho, Q, 10, prec)
+            its[pc] = (ctx.stat("iters"), ctx.stat("factors"), ctx.stat("precond_switches"))
+            log("sphere", prec, "precond", pc, "iters, factors, switches", its[pc], "err", _om_err(om, ref).max())
+            assert _om_err(om, ref).max() <= bar
+        assert its[2][2] >= 1 and its[2][1] > 0 and its[1][1] == 0 and its[0][2] == 0
+        assert its[1][0] > its[0][0]
+        wl = synth.config1()
+        ctx.set_option("precond", 2)
+        ctx.bands(wl.cells[0], wl.designs[0], Q, 8, prec)
+        log("smooth config-1 design: k-points moved to the pencil", ctx.stat("precond_switches"), "of", len(Q))
+    finally:
+        ctx.set_option("precond", 2)
+        ctx.set_option("maxit", 60)
+        ctx.set_option("tol_fp64", 1e-8)
 
 
 def test_adjoint_is_weighted_sum(ctx, config2_ref):
@@ -465,11 +532,13 @@ def test_small_rr_generalised(ctx, m, s, ndep):
 def test_kernel_class_timing(ctx):
     """The single-kernel timing classes (each launch records events at its kernel's start
     and end) see every launch, with positive durations and work, with the stage timers
-    on (profile 1) or off (profile 2)."""
+    on (profile 1) or off (profile 2); the pencil preconditioner (precond 0), so that the
+    factorisation and solve classes run."""
     wl = synth.config2()
     cell, rho = wl.cells[0], wl.designs[0]
     q = phx.kpath(cell.lattice, wl.nk, wl.path)
     counts = {}
+    ctx.set_option("precond", 0)
     for mode in (1, 2):
         ctx.set_option("profile_reset", 1)
         ctx.set_option("profile", mode)
@@ -486,6 +555,7 @@ def test_kernel_class_timing(ctx):
         assert (stage > 0) if mode == 1 else (stage == 0)
     for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
         assert counts[1, c] == counts[2, c]
+    ctx.set_option("precond", 2)
 
 
 @pytest.mark.parametrize("key,bad,good", [
@@ -497,7 +567,12 @@ def test_kernel_class_timing(ctx):
     ("streams", (0, 17), (1, 16)),
     ("profile", (3, -1), (0, 1, 2)),
     ("spin_wait", (2,), (0, 1)),
+    ("rr_fused", (3, -1), (0, 1, 2)),
+    ("stall_its", (1, 31, 2.5), (2, 8, 30)),
     ("gram_split", (-1, 17, 2.5), (0, 1, 16)),
+    ("precond", (-1, 3, 0.5), (0, 1, 2)),
+    ("degen_tol", (-1e-9, 0.1), (0, 1e-8)),
+    ("mem_limit_gb", (-1,), (0, 8.0)),
     ("no_such_option", (1.0,), ()),
 ])
 def test_option_ranges(key, bad, good):

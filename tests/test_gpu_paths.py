@@ -70,8 +70,12 @@ def config2():
     return cell, rho, q, wl.nbands, wl.sens_bands
 
 
-def test_k_chunks_equal_one_chunk(ctx, config2):
+@pytest.mark.parametrize("precond", [0, 2])
+def test_k_chunks_equal_one_chunk(ctx, config2, precond):
+    """Chunking with the pencil preconditioner (precond 0: shared factor groups end at chunk
+    boundaries) and with the default (block Jacobi on this smooth design)."""
     cell, rho, q, nb, bands = config2
+    ctx.set_option("precond", precond)
     res = {}
     small = {"fp64": 0.3, "mixed": 0.18}  # about 10 k-points per chunk (FP32 factors are half the size)
     try:
@@ -87,6 +91,7 @@ def test_k_chunks_equal_one_chunk(ctx, config2):
     finally:
         ctx.set_option("kshare", 2)
         ctx.set_option("mem_gb", 64.0)
+        ctx.set_option("precond", 2)
     for prec in ("fp64", "mixed"):
         one, three = res[1, "all", prec], res[1, "small", prec]
         assert one[2] == 1 and three[2] >= 3, (one[2], three[2])
@@ -98,13 +103,15 @@ def test_k_chunks_equal_one_chunk(ctx, config2):
         assert _om_err(b[0], a[0]).max() <= tol
 
 
-def test_k_point_alone_equals_k_point_in_a_chunk(ctx):
+@pytest.mark.parametrize("precond", [0, 1])
+def test_k_point_alone_equals_k_point_in_a_chunk(ctx, precond):
     """Per-k independence, including the order M-2 start (M = 4) and the near-convergence
-    switch of the FP64 path."""
+    switch of the FP64 path, with the pencil and with block Jacobi."""
     cases = [(synth.Cell("SC", 1.0, 8, 2), synth.box_smoothed_uniform(8, 101), "SC"),
              (synth.Cell("BCC", 1.0, 9, 4), synth.box_smoothed_uniform(9, 13), "BCC")]
     ctx.set_option("kshare", 1)
     ctx.set_option("tol_fp64", 1e-10)
+    ctx.set_option("precond", precond)
     try:
         for cell, rho, lat in cases:
             q = phx.kpath(lat, 12)[[1, 4, 9]]
@@ -116,11 +123,14 @@ def test_k_point_alone_equals_k_point_in_a_chunk(ctx):
     finally:
         ctx.set_option("kshare", 2)
         ctx.set_option("tol_fp64", 1e-8)
+        ctx.set_option("precond", 2)
 
 
 def test_enomem_retries_with_smaller_chunks(ctx, config2):
+    """The pencil preconditioner (precond 0), whose factors dominate the workspace."""
     cell, rho, q, nb, bands = config2
     ctx.set_option("kshare", 1)
+    ctx.set_option("precond", 0)
     try:
         ref_om, ref_dw = ctx.sens(cell, rho, q, nb, bands, "fp64")
         assert ctx.stat("enomem_retries") == 0
@@ -143,6 +153,7 @@ def test_enomem_retries_with_smaller_chunks(ctx, config2):
     finally:
         ctx.set_option("mem_limit_gb", 0)
         ctx.set_option("kshare", 2)
+        ctx.set_option("precond", 2)
 
 
 # ----------------------------------------------------------------------------- iteration cap
