@@ -21,23 +21,170 @@ namespace phx {
 
 constexpr int SMALL_NT = 1024;  // threads per workgroup of the small kernels (latency bound)
 
-__global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, int m, double drop, double2* C0,
-                                                        int* keep, const int* kact) {
-  if (kact && !kact[blockIdx.x]) return;  // a converged k-point
-  __shared__ double2 Ls[64][65];  // [col][row]
-  __shared__ double2 Xs[64][65];
-  __shared__ double D[64];
-  __shared__ int kp[64];
-  __shared__ double piv;
+// Shared state of the Jacobi eigensolver of one workgroup.
+struct JacobiLDS {
+  double2 As[64][65];  // [col][row]
+  double2 Vs[64][65];
+  int pp[32], qq[32], act[32];
+  double cs_[32], sn_[32];
+  double2 ph_[32];
+  double wred[SMALL_NT / 64][2];  // per-wave partial results of a reduction
+  int order[64];
+  int rot[2];  // per sweep parity: some pair rotated
+};
+
+// Wave-level sum and max (64 lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Max-reduction of one value per thread over the workgroup (L: an LDS state with wred).
+template <typename LDS>
+__device__ double block_max(LDS& L, double v) {
   const int tid = threadIdx.x;
-  const int k = blockIdx.x;
-  const double2* Gk = G + (long)k * m * m;
-  for (int e = tid; e < m * m; e += SMALL_NT) {
-    const int i = e % m, j = e / m;
-    const double2 a = Gk[i + j * m], b = Gk[j + i * m];
-    Ls[j][i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-  }
+  v = wave_max(v);
+  if ((tid & 63) == 0) L.wred[tid >> 6][0] = v;
   __syncthreads();
+  double r = L.wred[0][0];
+  for (int w = 1; w < SMALL_NT / 64; ++w) r = fmax(r, L.wred[w][0]);
+  __syncthreads();
+  return r;
+}
+
+// Cyclic Jacobi on the Hermitian mm x mm matrix L.As (mm even), accumulating the
+// rotations into L.Vs; returns the number of sweeps.  Each round rotates the mm/2 disjoint
+// pairs of the round-robin ordering at once: A <- J^H A J as (mm/2)^2 independent 2 x 2
+// blocks (rows of pair i, columns of pair j) and V <- V J, two barriers per round.
+__device__ int jacobi_sweeps(JacobiLDS& L, int mm, double floor_abs) {
+  const int tid = threadIdx.x;
+  const int half = mm / 2;
+  int sw = 0;
+  for (sw = 0; sw < 40; ++sw) {
+    // stop when the off-diagonal part is at rounding level, or the last sweep rotated nothing
+    double off = 0, dg = 0;
+    for (int e = tid; e < mm * mm; e += SMALL_NT) {
+      const int i = e % mm, j = e / mm;
+      const double a2 = cabs2(L.As[j][i]);
+      if (i == j) dg += a2; else off += a2;
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    if ((tid & 63) == 0) {
+      L.wred[tid >> 6][0] = off;
+      L.wred[tid >> 6][1] = dg;
+    }
+    __syncthreads();
+    double to = 0, td = 0;
+    for (int w = 0; w < SMALL_NT / 64; ++w) {
+      to += L.wred[w][0];
+      td += L.wred[w][1];
+    }
+    const bool stop = to <= 1e-32 * td || (sw > 0 && !L.rot[(sw - 1) & 1]);
+    __syncthreads();  // wred and rot read by every thread before they change
+    if (stop) break;
+    if (tid == 0) L.rot[sw & 1] = 0;
+    for (int r = 0; r < mm - 1; ++r) {
+      // rotation of each pair from its 2 x 2 diagonal block; below the thresholds the pair's
+      // off-diagonal entries are set to zero and its rotation is the identity
+      if (tid < half) {
+        int p, q;
+        if (tid == 0) { p = r; q = mm - 1; }
+        else { p = (r + tid) % (mm - 1); q = (r - tid + mm - 1) % (mm - 1); }
+        const double a = L.As[p][p].x, b = L.As[q][q].x;
+        const double2 c = L.As[q][p];  // row p, col q
+        // |c| scaled so that its square cannot underflow into subnormals.
+        const double cm = fmax(fabs(c.x), fabs(c.y));
+        double ac = 0.0;
+        if (cm > 0) {
+          const double xr = c.x / cm, yr = c.y / cm;
+          ac = cm * sqrt(xr * xr + yr * yr);
+        }
+        int act = 0;
+        double cs = 1.0, sn = 0.0;
+        double2 ph = make_double2(1.0, 0.0);
+        if (!(ac > floor_abs && ac > 1e-15 * sqrt(fabs(a) * fabs(b)))) {
+          L.As[q][p] = make_double2(0.0, 0.0);
+          L.As[p][q] = make_double2(0.0, 0.0);
+        } else {
+          act = 1;
+          ph = make_double2(c.x / ac, -c.y / ac);
+          const double tau = (b - a) / (2.0 * ac);
+          double t;
+          if (fabs(tau) > 1e150) t = 0.5 / tau;
+          else t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          cs = 1.0 / sqrt(1.0 + t * t);
+          sn = t * cs;
+          L.rot[sw & 1] = 1;
+        }
+        L.pp[tid] = p; L.qq[tid] = q; L.act[tid] = act;
+        L.cs_[tid] = cs; L.sn_[tid] = sn; L.ph_[tid] = ph;
+      }
+      __syncthreads();
+      // A <- J^H A J: block (i, j) holds rows p_i, q_i and columns p_j, q_j.  Columns
+      // (A J): c_p' = cs c_p - sn ph c_q, c_q' = sn c_p + cs ph c_q; rows (J^H A):
+      // r_p' = cs r_p - sn conj(ph) r_q, r_q' = sn r_p + cs conj(ph) r_q.
+      for (int e = tid; e < half * half; e += SMALL_NT) {
+        const int i = e % half, j = e / half;
+        const int ai = L.act[i], aj = L.act[j];
+        if (!ai && !aj) continue;
+        const int p = L.pp[i], q = L.qq[i], pc = L.pp[j], qc = L.qq[j];
+        double2 b00 = L.As[pc][p], b10 = L.As[pc][q], b01 = L.As[qc][p], b11 = L.As[qc][q];
+        if (aj) {
+          const double c = L.cs_[j], sj = L.sn_[j];
+          const double2 ph = L.ph_[j];
+          const double2 t0 = cmul(ph, b01), t1 = cmul(ph, b11);
+          const double2 n00 = csub(cscale(b00, c), cscale(t0, sj)), n01 = cadd(cscale(b00, sj), cscale(t0, c));
+          const double2 n10 = csub(cscale(b10, c), cscale(t1, sj)), n11 = cadd(cscale(b10, sj), cscale(t1, c));
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+        }
+        if (ai) {
+          const double c = L.cs_[i], si = L.sn_[i];
+          const double2 phc = cconj(L.ph_[i]);
+          const double2 t0 = cmul(phc, b10), t1 = cmul(phc, b11);
+          const double2 n00 = csub(cscale(b00, c), cscale(t0, si)), n10 = cadd(cscale(b00, si), cscale(t0, c));
+          const double2 n01 = csub(cscale(b01, c), cscale(t1, si)), n11 = cadd(cscale(b01, si), cscale(t1, c));
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+        }
+        if (i == j) {  // the rotated diagonal block: exactly diagonal and real
+          b00.y = 0.0;
+          b11.y = 0.0;
+          b01 = make_double2(0.0, 0.0);
+          b10 = make_double2(0.0, 0.0);
+        }
+        L.As[pc][p] = b00; L.As[pc][q] = b10; L.As[qc][p] = b01; L.As[qc][q] = b11;
+      }
+      // V <- V J on the columns of the rotated pairs
+      for (int e = tid; e < mm * half; e += SMALL_NT) {
+        const int row = e % mm, j = e / mm;
+        if (!L.act[j]) continue;
+        const int p = L.pp[j], q = L.qq[j];
+        const double c = L.cs_[j], sj = L.sn_[j];
+        const double2 vp = L.Vs[p][row], phvq = cmul(L.ph_[j], L.Vs[q][row]);
+        L.Vs[p][row] = csub(cscale(vp, c), cscale(phvq, sj));
+        L.Vs[q][row] = cadd(cscale(vp, sj), cscale(phvq, c));
+      }
+      __syncthreads();
+    }
+  }
+  return sw;
+}
+
+// Omega-orthonormalisation coefficients from the Hermitian Gram matrix in Ls (m x m,
+// [col][row]), in place: columns scaled to unit norm (D), Cholesky with dropping (a pivot at
+// or below `drop` drops its column: kp = 0), then the inverse Xs of the lower factor.
+// Every thread of the workgroup calls it.  The factorisation takes two barriers per
+// column: every thread takes the same pivot decision from the same value, the scaled
+// column goes to lc, then the trailing update reads lc; the inverse needs none: lane t
+// forms column t of L^{-1} by forward substitution, reading only the finished factor and
+// its own column.
+__device__ void chol_drop_all(double2 (&Ls)[64][65], double2 (&Xs)[64][65], double* D, int* kp, double2* lc, int m,
+                              double drop) {
+  const int tid = threadIdx.x;
   if (tid < m) {
     const double d = Ls[tid][tid].x;
     const bool ok = d > 1e-300 && isfinite(d);
@@ -51,44 +198,55 @@ __global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, i
   }
   __syncthreads();
   for (int c = 0; c < m; ++c) {
-    if (tid == 0) {
-      const double pv = Ls[c][c].x;
-      const int kc = kp[c] && (pv > drop);
-      kp[c] = kc;
-      piv = kc ? sqrt(pv) : 0.0;
-    }
-    __syncthreads();
-    const double pc = piv;
+    const double pv = Ls[c][c].x;
+    const int kc = kp[c] && (pv > drop);
+    const double pc = kc ? sqrt(pv) : 0.0;
+    if (tid < m) lc[tid] = (tid > c && pc > 0) ? cscale(Ls[c][tid], 1.0 / pc) : make_double2(0, 0);
+    __syncthreads();  // every thread has read the pivot; lc complete
+    if (tid == 0) kp[c] = kc;
     if (pc > 0) {
-      if (tid == c) Ls[c][c] = make_double2(pc, 0.0);
-      if (tid > c && tid < m) Ls[c][tid] = cscale(Ls[c][tid], 1.0 / pc);
+      if (tid < m) Ls[c][tid] = tid == c ? make_double2(pc, 0.0) : (tid > c ? lc[tid] : Ls[c][tid]);
+      const int r = m - c - 1;  // trailing rows and columns c+1 .. m-1
+      for (int e = tid; e < r * r; e += SMALL_NT) {
+        const int i = c + 1 + e % r, j = c + 1 + e / r;
+        if (i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(lc[i], lc[j]));
+      }
     } else {
       if (tid < m) Ls[c][tid] = make_double2(tid == c ? 1.0 : 0.0, 0.0);
       if (tid < c) Ls[tid][c] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    if (pc > 0) {
-      for (int e = tid; e < m * m; e += SMALL_NT) {
-        const int i = e % m, j = e / m;
-        if (j > c && i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(Ls[c][i], Ls[c][j]));
-      }
-    }
-    __syncthreads();
   }
-  // Xs = L^{-1}, one row at a time (thread t owns column t).
-  for (int i = 0; i < m; ++i) {
-    if (tid < m) {
-      const int t = tid;
-      double2 v = make_double2(0, 0);
-      if (t <= i) {
-        double2 s = make_double2(t == i ? 1.0 : 0.0, 0.0);
-        for (int l = t; l < i; ++l) s = csub(s, cmul(Ls[l][i], Xs[t][l]));
-        v = cscale(s, 1.0 / Ls[i][i].x);
-      }
-      Xs[t][i] = v;
+  if (tid < m) {  // column t of L^{-1}: rows t .. m-1
+    const int t = tid;
+    for (int i = 0; i < t; ++i) Xs[t][i] = make_double2(0.0, 0.0);
+    for (int i = t; i < m; ++i) {
+      double2 sacc = make_double2(i == t ? 1.0 : 0.0, 0.0);
+      for (int l = t; l < i; ++l) sacc = csub(sacc, cmul(Ls[l][i], Xs[t][l]));
+      Xs[t][i] = cscale(sacc, 1.0 / Ls[i][i].x);
     }
-    __syncthreads();
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, int m, double drop, double2* C0,
+                                                        int* keep, const int* kact) {
+  if (kact && !kact[blockIdx.x]) return;  // a converged k-point
+  __shared__ double2 Ls[64][65];  // [col][row]
+  __shared__ double2 Xs[64][65];
+  __shared__ double D[64];
+  __shared__ int kp[64];
+  __shared__ double2 lc[64];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x;
+  const double2* Gk = G + (long)k * m * m;
+  for (int e = tid; e < m * m; e += SMALL_NT) {
+    const int i = e % m, j = e / m;
+    const double2 a = Gk[i + j * m], b = Gk[j + i * m];
+    Ls[j][i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  }
+  __syncthreads();
+  chol_drop_all(Ls, Xs, D, kp, lc, m, drop);
   double2* Ck = C0 + (long)k * m * m;
   for (int e = tid; e < m * m; e += SMALL_NT) {
     const int r = e % m, c = e / m;
@@ -98,150 +256,6 @@ __global__ __launch_bounds__(SMALL_NT) void chol_drop_kernel(const double2* G, i
     Ck[r + c * m] = v;
   }
   if (tid < m) keep[k * m + tid] = kp[tid];
-}
-
-// Shared state of the Jacobi eigensolver of one workgroup.
-struct JacobiLDS {
-  double2 As[64][65];  // [col][row]
-  double2 Vs[64][65];
-  int pp[32], qq[32];
-  double cs_[32], sn_[32];
-  double2 ph_[32];
-  double red[SMALL_NT], red2[SMALL_NT];
-  int order[64];
-  int stop, rotated, nact;
-};
-
-// Max-reduction of one value per thread over the workgroup (uses L.red).
-__device__ double block_max(JacobiLDS& L, double v) {
-  const int tid = threadIdx.x;
-  L.red[tid] = v;
-  __syncthreads();
-  for (int w = SMALL_NT / 2; w > 0; w >>= 1) {
-    if (tid < w) L.red[tid] = fmax(L.red[tid], L.red[tid + w]);
-    __syncthreads();
-  }
-  const double r = L.red[0];
-  __syncthreads();
-  return r;
-}
-
-// Cyclic Jacobi on the Hermitian mm x mm matrix L.As (mm even), accumulating the
-// rotations into L.Vs; returns the number of sweeps.
-__device__ int jacobi_sweeps(JacobiLDS& L, int mm, double floor_abs) {
-  const int tid = threadIdx.x;
-  const int half = mm / 2;
-  int sw = 0;
-  for (sw = 0; sw < 40; ++sw) {
-    double off = 0, dg = 0;
-    for (int e = tid; e < mm * mm; e += SMALL_NT) {
-      const int i = e % mm, j = e / mm;
-      const double a2 = cabs2(L.As[j][i]);
-      if (i == j) dg += a2; else off += a2;
-    }
-    L.red[tid] = off;
-    L.red2[tid] = dg;
-    __syncthreads();
-    for (int w = SMALL_NT / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        L.red[tid] += L.red[tid + w];
-        L.red2[tid] += L.red2[tid + w];
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      L.stop = (L.red[0] <= 1e-32 * L.red2[0] || (sw > 0 && !L.rotated)) ? 1 : 0;
-      L.rotated = 0;
-    }
-    __syncthreads();
-    if (L.stop) break;
-    for (int r = 0; r < mm - 1; ++r) {
-      // Pair setup (wave 0): rotations below threshold are skipped; the pairs that do
-      // rotate are compacted so that the two update phases touch only their columns.
-      bool act = false;
-      int p = 0, q = 0;
-      double cs = 1.0, sn = 0.0;
-      double2 ph = make_double2(1.0, 0.0);
-      if (tid < half) {
-        if (tid == 0) { p = r; q = mm - 1; }
-        else { p = (r + tid) % (mm - 1); q = (r - tid + mm - 1) % (mm - 1); }
-        const double a = L.As[p][p].x, b = L.As[q][q].x;
-        const double2 c = L.As[q][p];  // row p, col q
-        // |c| scaled so that its square cannot underflow into subnormals.
-        const double cm = fmax(fabs(c.x), fabs(c.y));
-        double ac = 0.0;
-        if (cm > 0) {
-          const double xr = c.x / cm, yr = c.y / cm;
-          ac = cm * sqrt(xr * xr + yr * yr);
-        }
-        if (!(ac > floor_abs && ac > 1e-15 * sqrt(fabs(a) * fabs(b)))) {
-          // below the thresholds: set to zero (this pair owns both entries)
-          L.As[q][p] = make_double2(0.0, 0.0);
-          L.As[p][q] = make_double2(0.0, 0.0);
-        } else {
-          act = true;
-          ph = make_double2(c.x / ac, -c.y / ac);
-          const double tau = (b - a) / (2.0 * ac);
-          double t;
-          if (fabs(tau) > 1e150) t = 0.5 / tau;
-          else t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          cs = 1.0 / sqrt(1.0 + t * t);
-          sn = t * cs;
-        }
-      }
-      if (tid < 64) {
-        const unsigned long long mask = __ballot(act);
-        if (act) {
-          const int slot = __popcll(mask & ((1ull << tid) - 1ull));
-          L.pp[slot] = p; L.qq[slot] = q; L.cs_[slot] = cs; L.sn_[slot] = sn; L.ph_[slot] = ph;
-        }
-        if (tid == 0) {
-          L.nact = __popcll(mask);
-          if (L.nact) L.rotated = 1;
-        }
-      }
-      __syncthreads();
-      const int na = L.nact;
-      if (na == 0) continue;  // uniform: every thread read the same count after the barrier
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < na * mm; e += SMALL_NT) {
-        const int i = e / mm, row = e % mm;
-        const int p = L.pp[i], q = L.qq[i];
-        const double cs = L.cs_[i], sn = L.sn_[i];
-        const double2 ph = L.ph_[i];
-        const double2 ap = L.As[p][row], aq = L.As[q][row];
-        const double2 phaq = cmul(ph, aq);
-        L.As[p][row] = csub(cscale(ap, cs), cscale(phaq, sn));
-        L.As[q][row] = cadd(cscale(ap, sn), cscale(phaq, cs));
-        const double2 vp = L.Vs[p][row], vq = L.Vs[q][row];
-        const double2 phvq = cmul(ph, vq);
-        L.Vs[p][row] = csub(cscale(vp, cs), cscale(phvq, sn));
-        L.Vs[q][row] = cadd(cscale(vp, sn), cscale(phvq, cs));
-      }
-      __syncthreads();
-      // rows: A <- J^H A
-      for (int e = tid; e < na * mm; e += SMALL_NT) {
-        const int i = e / mm, col = e % mm;
-        const int p = L.pp[i], q = L.qq[i];
-        const double cs = L.cs_[i], sn = L.sn_[i];
-        const double2 phc = cconj(L.ph_[i]);
-        const double2 ap = L.As[col][p], aq = L.As[col][q];
-        const double2 phaq = cmul(phc, aq);
-        L.As[col][p] = csub(cscale(ap, cs), cscale(phaq, sn));
-        L.As[col][q] = cadd(cscale(ap, sn), cscale(phaq, cs));
-      }
-      __syncthreads();
-      if (tid < na) {
-        const int p = L.pp[tid], q = L.qq[tid];
-        L.As[q][p] = make_double2(0.0, 0.0);
-        L.As[p][q] = make_double2(0.0, 0.0);
-        L.As[p][p].y = 0.0;
-        L.As[q][q].y = 0.0;
-      }
-      __syncthreads();
-    }
-  }
-  return sw;
 }
 
 // L.order[0..s) = indices of the s lowest diagonal entries of L.As (ties in index order).
@@ -319,7 +333,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int
   __shared__ JacobiLDS L;
   __shared__ double D[64];
   __shared__ int kp[64];
-  __shared__ double piv;
+  __shared__ double2 lc[64];
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
   const double2* GK = G2 + (long)k * 2 * m * m;
@@ -333,56 +347,7 @@ __global__ __launch_bounds__(SMALL_NT) void rr_gen_kernel(const double2* G2, int
     Ls[j][i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
   }
   __syncthreads();
-  if (tid < m) {
-    const double d = Ls[tid][tid].x;
-    const bool ok = d > 1e-300 && isfinite(d);
-    D[tid] = ok ? 1.0 / sqrt(d) : 0.0;
-    kp[tid] = ok ? 1 : 0;
-  }
-  __syncthreads();
-  for (int e = tid; e < m * m; e += SMALL_NT) {
-    const int i = e % m, j = e / m;
-    Ls[j][i] = cscale(Ls[j][i], D[i] * D[j]);
-  }
-  __syncthreads();
-  for (int c = 0; c < m; ++c) {
-    if (tid == 0) {
-      const double pv = Ls[c][c].x;
-      const int kc = kp[c] && (pv > drop);
-      kp[c] = kc;
-      piv = kc ? sqrt(pv) : 0.0;
-    }
-    __syncthreads();
-    const double pc = piv;
-    if (pc > 0) {
-      if (tid == c) Ls[c][c] = make_double2(pc, 0.0);
-      if (tid > c && tid < m) Ls[c][tid] = cscale(Ls[c][tid], 1.0 / pc);
-    } else {
-      if (tid < m) Ls[c][tid] = make_double2(tid == c ? 1.0 : 0.0, 0.0);
-      if (tid < c) Ls[tid][c] = make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    if (pc > 0) {
-      for (int e = tid; e < m * m; e += SMALL_NT) {
-        const int i = e % m, j = e / m;
-        if (j > c && i >= j) Ls[j][i] = csub(Ls[j][i], cmulc(Ls[c][i], Ls[c][j]));
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = 0; i < m; ++i) {  // Xs = L^{-1}, one row at a time (thread t owns column t)
-    if (tid < m) {
-      const int t = tid;
-      double2 v = make_double2(0, 0);
-      if (t <= i) {
-        double2 sacc = make_double2(t == i ? 1.0 : 0.0, 0.0);
-        for (int l = t; l < i; ++l) sacc = csub(sacc, cmul(Ls[l][i], Xs[t][l]));
-        v = cscale(sacc, 1.0 / Ls[i][i].x);
-      }
-      Xs[t][i] = v;
-    }
-    __syncthreads();
-  }
+  chol_drop_all(Ls, Xs, D, kp, lc, m, drop);
   // C0[r][c] = D_r conj(Linv[c][r]) (upper triangular, dropped columns zero)
   auto c0 = [&](int r, int c) -> double2 {
     return (r < m && c < m && kp[c] && c >= r) ? cscale(cconj(Xs[r][c]), D[r]) : make_double2(0, 0);
