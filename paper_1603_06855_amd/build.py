@@ -1,4 +1,5 @@
-"""Builds libphx.so (all HIP sources under csrc/) for gfx950 with hipcc, in-tree."""
+"""Builds libphx.so in-tree: the HIP sources under csrc/ for gfx950 with hipcc, the plain
+C++ host module (no GPU code) with the host compiler, linked by hipcc."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["dense.hip", "physics.hip", "small.hip", "design.hip", "runtime.hip"]
+HOST_SOURCES = ["host.cpp"]
 LIB = os.path.join(HERE, "libphx.so")
 
 
@@ -27,11 +29,20 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         while len([p for _, p in procs if p.poll() is None]) >= jobs:
             procs[[i for i, (_, p) in enumerate(procs) if p.poll() is None][0]][1].wait()
+    cxx = os.environ.get("CXX", "g++")
+    for src in HOST_SOURCES:
+        obj = os.path.join(objdir, src.replace(".cpp", ".o"))
+        objs.append(obj)
+        cmd = [cxx, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"),
+               "-c", os.path.join(HERE, "csrc", src), "-o", obj]
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        while len([p for _, p in procs if p.poll() is None]) >= jobs:
+            procs[[i for i, (_, p) in enumerate(procs) if p.poll() is None][0]][1].wait()
     for cmd, p in procs:
         out, _ = p.communicate()
         msgs = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
         if p.returncode != 0:
-            raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + "\n".join(msgs))
+            raise RuntimeError("compile failed:\n" + " ".join(cmd) + "\n" + "\n".join(msgs))
         if verbose and msgs:
             print("\n".join(msgs), file=sys.stderr)
     tmp = LIB + ".tmp"

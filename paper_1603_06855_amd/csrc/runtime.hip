@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "../../include/phx.h"
+#include "phx_host.h"
 #include "phx_internal.h"
 #include "phx_physics.h"
 
@@ -364,64 +365,19 @@ void wait_stream(phx_ctx* ctx, hipStream_t st) {
   HIPCHK(hipEventSynchronize(ctx->wait_ev));
 }
 
-void prim_rows(int lattice, double A[3][3]) {
-  static const double sc[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  static const double bcc[3][3] = {{-0.5, 0.5, 0.5}, {0.5, -0.5, 0.5}, {0.5, 0.5, -0.5}};
-  static const double fcc[3][3] = {{0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};
-  const double(*s)[3] = lattice == PHX_SC ? sc : (lattice == PHX_BCC ? bcc : fcc);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) A[i][j] = s[i][j];
-}
-
-// Reciprocal rows b_j (a_i . b_j = delta_ij) and |det A|.
-double reciprocal(const double A[3][3], double T[3][3]) {
-  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
-                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
-                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
-  // inverse of A, then transpose: T[j][c] = inv(A)[c][j]
-  double inv[3][3];
-  inv[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
-  inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
-  inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
-  inv[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
-  inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
-  inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
-  inv[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
-  inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
-  inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
-  for (int j = 0; j < 3; ++j)
-    for (int c = 0; c < 3; ++c) T[j][c] = inv[c][j];
-  return fabs(det);
-}
-
-bool material_ok(const phx_material& m) {
-  return isfinite(m.density) && isfinite(m.youngs) && isfinite(m.poisson) && m.density > 0 && m.youngs > 0 &&
-         m.poisson > -1.0 && m.poisson < 0.5;
-}
+using phx_host::prim_rows;
+using phx_host::reciprocal;
 
 void check_cell(phx_ctx* ctx, const phx_cell* c) {
-  if (!c) fail(ctx, PHX_EINVAL, "cell is NULL");
-  if (c->lattice < PHX_SC || c->lattice > PHX_FCC) fail(ctx, PHX_EINVAL, "unknown lattice");
-  if (!(c->a > 0) || !isfinite(c->a)) fail(ctx, PHX_EINVAL, "cube edge a must be positive");
-  if (c->M < 1 || c->M > 8) fail(ctx, PHX_EINVAL, "plane-wave order M must be in [1, 8]");
-  if (c->nv < 2 * c->M + 1) fail(ctx, PHX_EINVAL, "nv must be at least 2M+1 (the centroid rule aliases otherwise)");
-  if (c->nv > 256) fail(ctx, PHX_EINVAL, "nv must be at most 256");
-  if (!material_ok(c->phase0) || !material_ok(c->phase1))
-    fail(ctx, PHX_EINVAL, "material needs density > 0, Young's modulus > 0, Poisson ratio in (-1, 1/2)");
-  if (!(c->simp_p >= 1.0) || !isfinite(c->simp_p)) fail(ctx, PHX_EINVAL, "simp_p must be >= 1");
+  if (const char* e = phx_host::check_cell(c)) fail(ctx, PHX_EINVAL, e);
 }
 
 void check_rho(phx_ctx* ctx, const double* rho, long n) {
-  if (!rho) fail(ctx, PHX_EINVAL, "rho is NULL");
-  for (long e = 0; e < n; ++e)
-    if (!isfinite(rho[e]) || rho[e] < 0) fail(ctx, PHX_EINVAL, "rho must be finite and non-negative");
+  if (const char* e = phx_host::check_rho(rho, n)) fail(ctx, PHX_EINVAL, e);
 }
 
 void check_q(phx_ctx* ctx, const double* q, int nk) {
-  if (nk < 1) fail(ctx, PHX_EINVAL, "nk must be positive");
-  if (!q) fail(ctx, PHX_EINVAL, "q is NULL");
-  for (long i = 0; i < 3L * nk; ++i)
-    if (!isfinite(q[i])) fail(ctx, PHX_EINVAL, "q must be finite");
+  if (const char* e = phx_host::check_q(q, nk)) fail(ctx, PHX_EINVAL, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -771,19 +727,10 @@ void precondition(Solver& sv) {
   }
 }
 
-int choose_block(phx_ctx* ctx, int nb, int N) {
-  int s = ctx->opt.block > 0 ? ctx->opt.block : std::min(21, nb + std::max(8, nb));
-  s = std::min(s, 3 * N);
-  return s;
-}
+int choose_block(phx_ctx* ctx, int nb, int N) { return phx_host::choose_block(ctx->opt.block, nb, N); }
 
 long per_k_bytes(const Design& d, int s, int prec, int precond) {
-  const long n3 = d.n3, m = 3 * s;
-  const long pc = prec == PHX_FP64 ? 16 : 8;
-  const long ws = prec == PHX_FP64 ? 128 : 256;
-  const long factor = precond == 1 ? 0 : n3 * n3 * pc + (n3 / 64) * 4096 * pc + ((n3 + ws - 1) / ws) * ws * ws * pc;
-  return factor + 3L * n3 * m * 16 +
-         2L * n3 * s * pc + 4L * d.Np * 7 * s * 16;
+  return phx_host::per_k_bytes(d.n3, d.Np, s, prec, precond);
 }
 
 // Pencil preconditioner: A = K + sigma Omega assembled and Cholesky-factored for the
@@ -806,28 +753,15 @@ void build_factors(Solver& sv, const double* q, const std::vector<int>& which, s
   const long n3 = sv.n3;
   std::vector<int> lead;
   {
-    const int kmax = ctx->opt.sbinv ? ctx->opt.kshare : 1;
-    auto cart = [&](int k, int c) {
-      return q[3 * k] * d.rec.t[0][c] + q[3 * k + 1] * d.rec.t[1][c] + q[3 * k + 2] * d.rec.t[2][c];
-    };
+    std::vector<double> qc(3L * nk);
+    std::vector<char> w(nk);
     for (int k = 0; k < nk; ++k) {
-      if (!which[k]) continue;
-      bool join = false;
-      if (!lead.empty()) {
-        const int l = lead.back();
-        double dd = 0, kk = 0, ll = 0;
-        for (int c = 0; c < 3; ++c) {
-          dd += (cart(k, c) - cart(l, c)) * (cart(k, c) - cart(l, c));
-          kk += cart(k, c) * cart(k, c);
-          ll += cart(l, c) * cart(l, c);
-        }
-        const double dist = sqrt(dd);
-        join = k - l < kmax && dist <= ctx->opt.kshare_dist &&
-               dist <= ctx->opt.kshare_rel * sqrt(std::min(kk, ll));
-      }
-      if (!join) lead.push_back(k);
-      fmap_h[k] = sv.nf + (int)lead.size() - 1;
+      w[k] = which[k] != 0;
+      for (int c = 0; c < 3; ++c)
+        qc[3 * k + c] = q[3 * k] * d.rec.t[0][c] + q[3 * k + 1] * d.rec.t[1][c] + q[3 * k + 2] * d.rec.t[2][c];
     }
+    phx_host::share_groups(qc.data(), nk, w.data(), ctx->opt.sbinv ? ctx->opt.kshare : 1, ctx->opt.kshare_dist,
+                           ctx->opt.kshare_rel, sv.nf, fmap_h.data(), lead);
   }
   const int nnew = (int)lead.size();
   if (nnew == 0) return;
@@ -1200,51 +1134,23 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
 long chunk_sensitivities(Solver& sv, const std::vector<double>& theta, const std::vector<int>& sel, double* out) {
   phx_ctx* ctx = sv.ctx;
   const int nk = sv.nk, s = sv.s, nsel = (int)sel.size();
-  const double dtol = ctx->opt.degen_tol;
-  std::vector<int> lo((size_t)nk * nsel), hi((size_t)nk * nsel);
-  std::vector<char> use(s, 0);
-  for (int b : sel) use[b] = 1;
-  auto om = [&](int k, int i) { return sqrt(std::max(theta[(size_t)k * s + i], 0.0)); };
-  long ndeg = 0;
-  for (int k = 0; k < nk; ++k)
-    for (int j = 0; j < nsel; ++j) {
-      int l = sel[j], h = sel[j];
-      if (dtol > 0 && theta[(size_t)k * s + sel[j]] > 0) {
-        while (l > 0 && om(k, l) - om(k, l - 1) < dtol * om(k, l)) --l;
-        while (h + 1 < s && om(k, h + 1) - om(k, h) < dtol * om(k, h + 1)) ++h;
-      }
-      lo[(size_t)k * nsel + j] = l;
-      hi[(size_t)k * nsel + j] = h;
-      if (h > l) {
-        ++ndeg;
-        for (int i = l; i <= h; ++i) use[i] = 1;
-      }
-    }
-  if (ndeg == 0) {
+  const phx_host::ClusterPlan pl = phx_host::cluster_plan(theta.data(), nk, s, sel.data(), nsel, ctx->opt.degen_tol);
+  if (pl.ndeg == 0) {
     adjoint_chunk(sv, sel, out);
     return 0;
   }
-  std::vector<int> ext;
-  for (int i = 0; i < s; ++i)
-    if (use[i]) ext.push_back(i);
-  const int next = (int)ext.size();
+  const int next = (int)pl.ext.size();
   const long nvox = sv.d->nvox;
   double* tmp = dbuf<double>(ctx, "sens_ext", (long)nk * next * nvox);
-  adjoint_chunk(sv, ext, tmp);
-  std::vector<double> coef((size_t)nk * nsel * next, 0.0);
-  for (int k = 0; k < nk; ++k)
-    for (int j = 0; j < nsel; ++j) {
-      const int l = lo[(size_t)k * nsel + j], h = hi[(size_t)k * nsel + j];
-      for (int t = 0; t < next; ++t)
-        if (ext[t] >= l && ext[t] <= h) coef[((size_t)k * nsel + j) * next + t] = 1.0 / (h - l + 1);
-    }
+  adjoint_chunk(sv, pl.ext, tmp);
+  const std::vector<double>& coef = pl.coef;
   double* cd = dbuf<double>(ctx, "sens_coef", (long)coef.size());
   HIPCHK(hipMemcpyAsync(cd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   launch_combine_cols(tmp, next, cd, nsel, nk, nvox, out, ctx->stream);
   KCHK(hipGetLastError());
   // the host coefficients must outlive the copy
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  return ndeg;
+  return pl.ndeg;
 }
 
 // Runs the eigensolver over k-chunks; fills omega (+ err bounds) and, when sel is
@@ -1258,7 +1164,7 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
                const std::vector<int>& sel, double* sens_dev, Design* dc = nullptr) {
   const int s = choose_block(ctx, nb, d.N);
   const long per = per_k_bytes(d, s, prec, ctx->opt.precond);
-  int kc = (int)std::max<long>(1, std::min<long>(nk, (long)(ctx->opt.mem_gb * 1073741824.0) / per));
+  int kc = phx_host::chunk_size(nk, ctx->opt.mem_gb, per);
   ctx->stats = Stats();
   ctx->stats.block = s;
   ctx->stats.kchunk = kc;
@@ -1365,14 +1271,7 @@ int guard(phx_ctx* ctx, const std::function<int()>& f) {
 }
 
 void check_bands(phx_ctx* ctx, const phx_cell* cell, int nb, int nsens, const int* band_no) {
-  const int L = 2 * cell->M + 1;
-  if (nb < 1 || nb > 16 || nb > 3 * L * L * L) fail(ctx, PHX_EINVAL, "nbands must be in [1, min(16, 3N)]");
-  if (ctx->opt.block > 0 && ctx->opt.block <= nb && ctx->opt.block < 3 * L * L * L)
-    fail(ctx, PHX_EINVAL, "option block must exceed nbands (the search block holds the wanted bands and guards)");
-  if (nsens < 0) fail(ctx, PHX_EINVAL, "nsens must be non-negative");
-  if (nsens > 0 && !band_no) fail(ctx, PHX_EINVAL, "band_no is NULL");
-  for (int j = 0; j < nsens; ++j)
-    if (band_no[j] < 1 || band_no[j] > nb) fail(ctx, PHX_EINVAL, "band_no entries must be in [1, nbands]");
+  if (const char* e = phx_host::check_bands(cell, nb, nsens, band_no, ctx->opt.block)) fail(ctx, PHX_EINVAL, e);
 }
 
 }  // namespace
@@ -1494,99 +1393,6 @@ int phx_get_stat(const phx_ctx* ctx, const char* key, double* value) {
   }
   else return PHX_EINVAL;
   return PHX_OK;
-}
-
-int phx_validate(const phx_cell* cell, const double* rho, int nk, const double* q, int nbands, int nsens,
-                 const int* band_no, char* msg, int msglen) {
-  phx_ctx tmp;
-  phx_ctx* ctx = &tmp;
-  int rc = PHX_OK;
-  try {
-    check_cell(ctx, cell);
-    if (rho) check_rho(ctx, rho, (long)cell->nv * cell->nv * cell->nv);
-    if (q || nk) check_q(ctx, q, nk);
-    if (nbands || nsens) check_bands(ctx, cell, nbands, nsens, band_no);
-  } catch (const Fail& f) {
-    rc = f.code;
-  }
-  if (msg && msglen > 0) {
-    strncpy(msg, ctx->err.c_str(), (size_t)msglen - 1);
-    msg[msglen - 1] = 0;
-  }
-  return rc;
-}
-
-int phx_kpath(phx_lattice lattice, const char* path, int nk, double* q_out) {
-  if (!q_out || lattice < PHX_SC || lattice > PHX_FCC) return PHX_EINVAL;
-  struct Pt { char c; double x, y, z; };
-  static const Pt sc[] = {{'G', 0, 0, 0}, {'X', 0, 0.5, 0}, {'M', 0.5, 0.5, 0}, {'R', 0.5, 0.5, 0.5}};
-  static const Pt bcc[] = {{'G', 0, 0, 0}, {'H', 0, 0, 1}, {'N', 0.5, 0.5, 0}, {'P', 0.5, 0.5, 0.5}};
-  static const Pt fcc[] = {{'G', 0, 0, 0}, {'X', 0, 1, 0}, {'W', 0.5, 1, 0}, {'K', 0.75, 0.75, 0}, {'L', 0.5, 0.5, 0.5},
-                           {'U', 0.25, 1, 0.25}};
-  const Pt* tab = lattice == PHX_SC ? sc : (lattice == PHX_BCC ? bcc : fcc);
-  const int ntab = lattice == PHX_FCC ? 6 : 4;
-  const char* def = lattice == PHX_SC ? "GXMGRX|MR" : (lattice == PHX_BCC ? "GHNGPH|PN" : "GXWKGLUWLK|UX");
-  std::string p = path ? path : def;
-  // branches of vertices
-  std::vector<std::vector<const Pt*>> br(1);
-  for (char ch : p) {
-    if (ch == '|') { br.emplace_back(); continue; }
-    const Pt* f = nullptr;
-    for (int i = 0; i < ntab; ++i)
-      if (tab[i].c == ch) f = &tab[i];
-    if (!f) return PHX_EINVAL;
-    br.back().push_back(f);
-  }
-  br.erase(std::remove_if(br.begin(), br.end(), [](const std::vector<const Pt*>& b) { return b.empty(); }), br.end());
-  int nvert = 0;
-  for (auto& b : br) nvert += (int)b.size();
-  if (nvert == 0 || nk < nvert) return PHX_EINVAL;
-  std::vector<double> len;
-  for (auto& b : br)
-    for (size_t i = 0; i + 1 < b.size(); ++i) {
-      const double dx = b[i + 1]->x - b[i]->x, dy = b[i + 1]->y - b[i]->y, dz = b[i + 1]->z - b[i]->z;
-      len.push_back(sqrt(dx * dx + dy * dy + dz * dz));
-    }
-  const int extra = nk - nvert;
-  std::vector<int> cnt(len.size(), 0);
-  const double tot = std::accumulate(len.begin(), len.end(), 0.0);
-  if (!len.empty() && tot > 0) {
-    std::vector<double> share(len.size());
-    int used = 0;
-    for (size_t i = 0; i < len.size(); ++i) {
-      share[i] = extra * len[i] / tot;
-      cnt[i] = (int)floor(share[i]);
-      used += cnt[i];
-    }
-    std::vector<size_t> ord(len.size());
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](size_t a, size_t b) { return (share[a] - cnt[a]) > (share[b] - cnt[b]); });
-    for (int r = 0; r < extra - used; ++r) cnt[ord[r]]++;
-  } else if (extra > 0) {
-    return PHX_EINVAL;
-  }
-  double A[3][3];
-  prim_rows(lattice, A);
-  int o = 0;
-  size_t si = 0;
-  auto emit = [&](double x, double y, double z) {
-    for (int j = 0; j < 3; ++j) q_out[3 * o + j] = A[j][0] * x + A[j][1] * y + A[j][2] * z;
-    ++o;
-  };
-  for (auto& b : br) {
-    emit(b[0]->x, b[0]->y, b[0]->z);
-    for (size_t i = 0; i + 1 < b.size(); ++i, ++si) {
-      const Pt *u = b[i], *v = b[i + 1];
-      const int c = cnt[si];
-      for (int j = 1; j <= c; ++j) {
-        const double t = (double)j / (c + 1);
-        emit(u->x + (v->x - u->x) * t, u->y + (v->y - u->y) * t, u->z + (v->z - u->z) * t);
-      }
-      emit(v->x, v->y, v->z);
-    }
-  }
-  return o == nk ? PHX_OK : PHX_EINVAL;
 }
 
 int phx_fourier(phx_ctx* ctx, const phx_cell* cell, const double* rho, double* out) {
@@ -2127,26 +1933,9 @@ int phx_zposv(phx_ctx* ctx, phx_precision prec, int n, int nrhs, int batch, cons
 // ------------------------------------------------------------------ design projection
 
 static long check_projection(phx_ctx* ctx, const phx_projection* p) {
-  if (!p) fail(ctx, PHX_EINVAL, "projection is NULL");
-  if (p->nv < 2 || (p->spacing != 1 && p->spacing != 2) || p->nv % p->spacing)
-    fail(ctx, PHX_EINVAL, "nv must be a positive multiple of spacing (1 or 2)");
-  const int nn = p->nv / p->spacing;
-  if (p->octant && nn % 2) fail(ctx, PHX_EINVAL, "the octant needs an even number of design nodes per axis");
-  const double rmin = p->spacing == 2 ? 0.8660254037844387 : 0.0;  // farthest element centroid from a node
-  if (!(p->radius > rmin) || !(2.0 * p->radius + p->spacing < p->nv))
-    fail(ctx, PHX_EINVAL, "radius must reach the nearest design node and stay below half the cell");
-  if (!(p->beta >= 0) || !(p->beta <= 1e3)) fail(ctx, PHX_EINVAL, "beta must lie in [0, 1000]");
-  const long nd = p->octant ? nn / 2 : nn;
-  return nd * nd * nd;
-}
-
-int phx_projection_size(const phx_projection* p, long* ndesign) {
-  if (!p || !ndesign || p->nv < 2 || (p->spacing != 1 && p->spacing != 2) || p->nv % p->spacing) return PHX_EINVAL;
-  const long nn = p->nv / p->spacing;
-  if (p->octant && nn % 2) return PHX_EINVAL;
-  const long nd = p->octant ? nn / 2 : nn;
-  *ndesign = nd * nd * nd;
-  return PHX_OK;
+  long nd = 0;
+  if (const char* e = phx_host::check_projection(p, &nd)) fail(ctx, PHX_EINVAL, e);
+  return nd;
 }
 
 int phx_project_dev(phx_ctx* ctx, const phx_projection* p, const double* x_dev, double* rho_dev, void* stream) {
