@@ -68,10 +68,12 @@ void launch_project_adjoint(int nv, int sp, double r, double beta, int oct, cons
 // small.hip: per-k dense kernels on m x m (m <= 64) Gram matrices, FP64.
 void launch_chol_drop(const double2* G, int m, int nk, double drop, double2* C0, int* keep, hipStream_t st,
                       const int* kact = nullptr);
-// Cx, Cp: m x s per k at k-stride sCx (0: m s).
+// Cx, Cp: m x s per k at k-stride sCx (0: m s).  method 0: cyclic Jacobi on the projected
+// matrix (eigenvalues to high relative accuracy); 1: Householder tridiagonalisation,
+// multisection and inverse iteration (absolute accuracy eps ||A||; s <= 24, else Jacobi).
 void launch_rr_gen(const double2* G2, int m, int s, int nk, double drop, double2* C0, int* keep, double2* Cx,
                    double2* Cp, double* theta, int* sweeps, hipStream_t st, const int* kact = nullptr,
-                   long sCx = 0);
+                   long sCx = 0, int method = 0);
 void launch_rr_eig(const double2* G, const int* keep, int m, int s, int nk, double2* C, double* theta,
                    int* sweeps, hipStream_t st, const int* kact = nullptr);
 

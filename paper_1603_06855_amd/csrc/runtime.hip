@@ -57,6 +57,7 @@ struct Opts {
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
   int streams = 4;           // designs solved concurrently by the batched call
   int rr_fused = 2;          // 1: second orthonormalisation folded into Rayleigh-Ritz; 2: both
+  int small_eig = 1;         // eigensolver of the folded Rayleigh-Ritz problem: 0 Jacobi, 1 tridiagonal
   int sbinv = 1;             // 1: preconditioner solves through explicit super-block inverses
   int kskip = 1;             // 1: k-points whose wanted bands have converged skip later iterations
   int kshare = 2;            // at most this many consecutive k-points share one preconditioner factor
@@ -697,7 +698,7 @@ void rayleigh_ritz_fused(Solver& sv, Sel k) {
   // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
   // the basis produces both: columns 0..s-1 -> X, s..2s-1 -> P (basis columns 2s..3s-1)
   launch_rr_gen(sv.G2, m, s, sv.nk, ctx->opt.drop, sv.C0, sv.keep, sv.Cp, sv.Cp + m * s, sv.theta, sv.sweeps,
-                ctx->stream, k.d, 2 * m * s);
+                ctx->stream, k.d, 2 * m * s, ctx->opt.small_eig);
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
@@ -1340,6 +1341,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
   else if (k == "streams") { if (!(v >= 1 && v <= 16)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "rr_fused") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.rr_fused = (int)v; }
+  else if (k == "small_eig") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.small_eig = (int)v; }
   else if (k == "sbinv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.sbinv = (int)v; }
   else if (k == "kskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.kskip = (int)v; }
   else if (k == "kshare") { if (!(v >= 1 && v <= 8 && v == (int)v)) return bad(); ctx->opt.kshare = (int)v; }
@@ -1875,7 +1877,7 @@ int phx_small_rr(phx_ctx* ctx, int m, int s, int batch, const double* G2, double
     int* dk = dbuf<int>(ctx, "tK", (long)m * batch);
     double* dt = dbuf<double>(ctx, "tT", (long)s * batch);
     HIPCHK(hipMemcpyAsync(dg, G2, n2 * sizeof(double2), hipMemcpyHostToDevice, st));
-    launch_rr_gen(dg, m, s, batch, drop, dc0, dk, dx, dp, dt, nullptr, st);
+    launch_rr_gen(dg, m, s, batch, drop, dc0, dk, dx, dp, dt, nullptr, st, nullptr, 0, ctx->opt.small_eig);
     KCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(Cx, dx, ns * sizeof(double2), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(Cp, dp, ns * sizeof(double2), hipMemcpyDeviceToHost, st));

@@ -492,11 +492,14 @@ def test_sens_batch_uneven_m_matches_single_design_calls(ctx):
     ctx.set_option("streams", 4)
 
 
-@pytest.mark.parametrize("m,s,ndep", [(63, 21, 0), (48, 16, 3), (54, 18, 0), (9, 4, 1)])
-def test_small_rr_generalised(ctx, m, s, ndep):
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("m,s,ndep", [(63, 21, 0), (48, 16, 3), (54, 18, 0), (9, 4, 1), (40, 24, 0), (40, 30, 2)])
+def test_small_rr_generalised(ctx, m, s, ndep, method):
     """Rayleigh-Ritz from the two Gram matrices of a non-orthonormal basis (with dependent
     and zero columns): Omega-orthonormal Ritz vectors, the pencil's lowest eigenvalues on
-    the kept subspace, and the previous-direction coefficients."""
+    the kept subspace, and the previous-direction coefficients; both small eigensolvers
+    (0: Jacobi, 1: tridiagonal; above 24 pairs method 1 falls back to Jacobi)."""
+    ctx.set_option("small_eig", method)
     rng = np.random.default_rng(m + s + ndep)
     n = 200
     S = _rand(rng, 2, n, m)
@@ -527,6 +530,74 @@ def test_small_rr_generalised(ctx, m, s, ndep):
         D = S[b] @ (Cx[b] - Cp[b])
         coef, *_ = np.linalg.lstsq(S[b][:, :s], D, rcond=None)
         assert np.abs(S[b][:, :s] @ coef - D).max() < 1e-9 * max(np.abs(D).max(), 1.0)
+    ctx.set_option("small_eig", 1)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_small_rr_degenerate_spectrum(ctx, method):
+    """A basis that spans an invariant subspace whose eigenvalues come in exact pairs and
+    triples (as at the symmetric k-points), mixed by a random unitary: the Ritz values are
+    those eigenvalues, and the Ritz vectors of each repeated eigenvalue are an Omega-
+    orthonormal basis of its eigenspace."""
+    ctx.set_option("small_eig", method)
+    rng = np.random.default_rng(99)
+    n, m, s = 120, 63, 21
+    vals = np.repeat(np.linspace(0.5, 9.0, 25), [2, 3, 1] * 8 + [1])[:n]
+    vals = np.concatenate([vals, np.linspace(20.0, 40.0, n - len(vals))])
+    W = np.diag(1.0 + rng.random(n))
+    Wh = np.sqrt(W)
+    Qn, _ = np.linalg.qr(_rand(rng, n, n))
+    Z = np.linalg.solve(Wh, Qn)                    # W-orthonormal eigenvectors of K Z = W Z vals
+    K = W @ Z @ np.diag(vals) @ np.conj(Z.T) @ W
+    U, _ = np.linalg.qr(_rand(rng, m, m))
+    S = np.stack([Z[:, :m] @ U, Z[:, :m] @ U])
+    SH = np.conj(np.transpose(S, (0, 2, 1)))
+    G2 = np.concatenate([SH @ K @ S, SH @ W @ S], axis=2)
+    Cx, Cp, th, keep = ctx.small_rr(G2, s)
+    ref = np.sort(vals[:m])[:s]
+    for b in range(2):
+        assert np.abs(th[b] - ref).max() < 1e-12 * vals[:m].max()
+        X = S[b] @ Cx[b]
+        assert np.abs(np.conj(X.T) @ W @ X - np.eye(s)).max() < 1e-11
+        R = K @ X - W @ X * th[b][None, :]
+        assert np.abs(R).max() < 1e-10 * vals.max()
+    ctx.set_option("small_eig", 1)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_small_rr_null_space(ctx, method):
+    """A stiffness with a three-dimensional null space (the rigid translations at Gamma)
+    whose null vectors lie in the basis, next to dependent and zero columns: three exact
+    zero Ritz values; the Ritz vectors stay finite, Omega-orthonormal and Galerkin.  (Their
+    near-zero shifts are equal to rounding, so unguarded inverse iteration would give three
+    copies of one vector.)"""
+    ctx.set_option("small_eig", method)
+    rng = np.random.default_rng(5)
+    n, m, s = 150, 60, 20
+    W = np.diag(1.0 + rng.random(n))
+    Wh = np.sqrt(W)
+    Qn, _ = np.linalg.qr(_rand(rng, n, n))
+    Z = np.linalg.solve(Wh, Qn)
+    vals = np.concatenate([[0.0, 0.0, 0.0], np.sort(rng.uniform(5.0, 40.0, n - 3))])
+    K = W @ Z @ np.diag(vals) @ np.conj(Z.T) @ W
+    S = np.stack([np.concatenate([Z[:, :3], _rand(rng, n, m - 3)], axis=1) for _ in range(2)])
+    S[1, :, 10] = S[1, :, 4] * 2.0   # a dependent column
+    S[1, :, m - 1] = 0               # a zero column
+    SH = np.conj(np.transpose(S, (0, 2, 1)))
+    G2 = np.concatenate([SH @ K @ S, SH @ W @ S], axis=2)
+    Cx, Cp, th, keep = ctx.small_rr(G2, s)
+    import scipy.linalg as sla
+    for b in range(2):
+        assert np.all(np.isfinite(Cx[b])) and np.all(np.isfinite(Cp[b]))
+        assert np.all(np.abs(th[b][:3]) <= 1e-12 * vals.max())
+        X = S[b] @ Cx[b]
+        assert np.abs(np.conj(X.T) @ W @ X - np.eye(s)).max() < 1e-10
+        R = np.conj(S[b].T) @ (K @ X - W @ X * th[b][None, :])
+        assert np.abs(R).max() < 1e-9 * np.abs(K).max() * np.abs(S[b]).max() * n
+        Q, _ = np.linalg.qr(S[b][:, keep[b].astype(bool)])
+        ref = sla.eigh(np.conj(Q.T) @ K @ Q, np.conj(Q.T) @ W @ Q, eigvals_only=True)[:s]
+        assert np.abs(th[b] - ref).max() < 1e-11 * np.abs(ref).max()
+    ctx.set_option("small_eig", 1)
 
 
 def test_kernel_class_timing(ctx):
