@@ -39,10 +39,31 @@ struct JacobiLDS {
   int rot[2];  // per sweep parity: some pair rotated
 };
 
-// Wave-level sum and max (64 lanes).
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// v from lane (lane ^ 1), (lane ^ 2) or the mirrored lane of its 8- or 16-lane row (DPP
+// quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror): register moves, no LDS.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each 16-lane row of the wavefront, in every lane of the row.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // pairs
+  v += dpp_d<0x4E>(v);   // quads
+  v += dpp_d<0x141>(v);  // 8 lanes
+  v += dpp_d<0x140>(v);  // 16 lanes
   return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane);
+
+// Wave-level sum (64 lanes), the same value in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (readlane_d(v, 15) + readlane_d(v, 31)) + (readlane_d(v, 47) + readlane_d(v, 63));
 }
 __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -81,8 +102,9 @@ __device__ __forceinline__ double rcp_nr(double q) {
 
 // Sum over the 32 lanes of each half of the wavefront.
 __device__ __forceinline__ double half_sum(double v) {
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v = row16_sum(v);
+  const double s0 = readlane_d(v, 15) + readlane_d(v, 31), s1 = readlane_d(v, 47) + readlane_d(v, 63);
+  return (threadIdx.x & 32) ? s1 : s0;
 }
 
 __device__ __forceinline__ double wave_min(double v) {
