@@ -117,6 +117,13 @@ const char* phx_last_error(const phx_ctx* ctx);
  * the second folded; with 1 and 2 a k-point whose residual is below 1e-13/tolerance (the
  * last iterations of an FP64 solve) has its basis orthonormalised twice explicitly; 0:
  * always two explicit orthonormalisations of the basis before Rayleigh-Ritz),
+ * "small_eig" (1, default: the eigenproblem of the folded Rayleigh-Ritz step, order
+ * m = 3s, by Householder reduction to real tridiagonal form, multisection on Sturm
+ * counts and inverse iteration, with exactly zero rows of the projected matrix (null
+ * vectors of K in the basis) deflated as eigenvalue 0; eigenvalues accurate to a small
+ * multiple of eps times the projected matrix's norm; 0: cyclic Jacobi, accurate relative
+ * to each eigenvalue and several times slower; more than 24 wanted pairs always take
+ * Jacobi; also selects the solver of phx_small_rr),
  * "mem_gb" (device memory budget that sets the k-chunk size, default 64; per worker
  * context of phx_sens_batch_dev), "mem_limit_gb" (hard cap on the device workspace one
  * context, or each worker context of a batched call, may hold; 0, default: none; a
@@ -318,7 +325,8 @@ int phx_small_eig(phx_ctx* ctx, int m, int s, int batch, const double* G, const 
 /* phx_small_rr: Rayleigh-Ritz on a basis S that is only approximately
  * Omega-orthonormal, from G2 = S^H [K S | Omega S] (m x 2m per batch item):
  * Omega-Cholesky with scaling and dropping as phx_small_orth, then the s lowest
- * eigenpairs of the projected K.  Cx (m x s): Ritz-vector coefficients in S
+ * eigenpairs of the projected K (by the solver the option "small_eig" selects).
+ * Cx (m x s): Ritz-vector coefficients in S
  * ((S Cx)^H Omega (S Cx) = I, G_K Cx = G_Omega Cx diag(theta)); Cp (m x s): the
  * same with only the contributions of columns s.. of the orthonormalised basis
  * (the previous-direction update); keep (m): columns kept by the Cholesky. */

@@ -193,6 +193,24 @@ def test_bands_config1_rayleigh_ritz_forms(ctx, config1_ref, fused, prec, bar):
     assert _om_err(om, ref).max() <= bar
 
 
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_bands_config1_small_eigensolvers(ctx, config1_ref, method, prec, bar):
+    """The folded Rayleigh-Ritz step with either small eigensolver (0: Jacobi, 1:
+    tridiagonal with multisection and inverse iteration) meets the bar at every k-point,
+    Gamma's three zero modes included."""
+    cell, rho, Q, ref = config1_ref
+    ctx.set_option("small_eig", method)
+    ctx.set_option("tol_fp64", 1e-10)
+    try:
+        om = ctx.bands(cell, rho, Q, ref.shape[1], prec)
+        log("small_eig", method, prec, "iters", ctx.stat("iters"), "max rel err", _om_err(om, ref).max())
+    finally:
+        ctx.set_option("small_eig", 1)
+        ctx.set_option("tol_fp64", 1e-8)
+    assert _om_err(om, ref).max() <= bar
+
+
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
 def test_bands_config1_converged_k_points_frozen_or_not(ctx, config1_ref, prec, bar):
     """Freezing each k-point once its wanted bands meet the tolerance (option kskip)
@@ -639,6 +657,7 @@ def test_kernel_class_timing(ctx):
     ("profile", (3, -1), (0, 1, 2)),
     ("spin_wait", (2,), (0, 1)),
     ("rr_fused", (3, -1), (0, 1, 2)),
+    ("small_eig", (-1, 2, 0.5), (0, 1)),
     ("stall_its", (1, 31, 2.5), (2, 8, 30)),
     ("gram_split", (-1, 17, 2.5), (0, 1, 16)),
     ("precond", (-1, 3, 0.5), (0, 1, 2)),
