@@ -133,7 +133,8 @@ const char* phx_last_error(const phx_ctx* ctx);
  * for M >= 4 every k-chunk is first solved at order M-2 to the residual
  * "coarse_tol", default 1e-3, and its Ritz vectors, embedded in the order-M
  * plane-wave set, start the order-M solve; 0: start from plane-wave unit
- * vectors; default 1),
+ * vectors; default 1), "coarse_drop" (1..3, default 2: the coarse start's order is
+ * M - coarse_drop, at least 1),
  * "profile" (0, default: off; 1: every kernel class is timed with HIP events,
  * stage intervals on the library stream and, for the classes herk, op_gemm,
  * solve_upd and solve_diag, events that each launch records at its kernel's start

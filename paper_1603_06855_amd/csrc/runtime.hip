@@ -55,6 +55,7 @@ struct Opts {
   double mem_gb = 64.0;
   int coarse = 1;            // start orders M >= 4 from the order M-2 Ritz vectors
   double coarse_tol = 1e-3;  // residual tolerance of that coarse solve
+  int coarse_drop = 2;       // the coarse start's order: M - coarse_drop (at least 1)
   int streams = 4;           // designs solved concurrently by the batched call
   int rr_fused = 2;          // 1: second orthonormalisation folded into Rayleigh-Ritz; 2: both
   int small_eig = 1;         // eigensolver of the folded Rayleigh-Ritz problem: 0 Jacobi, 1 tridiagonal
@@ -1241,7 +1242,7 @@ int run_design(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, int pre
 Design* coarse_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, const double* rho_dev, Design& dc) {
   if (!ctx->opt.coarse || cell.M < 4) return nullptr;
   phx_cell cc = cell;
-  cc.M = cell.M - 2;
+  cc.M = std::max(1, cell.M - ctx->opt.coarse_drop);
   setup_design(ctx, cc, rho_host, rho_dev, dc, "c0:");
   return &dc;
 }
@@ -1339,6 +1340,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "mem_gb") { if (!(v > 0)) return bad(); ctx->opt.mem_gb = v; }
   else if (k == "coarse") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.coarse = (int)v; }
   else if (k == "coarse_tol") { if (!(v > 0 && v < 1)) return bad(); ctx->opt.coarse_tol = v; }
+  else if (k == "coarse_drop") { if (!(v >= 1 && v <= 3 && v == (int)v)) return bad(); ctx->opt.coarse_drop = (int)v; }
   else if (k == "streams") { if (!(v >= 1 && v <= 16)) return bad(); ctx->opt.streams = (int)v; }
   else if (k == "rr_fused") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.rr_fused = (int)v; }
   else if (k == "small_eig") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.small_eig = (int)v; }

@@ -658,6 +658,7 @@ def test_kernel_class_timing(ctx):
     ("spin_wait", (2,), (0, 1)),
     ("rr_fused", (3, -1), (0, 1, 2)),
     ("small_eig", (-1, 2, 0.5), (0, 1)),
+    ("coarse_drop", (0, 4, 1.5), (1, 2, 3)),
     ("stall_its", (1, 31, 2.5), (2, 8, 30)),
     ("gram_split", (-1, 17, 2.5), (0, 1, 16)),
     ("precond", (-1, 3, 0.5), (0, 1, 2)),
