@@ -26,7 +26,8 @@ namespace phx {
 // right-hand-side blocks of the triangular solves and subspace updates.
 // MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update), 2 k-shared
 // operator times a block (same code as 0; a separate instantiation so that profilers
-// report the matrix-free operator products on their own).
+// report the matrix-free operator products on their own), 3 a real k-shared operator
+// (g.Ar) times a complex block: two real products per complex one instead of three.
 template <typename R, int OPA, int OPB, int BM, int BN, int MODE>
 __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
@@ -108,7 +109,11 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPA == 0) { i = row0 + (gi % (BM / VA)) * VA + q; k = k0 + gi / (BM / VA); }
         else { k = k0 + (gi % (KS / VA)) * VA + q; i = row0 + gi / (KS / VA); }
         C v = mk<R>(0, 0);
-        if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+        if constexpr (MODE == 3) {
+          if (i < g.M && k < kend) v = mk<R>(g.Ar[i + (long)k * g.lda], 0);
+        } else {
+          if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+        }
         ra[r * VA + q] = v;
       }
     }
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPA == 0) { ii = (gi % (BM / VA)) * VA + q; kk = gi / (BM / VA); }
         else { kk = (gi % (KS / VA)) * VA + q; ii = gi / (KS / VA); }
         Asr[kk][ii] = ra[r * VA + q].x;
-        Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
+        if constexpr (MODE != 3) Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
       }
     }
 #pragma unroll
@@ -157,24 +162,41 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
     for (int kk = 0; kk < KS / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      R ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+      if constexpr (MODE == 3) {  // real A: t1 = A Re B, t2 = A Im B
+        R ar[2], br[2], bi[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
-        ai[x] = Asi[kr][wr * 32 + x * 16 + (lane & 15)];
-        br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
-        bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
-        as[x] = ar[x] + ai[x];
-        bs[x] = br[x] + bi[x];
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
-          t2[x][y] = mfma16(bi[y], ai[x], t2[x][y]);
-          t3[x][y] = mfma16(bs[y], as[x], t3[x][y]);
+        for (int x = 0; x < 2; ++x) {
+          ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
+          br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
+          bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
         }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+            t2[x][y] = mfma16(bi[y], ar[x], t2[x][y]);
+          }
+      } else {
+        R ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
+          ai[x] = Asi[kr][wr * 32 + x * 16 + (lane & 15)];
+          br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
+          bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
+          as[x] = ar[x] + ai[x];
+          bs[x] = br[x] + bi[x];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+            t2[x][y] = mfma16(bi[y], ai[x], t2[x][y]);
+            t3[x][y] = mfma16(bs[y], as[x], t3[x][y]);
+          }
+      }
     }
   };
 
@@ -216,7 +238,8 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         // row l/16 + 4r of the 16x16 block, column l%16 in both (here rows are C columns).
         const int col = col0 + wc * 32 + y * 16 + (sizeof(R) == 8 ? ((lane >> 4) + 4 * r) : (((lane >> 4) << 2) + r));
         if (row < g.M && col < g.N) {
-          const C acc = mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
+          const C acc = MODE == 3 ? mk<R>(t1[x][y][r], t2[x][y][r])
+                                  : mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
           C v = cmul(g.alpha, acc);
           if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * ldc]));
           Cb[row + (long)col * ldc] = v;
@@ -509,6 +532,9 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.tri) {
     if (opa == 0 && opb == 1) PHX_LAUNCH((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid);
     else return (int)hipErrorInvalidValue;
+  } else if (g.op == 2) {
+    if (opa != 0 || opb != 0 || !g.Ar) return (int)hipErrorInvalidValue;
+    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 3>), grid);
   } else if (g.op) {
     if (opa != 0 || opb != 0) return (int)hipErrorInvalidValue;
     PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 2>), grid);

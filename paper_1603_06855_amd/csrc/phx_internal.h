@@ -20,7 +20,7 @@ struct GemmArgs {
   C_t<R>* Cm; long ldc, sC; int dC;
   C_t<R> alpha, beta;
   int tri;
-  int op;  // 1: A is a k-shared operator (stride 0); selects a separately named kernel
+  int op;  // 1: A is a k-shared operator (stride 0); selects a separately named kernel; 2: a real one (Ar)
   const int* kact;  // optional device mask: batch item b is skipped when kact[b / kdiv] == 0
   int kdiv;
   int ksplit;
@@ -29,6 +29,7 @@ struct GemmArgs {
   const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
   hipEvent_t ev0, ev1;  // optional: recorded at the start and the end of the (single) kernel's execution
   int tiled;            // 1: always the LDS-tiled kernel, never the streaming few-RHS one
+  const R* Ar;          // op == 2: the operator is real (Ar, ld lda) and A is unused
 };
 
 template <typename R>

@@ -28,10 +28,15 @@ template <typename R>
 void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                      int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st);
 // kact (optional, device): per-k mask; k-points with kact[k] == 0 are skipped.
+// pairN = N > 0: strain channels written in the real basis of launch_realify (pairs of
+// waves n_p, -n_p combined), and the force kernel's inputs read in that basis.
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st, const int* kact = nullptr);
+                   double2* tr, hipStream_t st, const int* kact = nullptr, int pairN = 0);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr);
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr, int pairN = 0);
+// Mr = Re(U^H Mc U), U the unitary pairing each wave n_p with -n_p (see realify_kernel):
+// real symmetric for the Fourier matrix of a real field and for its inverse.
+void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st);
 void launch_zero(double2* X, long n, hipStream_t st);
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
 void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,

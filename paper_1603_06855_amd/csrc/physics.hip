@@ -210,44 +210,139 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double2* Dm, const 
 // Y = B(K_p) X_p (6 per wave) and the trace t = K_p . X_p.
 // X: 3Np x ncol per k (ld ldx, k-stride sX).  Y: Np x 6 ncol per k, t: Np x ncol.
 // ---------------------------------------------------------------------------
+// Strain channels of one wave: Y = (K1 x1, K2 x2, K3 x3, (K3 x2 + K2 x3)/sqrt2,
+// (K3 x1 + K1 x3)/sqrt2, (K2 x1 + K1 x2)/sqrt2) (Mandel) and the trace K . x.
+__device__ __forceinline__ void wave_strain(const double* K, double2 x1, double2 x2, double2 x3, double2 (&y)[6],
+                                            double2& t) {
+  const double r2 = 0.70710678118654752440;
+  y[0] = cscale(x1, K[0]);
+  y[1] = cscale(x2, K[1]);
+  y[2] = cscale(x3, K[2]);
+  y[3] = cscale(cadd(cscale(x2, K[2]), cscale(x3, K[1])), r2);
+  y[4] = cscale(cadd(cscale(x1, K[2]), cscale(x3, K[0])), r2);
+  y[5] = cscale(cadd(cscale(x1, K[1]), cscale(x2, K[0])), r2);
+  t = cadd(cadd(cscale(x1, K[0]), cscale(x2, K[1])), cscale(x3, K[2]));
+}
+
+// Force of one wave from its Mandel stress S = z + (t / 3)[1,1,1,0,0,0]: c2 B(K)^T S.
+__device__ __forceinline__ void wave_force(const double* K, const double2 (&z)[6], double2 t, double c2,
+                                           double2 (&o)[3]) {
+  const double2 t3 = cscale(t, 1.0 / 3.0);
+  const double2 s0 = cadd(z[0], t3), s1 = cadd(z[1], t3), s2 = cadd(z[2], t3);
+  const double r2 = 0.70710678118654752440;
+  o[0] = cscale(cadd(cscale(s0, K[0]), cscale(cadd(cscale(z[4], K[2]), cscale(z[5], K[1])), r2)), c2);
+  o[1] = cscale(cadd(cscale(s1, K[1]), cscale(cadd(cscale(z[3], K[2]), cscale(z[5], K[0])), r2)), c2);
+  o[2] = cscale(cadd(cscale(s2, K[2]), cscale(cadd(cscale(z[3], K[1]), cscale(z[4], K[0])), r2)), c2);
+}
+
+// Mandel strain (6 channels, Np x 6 ncol per k) and trace (Np x ncol per k) of ncol
+// displacement columns.  pairN = N > 0: the channels are written in the basis of
+// realify_kernel, u_p = (e_p + e_pb)/sqrt2, u_pb = i (e_p - e_pb)/sqrt2 (p < c = (N-1)/2,
+// pb = N-1-p), u_c = e_c: row p gets (y_p + y_pb)/sqrt2 and row pb gets -i (y_p - y_pb)/sqrt2;
+// one thread takes both waves of a pair (padding rows from N on are copied).
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
-                              double2* Y, double2* tr, const int* kact) {
+                              double2* Y, double2* tr, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
   if (p >= Np || (kact && !kact[k])) return;
-  const double* K = Kv + ((long)k * Np + p) * 3;
-  const double2* x = X + (long)k * sX + (long)j * ldx + p;
-  const double2 x1 = x[0], x2 = x[Np], x3 = x[2 * Np];
+  const int c = (pairN - 1) / 2;
+  if (pairN > 0 && p > c && p < pairN) return;  // the partner thread writes this row
+  const double2* x = X + (long)k * sX + (long)j * ldx;
+  double2* y = Y + (long)k * Np * 6 * ncol + (long)(6 * j) * Np;
+  double2* tp = tr + (long)k * Np * ncol + (long)j * Np;
+  double2 ya[6], ta;
+  wave_strain(Kv + ((long)k * Np + p) * 3, x[p], x[Np + p], x[2 * Np + p], ya, ta);
+  if (pairN == 0 || p >= pairN || p == c) {
+    for (int ch = 0; ch < 6; ++ch) y[ch * Np + p] = ya[ch];
+    tp[p] = ta;
+    return;
+  }
+  const int pb = pairN - 1 - p;
+  double2 yb[6], tb;
+  wave_strain(Kv + ((long)k * Np + pb) * 3, x[pb], x[Np + pb], x[2 * Np + pb], yb, tb);
   const double r2 = 0.70710678118654752440;
-  double2* y = Y + (long)k * Np * 6 * ncol + (long)(6 * j) * Np + p;
-  y[0] = cscale(x1, K[0]);
-  y[Np] = cscale(x2, K[1]);
-  y[2 * Np] = cscale(x3, K[2]);
-  y[3 * Np] = cscale(cadd(cscale(x2, K[2]), cscale(x3, K[1])), r2);
-  y[4 * Np] = cscale(cadd(cscale(x1, K[2]), cscale(x3, K[0])), r2);
-  y[5 * Np] = cscale(cadd(cscale(x1, K[1]), cscale(x2, K[0])), r2);
-  tr[(long)k * Np * ncol + (long)j * Np + p] = cadd(cadd(cscale(x1, K[0]), cscale(x2, K[1])), cscale(x3, K[2]));
+  for (int ch = 0; ch < 6; ++ch) {
+    const double2 sm = cadd(ya[ch], yb[ch]), df = csub(ya[ch], yb[ch]);
+    y[ch * Np + p] = cscale(sm, r2);
+    y[ch * Np + pb] = make_double2(df.y * r2, -df.x * r2);  // -i df / sqrt2
+  }
+  const double2 sm = cadd(ta, tb), df = csub(ta, tb);
+  tp[p] = cscale(sm, r2);
+  tp[pb] = make_double2(df.y * r2, -df.x * r2);
 }
 
 // Mandel stress coefficients S = Zy + (Zt / 3) [1,1,1,0,0,0] and the force
-// (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).
+// (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).  pairN = N > 0:
+// Zy and Zt are in the basis of realify_kernel and go back first (row p of the result is
+// (z_p + i z_pb)/sqrt2, row pb is (z_p - i z_pb)/sqrt2).
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
-                             double2* KX, long ldk, long sK, const int* kact) {
+                             double2* KX, long ldk, long sK, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
   if (p >= Np || (kact && !kact[k])) return;
-  const double* K = Kv + ((long)k * Np + p) * 3;
-  const double2* z = Zy + (long)k * Np * 6 * ncol + (long)(6 * j) * Np + p;
-  const double2 t3 = cscale(Zt[(long)k * Np * ncol + (long)j * Np + p], 1.0 / 3.0);
-  const double2 s0 = cadd(z[0], t3), s1 = cadd(z[Np], t3), s2 = cadd(z[2 * Np], t3);
-  const double2 s3 = z[3 * Np], s4 = z[4 * Np], s5 = z[5 * Np];
+  const int c = (pairN - 1) / 2;
+  if (pairN > 0 && p > c && p < pairN) return;
+  const double2* z = Zy + (long)k * Np * 6 * ncol + (long)(6 * j) * Np;
+  const double2* zt = Zt + (long)k * Np * ncol + (long)j * Np;
+  double2* o = KX + (long)k * sK + (long)j * ldk;
+  double2 za[6], fa[3];
+  for (int ch = 0; ch < 6; ++ch) za[ch] = z[ch * Np + p];
+  if (pairN == 0 || p >= pairN || p == c) {
+    wave_force(Kv + ((long)k * Np + p) * 3, za, zt[p], c2, fa);
+    for (int d = 0; d < 3; ++d) o[d * Np + p] = fa[d];
+    return;
+  }
+  const int pb = pairN - 1 - p;
   const double r2 = 0.70710678118654752440;
-  double2* o = KX + (long)k * sK + (long)j * ldk + p;
-  o[0] = cscale(cadd(cscale(s0, K[0]), cscale(cadd(cscale(s4, K[2]), cscale(s5, K[1])), r2)), c2);
-  o[Np] = cscale(cadd(cscale(s1, K[1]), cscale(cadd(cscale(s3, K[2]), cscale(s5, K[0])), r2)), c2);
-  o[2 * Np] = cscale(cadd(cscale(s2, K[2]), cscale(cadd(cscale(s3, K[1]), cscale(s4, K[0])), r2)), c2);
+  double2 zp[6], zq[6], fb[3];
+  for (int ch = 0; ch < 6; ++ch) {
+    const double2 u = za[ch], w = z[ch * Np + pb];
+    const double2 iw = make_double2(-w.y, w.x);
+    zp[ch] = cscale(cadd(u, iw), r2);
+    zq[ch] = cscale(csub(u, iw), r2);
+  }
+  const double2 tu = zt[p], tw = zt[pb], itw = make_double2(-tw.y, tw.x);
+  wave_force(Kv + ((long)k * Np + p) * 3, zp, cscale(cadd(tu, itw), r2), c2, fa);
+  wave_force(Kv + ((long)k * Np + pb) * 3, zq, cscale(csub(tu, itw), r2), c2, fb);
+  for (int d = 0; d < 3; ++d) {
+    o[d * Np + p] = fa[d];
+    o[d * Np + pb] = fb[d];
+  }
+}
+
+// The Hermitian Np x Np operator Mc with Mc[N-1-p][N-1-q] = conj(Mc[p][q]) (the Fourier
+// matrix of a real field on the waves n_p, n_{N-1-p} = -n_p, or its inverse) in the basis
+// u_p = (e_p + e_pb)/sqrt2, u_pb = i (e_p - e_pb)/sqrt2 (p < c = (N-1)/2, pb = N-1-p),
+// u_c = e_c, where it is real symmetric: Mr[a][b] = Re(u_a^H Mc u_b) (the imaginary part is
+// rounding).  Rows and columns from N on (the padding) are copied.  Column-major.
+__global__ void realify_kernel(const double2* Mc, int N, int Np, double* Mr) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)Np * Np) return;
+  const int a = (int)(e % Np), b = (int)(e / Np);
+  if (a >= N || b >= N) {
+    Mr[e] = Mc[e].x;
+    return;
+  }
+  const int c = (N - 1) / 2;
+  const double r2 = 0.70710678118654752440;
+  // u_x = al e_px + be e_qx
+  auto basis = [&](int x, int& px, int& qx, double2& al, double2& be) {
+    if (x == c) { px = qx = c; al = make_double2(1, 0); be = make_double2(0, 0); }
+    else if (x < c) { px = x; qx = N - 1 - x; al = make_double2(r2, 0); be = make_double2(r2, 0); }
+    else { px = N - 1 - x; qx = x; al = make_double2(0, r2); be = make_double2(0, -r2); }
+  };
+  int pa, qa, pb, qb;
+  double2 aa, ba, ab, bb;
+  basis(a, pa, qa, aa, ba);
+  basis(b, pb, qb, ab, bb);
+  auto m = [&](int r, int col) { return Mc[r + (long)col * Np]; };
+  double2 v = cmul(cmulc(ab, aa), m(pa, pb));  // conj(al_a) al_b M[pa][pb]
+  if (qb != pb) v = cadd(v, cmul(cmulc(bb, aa), m(pa, qb)));
+  if (qa != pa) v = cadd(v, cmul(cmulc(ab, ba), m(qa, pb)));
+  if (qa != pa && qb != pb) v = cadd(v, cmul(cmulc(bb, ba), m(qa, qb)));
+  Mr[e] = v.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -552,15 +647,20 @@ template void launch_assemble<float>(const double2*, const double2*, const doubl
                                      double, const double*, float2*, long, int, hipStream_t);
 
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st, const int* kact) {
+                   double2* tr, hipStream_t st, const int* kact, int pairN) {
   hipLaunchKernelGGL(strain_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
-                     tr, kact);
+                     tr, kact, pairN);
 }
 
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact) {
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact, int pairN) {
   hipLaunchKernelGGL(force_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
-                     ldk, sK, kact);
+                     ldk, sK, kact, pairN);
+}
+
+void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st) {
+  const long n = (long)Np * Np;
+  hipLaunchKernelGGL(realify_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Mc, N, Np, Mr);
 }
 
 void launch_zero(double2* X, long n, hipStream_t st) {

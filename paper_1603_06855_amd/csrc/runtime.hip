@@ -89,18 +89,19 @@ struct Stats {
 enum RtClass {
   PROF_ASSEMBLE = phx::PROF_NCLASS_DENSE,
   PROF_APPLY,     // strain and force (pointwise parts of the matrix-free K X)
-  PROF_OP_GEMM,   // the k-shared operator products Bm Y, Dm t, Omega_s X
+  PROF_OP_GEMM,   // the k-shared complex operator product Omega_s X
   PROF_GRAM,
   PROF_SMALL,
   PROF_UPDATE,
   PROF_RESIDUAL,
   PROF_ADJOINT,
+  PROF_OP_REAL,   // the real compliance products Br Y, Dr t (K X in the real basis)
   PROF_NCLASS
 };
 const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",      "herk",  "trsm_diag", "trsm_update",
                                              "solve_upd",  "solve_diag", "sbinv", "assemble",  "apply",
                                              "op_gemm",    "gram",      "small", "update",    "residual",
-                                             "adjoint"};
+                                             "adjoint",    "op_real"};
 
 struct PendKernel {
   int cls;
@@ -399,6 +400,8 @@ struct Design {
   double2* Os = nullptr;   // Np x Np
   double2* Dm = nullptr;   // Pv^{-1} - Pd^{-1}
   double2* Bm = nullptr;   // Pd^{-1}
+  double* Dr = nullptr;    // Dm and Bm in the real basis pairing n_p with -n_p (launch_realify)
+  double* Br = nullptr;
 };
 
 MaterialND nondim(const phx_cell& c) {
@@ -501,6 +504,13 @@ void setup_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, co
   d.Os = ops;
   d.Dm = inv;
   d.Bm = inv + NN;
+  // the two compliance inverses in the basis where they are real: the operator products
+  // of K X take two real products per complex one instead of three
+  d.Dr = dbuf<double>(ctx, tag + "opr", 2 * NN);
+  d.Br = d.Dr + NN;
+  launch_realify(d.Dm, d.N, d.Np, d.Dr, st);
+  launch_realify(d.Bm, d.N, d.Np, d.Br, st);
+  KCHK(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
@@ -550,8 +560,9 @@ template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
           int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1,
-          int csplit = 0, int cgap = 0) {
+          int csplit = 0, int cgap = 0, const R* Ar = nullptr) {
   GemmArgs<R> g{};
+  g.Ar = Ar;
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &g.ev0, &g.ev1);
     ctx->pk.set = false;
@@ -589,25 +600,26 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   double2* X = Big + c0 * n3;
   const double Np = d.Np, nk = nm;  // algorithmic work counts the selected k-points only
   PROF_BEGIN(PROF_APPLY);
-  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk);
+  // strain channels in the real basis (each wave paired with its opposite)
+  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
-  // algorithmic flops of an operator product: 8 Np^2 per column; the operator is read
-  // once and the block read and written once.  The deviatoric product runs one batch
-  // item per k-point (shared operator, stride 0) so that converged k-points are
-  // skipped; the volumetric one (a sixth of the columns, too narrow per k for a full
-  // tile) runs over all k-points as one product (columns of converged k-points are
-  // computed from their last strains and not used).
+  // The compliance products with the real operators: 4 Np^2 flops per complex column (two
+  // real products); the operator (8 B per entry) read once, the block read and written
+  // once.  The deviatoric product runs one batch item per k-point (shared operator,
+  // stride 0) so that converged k-points are skipped; the volumetric one (a sixth of the
+  // columns, too narrow per k for a full tile) runs over all k-points as one product
+  // (columns of converged k-points are computed from their last strains and not used).
   const int ny = 6 * ncol, nt = ncol * sv.nk;
   const long sy = (long)d.Np * ny;
-  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * ny * nk, 16.0 * (Np * Np + 2.0 * Np * ny * nk));
-  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, d.Bm, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
-               nullptr, 1, msk, 1);
-  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * nt, 16.0 * (Np * Np + 2.0 * Np * nt));
-  gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, d.Dm, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
-               nullptr, 1);
+  PROF_KERNEL(PROF_OP_REAL, 4.0 * Np * Np * ny * nk, 8.0 * Np * Np + 32.0 * Np * ny * nk);
+  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, nullptr, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
+               nullptr, 2, msk, 1, 0, 0, d.Br);
+  PROF_KERNEL(PROF_OP_REAL, 4.0 * Np * Np * nt, 8.0 * Np * Np + 32.0 * Np * nt);
+  gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, nullptr, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
+               nullptr, 2, nullptr, 1, 0, 0, d.Dr);
   PROF_BEGIN(PROF_APPLY);
-  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk);
+  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
   // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
