@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 CLASSES = ["potrf_diag", "panel", "herk", "trsm_diag", "trsm_update", "solve_upd", "solve_diag", "sbinv",
-           "assemble", "apply", "op_gemm", "op_real", "gram", "small", "update", "residual", "adjoint"]
+           "assemble", "apply", "op_gemm", "gram", "small", "update", "residual", "adjoint"]
 FACTOR_CLASSES = ["potrf_diag", "panel", "herk", "sbinv"]
 
 
@@ -158,14 +158,13 @@ def main():
         upd = ("phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
                else f"phx::nrhs_kernel<double, 1, {nbk}, 1>")
         return {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", fpn, "mfma"),
-                "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 2>", "fp64", "mfma"),
-                "op_real": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 3>", "fp64", "mfma"),
+                "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 3>", "fp64", "mfma"),
                 "solve_upd": (upd, fpn, "hbm")}
 
     # The library counts the work of the padded problem (Np = 64 ceil(N / 64) waves per
     # displacement component); the algorithmic work is that of the N-wave problem: the
     # Cholesky update scales as the cube of the size, the operator products as the square.
-    unpad = {"herk": (N / Np) ** 3, "op_gemm": (N / Np) ** 2, "op_real": (N / Np) ** 2}
+    unpad = {"herk": (N / Np) ** 3, "op_gemm": (N / Np) ** 2}
 
     def entry(prof, c, single):
         """Roofline entry of single-kernel class c from per-step class counters."""

@@ -24,10 +24,9 @@ namespace phx {
 // (w % WM) * 32 .. +32 and columns (w / WM) * 32 .. +32 with 2 x 2 MFMA blocks.
 // Shapes: 64 x 64 (WM = 2) for square work, 128 x 32 (WM = 4) for the narrow
 // right-hand-side blocks of the triangular solves and subspace updates.
-// MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update), 2 k-shared
-// operator times a block (same code as 0; a separate instantiation so that profilers
-// report the matrix-free operator products on their own), 3 a real k-shared operator
-// (g.Ar) times a complex block: two real products per complex one instead of three.
+// MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update), 3 a real
+// k-shared operator (g.Ar) times a complex block: two real products per complex one
+// instead of three (the matrix-free operator products).
 template <typename R, int OPA, int OPB, int BM, int BN, int MODE>
 __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
@@ -532,12 +531,9 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.tri) {
     if (opa == 0 && opb == 1) PHX_LAUNCH((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid);
     else return (int)hipErrorInvalidValue;
-  } else if (g.op == 2) {
-    if (opa != 0 || opb != 0 || !g.Ar) return (int)hipErrorInvalidValue;
-    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 3>), grid);
   } else if (g.op) {
-    if (opa != 0 || opb != 0) return (int)hipErrorInvalidValue;
-    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 2>), grid);
+    if (g.op != 2 || opa != 0 || opb != 0 || !g.Ar) return (int)hipErrorInvalidValue;
+    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 3>), grid);
   } else if (narrow) {
     PHX_GEMM_LAUNCH(128, 32, 0);
   } else {

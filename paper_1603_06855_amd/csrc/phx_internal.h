@@ -20,7 +20,7 @@ struct GemmArgs {
   C_t<R>* Cm; long ldc, sC; int dC;
   C_t<R> alpha, beta;
   int tri;
-  int op;  // 1: A is a k-shared operator (stride 0); selects a separately named kernel; 2: a real one (Ar)
+  int op;  // 2: A is a real k-shared operator (Ar, stride 0), the matrix-free operator products
   const int* kact;  // optional device mask: batch item b is skipped when kact[b / kdiv] == 0
   int kdiv;
   int ksplit;

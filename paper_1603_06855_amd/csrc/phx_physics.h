@@ -28,8 +28,8 @@ template <typename R>
 void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                      int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st);
 // kact (optional, device): per-k mask; k-points with kact[k] == 0 are skipped.
-// pairN = N > 0: strain channels written in the real basis of launch_realify (pairs of
-// waves n_p, -n_p combined), and the force kernel's inputs read in that basis.
+// pairN = N > 0: the displacement columns, the strain channels, the stresses and the
+// forces are all in the paired basis of launch_realify (each wave n_p with -n_p).
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
                    double2* tr, hipStream_t st, const int* kact = nullptr, int pairN = 0);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
@@ -38,7 +38,14 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
 // real symmetric for the Fourier matrix of a real field and for its inverse.
 void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st);
 void launch_zero(double2* X, long n, hipStream_t st);
-void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st);
+// pairN = N > 0: the unit columns in the paired basis (launch_realify); Np: rows per component.
+void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st, int Np,
+                         int pairN);
+// Vector blocks (3 Np rows per column, ncol columns per k) to the paired basis in place
+// (dir > 0) or back to plane waves (dir < 0); k-points with kact[k] == 0 are skipped.
+template <typename T>
+void launch_pair(T* X, long ldx, long sX, int ncol, int N, int Np, int nk, int dir, hipStream_t st,
+                 const int* kact = nullptr);
 void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,
                     int Np, int s, int nk, hipStream_t st);
 template <typename R>
@@ -52,7 +59,7 @@ void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk
 template <typename R>
 void launch_jacobi(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                    double c2, const double* sigma, const C_t<R>* Rp, long sR, int s, double2* W, long sW, int nk,
-                   hipStream_t st, const int* kact = nullptr);
+                   hipStream_t st, const int* kact = nullptr, int pairN = 0);
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,
                        int Np, int nk, double2* Fc, hipStream_t st);
 void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int nsel, long n, int nk, double2* Y,

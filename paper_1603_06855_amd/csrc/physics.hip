@@ -235,11 +235,31 @@ __device__ __forceinline__ void wave_force(const double* K, const double2 (&z)[6
   o[2] = cscale(cadd(cscale(s2, K[2]), cscale(cadd(cscale(z[3], K[1]), cscale(z[4], K[0])), r2)), c2);
 }
 
+// The pairing of each wave with its opposite.  With c = (N-1)/2 and pb = N-1-p for p < c
+// (the wave index is lexicographic in n, so n_pb = -n_p and n_c = 0), the unitary U has the
+// columns u_p = (e_p + e_pb)/sqrt2, u_pb = i (e_p - e_pb)/sqrt2 and u_c = e_c.  A vector's
+// coordinates in that basis: (v_p, v_pb) -> U^H v = ((v_p + v_pb)/sqrt2, -i (v_p - v_pb)/sqrt2);
+// back: (a, b) -> U (a, b) = ((a + i b)/sqrt2, (a - i b)/sqrt2).  Every operator built from a
+// real field (Omega_s, the compliance inverses) is real symmetric in it (realify_kernel).
+__device__ __forceinline__ void to_pair(double2& a, double2& b) {
+  const double r2 = 0.70710678118654752440;
+  const double2 sm = cadd(a, b), df = csub(a, b);
+  a = cscale(sm, r2);
+  b = make_double2(df.y * r2, -df.x * r2);
+}
+__device__ __forceinline__ void from_pair(double2& a, double2& b) {
+  const double r2 = 0.70710678118654752440;
+  const double2 ib = make_double2(-b.y, b.x);
+  const double2 u = cscale(cadd(a, ib), r2), w = cscale(csub(a, ib), r2);
+  a = u;
+  b = w;
+}
+
 // Mandel strain (6 channels, Np x 6 ncol per k) and trace (Np x ncol per k) of ncol
-// displacement columns.  pairN = N > 0: the channels are written in the basis of
-// realify_kernel, u_p = (e_p + e_pb)/sqrt2, u_pb = i (e_p - e_pb)/sqrt2 (p < c = (N-1)/2,
-// pb = N-1-p), u_c = e_c: row p gets (y_p + y_pb)/sqrt2 and row pb gets -i (y_p - y_pb)/sqrt2;
-// one thread takes both waves of a pair (padding rows from N on are copied).
+// displacement columns.  pairN = N > 0: the columns X and the outputs are all in the
+// paired basis (to_pair): one thread takes both waves of a pair, returns them to plane
+// waves, forms their strains and pairs the channels again (padding rows from N on are
+// taken as they are).
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
                               double2* Y, double2* tr, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,30 +272,36 @@ __global__ void strain_kernel(const double2* X, long ldx, long sX, const double*
   double2* y = Y + (long)k * Np * 6 * ncol + (long)(6 * j) * Np;
   double2* tp = tr + (long)k * Np * ncol + (long)j * Np;
   double2 ya[6], ta;
-  wave_strain(Kv + ((long)k * Np + p) * 3, x[p], x[Np + p], x[2 * Np + p], ya, ta);
   if (pairN == 0 || p >= pairN || p == c) {
+    wave_strain(Kv + ((long)k * Np + p) * 3, x[p], x[Np + p], x[2 * Np + p], ya, ta);
     for (int ch = 0; ch < 6; ++ch) y[ch * Np + p] = ya[ch];
     tp[p] = ta;
     return;
   }
   const int pb = pairN - 1 - p;
-  double2 yb[6], tb;
-  wave_strain(Kv + ((long)k * Np + pb) * 3, x[pb], x[Np + pb], x[2 * Np + pb], yb, tb);
-  const double r2 = 0.70710678118654752440;
-  for (int ch = 0; ch < 6; ++ch) {
-    const double2 sm = cadd(ya[ch], yb[ch]), df = csub(ya[ch], yb[ch]);
-    y[ch * Np + p] = cscale(sm, r2);
-    y[ch * Np + pb] = make_double2(df.y * r2, -df.x * r2);  // -i df / sqrt2
+  double2 xa[3], xb[3];
+  for (int d = 0; d < 3; ++d) {
+    xa[d] = x[d * Np + p];
+    xb[d] = x[d * Np + pb];
+    from_pair(xa[d], xb[d]);
   }
-  const double2 sm = cadd(ta, tb), df = csub(ta, tb);
-  tp[p] = cscale(sm, r2);
-  tp[pb] = make_double2(df.y * r2, -df.x * r2);
+  double2 yb[6], tb;
+  wave_strain(Kv + ((long)k * Np + p) * 3, xa[0], xa[1], xa[2], ya, ta);
+  wave_strain(Kv + ((long)k * Np + pb) * 3, xb[0], xb[1], xb[2], yb, tb);
+  for (int ch = 0; ch < 6; ++ch) {
+    to_pair(ya[ch], yb[ch]);
+    y[ch * Np + p] = ya[ch];
+    y[ch * Np + pb] = yb[ch];
+  }
+  to_pair(ta, tb);
+  tp[p] = ta;
+  tp[pb] = tb;
 }
 
 // Mandel stress coefficients S = Zy + (Zt / 3) [1,1,1,0,0,0] and the force
 // (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).  pairN = N > 0:
-// Zy and Zt are in the basis of realify_kernel and go back first (row p of the result is
-// (z_p + i z_pb)/sqrt2, row pb is (z_p - i z_pb)/sqrt2).
+// Zy, Zt and KX are in the paired basis (to_pair); the stresses of a pair go back to plane
+// waves, and their forces are paired again.
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
                              double2* KX, long ldk, long sK, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,18 +321,17 @@ __global__ void force_kernel(const double2* Zy, const double2* Zt, const double*
     return;
   }
   const int pb = pairN - 1 - p;
-  const double r2 = 0.70710678118654752440;
-  double2 zp[6], zq[6], fb[3];
+  double2 zq[6], fb[3];
   for (int ch = 0; ch < 6; ++ch) {
-    const double2 u = za[ch], w = z[ch * Np + pb];
-    const double2 iw = make_double2(-w.y, w.x);
-    zp[ch] = cscale(cadd(u, iw), r2);
-    zq[ch] = cscale(csub(u, iw), r2);
+    zq[ch] = z[ch * Np + pb];
+    from_pair(za[ch], zq[ch]);
   }
-  const double2 tu = zt[p], tw = zt[pb], itw = make_double2(-tw.y, tw.x);
-  wave_force(Kv + ((long)k * Np + p) * 3, zp, cscale(cadd(tu, itw), r2), c2, fa);
-  wave_force(Kv + ((long)k * Np + pb) * 3, zq, cscale(csub(tu, itw), r2), c2, fb);
+  double2 ta = zt[p], tb = zt[pb];
+  from_pair(ta, tb);
+  wave_force(Kv + ((long)k * Np + p) * 3, za, ta, c2, fa);
+  wave_force(Kv + ((long)k * Np + pb) * 3, zq, tb, c2, fb);
   for (int d = 0; d < 3; ++d) {
+    to_pair(fa[d], fb[d]);
     o[d * Np + p] = fa[d];
     o[d * Np + pb] = fb[d];
   }
@@ -353,11 +378,30 @@ __global__ void zero_kernel(double2* X, long n) {
     X[e] = make_double2(0, 0);
 }
 
-__global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* idx, int s) {
+// Unit columns: column j of k-point k is the plane wave row idx[k s + j] (component d =
+// row / Np, wave q = row % Np).  pairN = N > 0: written in the paired basis (to_pair): e_q
+// with q < c has the coordinates 1/sqrt2 at q and -i/sqrt2 at N-1-q, with q > c 1/sqrt2 at
+// N-1-q and i/sqrt2 at q; e_c is u_c.  The columns must be zero before.
+__global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* idx, int s, int Np, int pairN) {
   const int j = threadIdx.x;
   const int k = blockIdx.x;
   if (j >= s) return;
-  X[(long)k * sX + (long)j * ldx + idx[k * s + j]] = make_double2(1.0, 0.0);
+  const int row = idx[k * s + j], q = row % Np, base = row - q;
+  double2* x = X + (long)k * sX + (long)j * ldx + base;
+  const int c = (pairN - 1) / 2;
+  if (pairN == 0 || q >= pairN || q == c) {
+    x[q] = make_double2(1.0, 0.0);
+    return;
+  }
+  const double r2 = 0.70710678118654752440;
+  const int qb = pairN - 1 - q;
+  if (q < c) {
+    x[q] = make_double2(r2, 0.0);
+    x[qb] = make_double2(0.0, -r2);
+  } else {
+    x[qb] = make_double2(r2, 0.0);
+    x[q] = make_double2(0.0, r2);
+  }
 }
 
 // R = KX - theta OX per column (one block per (column, k)); writes R into Rp in the
@@ -429,35 +473,16 @@ __global__ void widen_kernel(const C_t<R>* Rp, long sR, long n, double2* W, long
 // form, from the diagonals of the k-shared operators and the wave vector K_p: never from
 // K(k) itself).  Padding waves (p >= N) are identity.  R: n3 x s per k (k-stride sR,
 // precision R); W: n3 x s per k in FP64 (ld n3, k-stride sW).  One thread per (wave, k).
-template <typename R>
-__global__ __launch_bounds__(256) void jacobi_kernel(const double2* Dm, const double2* Bm, const double2* Os,
-                                                      const double* Kv, int N, int Np, double c2,
-                                                      const double* sigma, const C_t<R>* Rp, long sR, int s,
-                                                      double2* W, long sW, const int* kact) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (p >= Np || (kact && !kact[k])) return;
-  const long n3 = 3L * Np;
-  const C_t<R>* r = Rp + (long)k * sR + p;
-  double2* w = W + (long)k * sW + p;
-  if (p >= N) {
-    for (int j = 0; j < s; ++j)
-      for (int c = 0; c < 3; ++c) {
-        const C_t<R> v = r[j * n3 + c * Np];
-        w[j * n3 + c * Np] = make_double2((double)v.x, (double)v.y);
-      }
-    return;
-  }
-  // the diagonal entries of Hermitian operators are real
-  const double dm = Dm[p + (long)p * Np].x, bm = Bm[p + (long)p * Np].x, os = Os[p + (long)p * Np].x;
-  const double* kp = Kv + ((long)k * Np + p) * 3;
+// pairN = N > 0: R and W are in the paired basis (to_pair); the thread of a pair (p < c)
+// takes both waves, D(k) being block diagonal in plane waves, not in the pairs.
+// The inverse of wave p's block (symmetric positive definite) by its adjugate.
+__device__ __forceinline__ void jacobi_block(double dm, double bm, double os, const double* kp, double c2,
+                                             double sigma, double (&inv)[3][3]) {
   const double kk = kp[0] * kp[0] + kp[1] * kp[1] + kp[2] * kp[2];
   double a[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      a[i][j] = c2 * kp[i] * kp[j] * (dm / 3.0 + 0.5 * bm) + (i == j ? 0.5 * c2 * kk * bm + sigma[k] * os : 0.0);
-  // inverse of the symmetric positive definite 3 x 3 block by its adjugate
-  double inv[3][3];
+      a[i][j] = c2 * kp[i] * kp[j] * (dm / 3.0 + 0.5 * bm) + (i == j ? 0.5 * c2 * kk * bm + sigma * os : 0.0);
   inv[0][0] = a[1][1] * a[2][2] - a[1][2] * a[2][1];
   inv[0][1] = a[0][2] * a[2][1] - a[0][1] * a[2][2];
   inv[0][2] = a[0][1] * a[1][2] - a[0][2] * a[1][1];
@@ -467,22 +492,102 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* Dm, const do
   inv[2][0] = a[1][0] * a[2][1] - a[1][1] * a[2][0];
   inv[2][1] = a[0][1] * a[2][0] - a[0][0] * a[2][1];
   inv[2][2] = a[0][0] * a[1][1] - a[0][1] * a[1][0];
-  const double det = a[0][0] * inv[0][0] + a[0][1] * inv[1][0] + a[0][2] * inv[2][0];
-  const double id = 1.0 / det;
-  for (int j = 0; j < s; ++j) {
-    double2 v[3];
+  const double id = 1.0 / (a[0][0] * inv[0][0] + a[0][1] * inv[1][0] + a[0][2] * inv[2][0]);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) inv[i][j] *= id;
+}
+
+__device__ __forceinline__ void apply3(const double (&inv)[3][3], const double2 (&v)[3], double2 (&o)[3]) {
+  for (int i = 0; i < 3; ++i) {
+    o[i] = make_double2(0, 0);
     for (int c = 0; c < 3; ++c) {
-      const C_t<R> x = r[j * n3 + c * Np];
+      o[i].x += inv[i][c] * v[c].x;
+      o[i].y += inv[i][c] * v[c].y;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void jacobi_kernel(const double2* Dm, const double2* Bm, const double2* Os,
+                                                      const double* Kv, int N, int Np, double c2,
+                                                      const double* sigma, const C_t<R>* Rp, long sR, int s,
+                                                      double2* W, long sW, const int* kact, int pairN) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (p >= Np || (kact && !kact[k])) return;
+  const int cp = (pairN - 1) / 2;
+  if (pairN > 0 && p > cp && p < pairN) return;  // the partner thread writes this row
+  const long n3 = 3L * Np;
+  const C_t<R>* r = Rp + (long)k * sR;
+  double2* w = W + (long)k * sW;
+  if (p >= N) {
+    for (int j = 0; j < s; ++j)
+      for (int c = 0; c < 3; ++c) {
+        const C_t<R> v = r[j * n3 + c * Np + p];
+        w[j * n3 + c * Np + p] = make_double2((double)v.x, (double)v.y);
+      }
+    return;
+  }
+  // the diagonal entries of Hermitian operators are real
+  auto block = [&](int q, double (&inv)[3][3]) {
+    jacobi_block(Dm[q + (long)q * Np].x, Bm[q + (long)q * Np].x, Os[q + (long)q * Np].x,
+                 Kv + ((long)k * Np + q) * 3, c2, sigma[k], inv);
+  };
+  auto load = [&](int j, int q, double2 (&v)[3]) {
+    for (int c = 0; c < 3; ++c) {
+      const C_t<R> x = r[j * n3 + c * Np + q];
       v[c] = make_double2((double)x.x, (double)x.y);
     }
-    for (int i = 0; i < 3; ++i) {
-      double2 o = make_double2(0, 0);
-      for (int c = 0; c < 3; ++c) {
-        o.x += inv[i][c] * v[c].x;
-        o.y += inv[i][c] * v[c].y;
-      }
-      w[j * n3 + i * Np] = make_double2(o.x * id, o.y * id);
+  };
+  double inv[3][3];
+  block(p, inv);
+  if (pairN == 0 || p == cp) {
+    for (int j = 0; j < s; ++j) {
+      double2 v[3], o[3];
+      load(j, p, v);
+      apply3(inv, v, o);
+      for (int c = 0; c < 3; ++c) w[j * n3 + c * Np + p] = o[c];
     }
+    return;
+  }
+  const int pb = pairN - 1 - p;
+  double invb[3][3];
+  block(pb, invb);
+  for (int j = 0; j < s; ++j) {
+    double2 va[3], vb[3], oa[3], ob[3];
+    load(j, p, va);
+    load(j, pb, vb);
+    for (int c = 0; c < 3; ++c) from_pair(va[c], vb[c]);
+    apply3(inv, va, oa);
+    apply3(invb, vb, ob);
+    for (int c = 0; c < 3; ++c) {
+      to_pair(oa[c], ob[c]);
+      w[j * n3 + c * Np + p] = oa[c];
+      w[j * n3 + c * Np + pb] = ob[c];
+    }
+  }
+}
+
+// Change of basis of vector blocks in place: dir > 0 plane waves -> paired basis (to_pair),
+// dir < 0 back (from_pair).  X: n3 = 3 Np rows (three components of Np waves, the first N
+// paired) x ncol per k (ld ldx, k-stride sX); T = float2 or double2, arithmetic in FP64.
+template <typename T>
+__global__ void pair_kernel(T* X, long ldx, long sX, int ncol, int N, int Np, int dir, const int* kact) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  const int c = (N - 1) / 2;
+  if (p >= c || j >= ncol || (kact && !kact[k])) return;
+  T* x = X + (long)k * sX + (long)j * ldx;
+  const int pb = N - 1 - p;
+  for (int d = 0; d < 3; ++d) {
+    const T u = x[d * Np + p], v = x[d * Np + pb];
+    double2 a = make_double2((double)u.x, (double)u.y), b = make_double2((double)v.x, (double)v.y);
+    if (dir > 0) to_pair(a, b);
+    else from_pair(a, b);
+    x[d * Np + p].x = a.x;
+    x[d * Np + p].y = a.y;
+    x[d * Np + pb].x = b.x;
+    x[d * Np + pb].y = b.y;
   }
 }
 
@@ -668,9 +773,20 @@ void launch_zero(double2* X, long n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, st, X, n);
 }
 
-void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st) {
-  hipLaunchKernelGGL(unit_columns_kernel, dim3(nk), dim3(64), 0, st, X, ldx, sX, idx, s);
+void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st, int Np,
+                         int pairN) {
+  hipLaunchKernelGGL(unit_columns_kernel, dim3(nk), dim3(64), 0, st, X, ldx, sX, idx, s, Np, pairN);
 }
+
+template <typename T>
+void launch_pair(T* X, long ldx, long sX, int ncol, int N, int Np, int nk, int dir, hipStream_t st, const int* kact) {
+  const int c = (N - 1) / 2;
+  if (c > 0 && ncol > 0 && nk > 0)
+    hipLaunchKernelGGL((pair_kernel<T>), dim3(nblk(c, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, ncol, N, Np, dir,
+                       kact);
+}
+template void launch_pair<double2>(double2*, long, long, int, int, int, int, int, hipStream_t, const int*);
+template void launch_pair<float2>(float2*, long, long, int, int, int, int, int, hipStream_t, const int*);
 
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
@@ -694,16 +810,16 @@ template void launch_widen<double>(const double2*, long, long, double2*, long, i
 template <typename R>
 void launch_jacobi(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                    double c2, const double* sigma, const C_t<R>* Rp, long sR, int s, double2* W, long sW, int nk,
-                   hipStream_t st, const int* kact) {
+                   hipStream_t st, const int* kact, int pairN) {
   hipLaunchKernelGGL((jacobi_kernel<R>), dim3(nblk(Np, 256), nk), dim3(256), 0, st, Dm, Bm, Os, Kv, N, Np, c2, sigma,
-                     Rp, sR, s, W, sW, kact);
+                     Rp, sR, s, W, sW, kact, pairN);
 }
 template void launch_jacobi<double>(const double2*, const double2*, const double2*, const double*, int, int, double,
                                     const double*, const double2*, long, int, double2*, long, int, hipStream_t,
-                                    const int*);
+                                    const int*, int);
 template void launch_jacobi<float>(const double2*, const double2*, const double2*, const double*, int, int, double,
                                    const double*, const float2*, long, int, double2*, long, int, hipStream_t,
-                                   const int*);
+                                   const int*, int);
 template void launch_widen<float>(const float2*, long, long, double2*, long, int, hipStream_t, const int*);
 
 void launch_field_coef(const double2* X, long ldx, long sX, int nsel, const double2* Zy, const double2* Zt, int N,

@@ -89,19 +89,18 @@ struct Stats {
 enum RtClass {
   PROF_ASSEMBLE = phx::PROF_NCLASS_DENSE,
   PROF_APPLY,     // strain and force (pointwise parts of the matrix-free K X)
-  PROF_OP_GEMM,   // the k-shared complex operator product Omega_s X
+  PROF_OP_GEMM,   // the k-shared operator products (Dm, Bm, Omega_s, real in the paired basis)
   PROF_GRAM,
   PROF_SMALL,
   PROF_UPDATE,
   PROF_RESIDUAL,
   PROF_ADJOINT,
-  PROF_OP_REAL,   // the real compliance products Br Y, Dr t (K X in the real basis)
   PROF_NCLASS
 };
 const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",      "herk",  "trsm_diag", "trsm_update",
                                              "solve_upd",  "solve_diag", "sbinv", "assemble",  "apply",
                                              "op_gemm",    "gram",      "small", "update",    "residual",
-                                             "adjoint",    "op_real"};
+                                             "adjoint"};
 
 struct PendKernel {
   int cls;
@@ -400,8 +399,11 @@ struct Design {
   double2* Os = nullptr;   // Np x Np
   double2* Dm = nullptr;   // Pv^{-1} - Pd^{-1}
   double2* Bm = nullptr;   // Pd^{-1}
-  double* Dr = nullptr;    // Dm and Bm in the real basis pairing n_p with -n_p (launch_realify)
+  // Dm, Bm and Os in the basis pairing each wave n_p with -n_p (launch_realify), where they
+  // are real: the eigensolver's vectors live in that basis
+  double* Dr = nullptr;
   double* Br = nullptr;
+  double* Or = nullptr;
 };
 
 MaterialND nondim(const phx_cell& c) {
@@ -504,12 +506,14 @@ void setup_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, co
   d.Os = ops;
   d.Dm = inv;
   d.Bm = inv + NN;
-  // the two compliance inverses in the basis where they are real: the operator products
-  // of K X take two real products per complex one instead of three
-  d.Dr = dbuf<double>(ctx, tag + "opr", 2 * NN);
+  // the operators in the basis where they are real: each product with a complex block takes
+  // two real products instead of three
+  d.Dr = dbuf<double>(ctx, tag + "opr", 3 * NN);
   d.Br = d.Dr + NN;
+  d.Or = d.Dr + 2 * NN;
   launch_realify(d.Dm, d.N, d.Np, d.Dr, st);
   launch_realify(d.Bm, d.N, d.Np, d.Br, st);
+  launch_realify(d.Os, d.N, d.Np, d.Or, st);
   KCHK(hipGetLastError());
 }
 
@@ -600,7 +604,7 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   double2* X = Big + c0 * n3;
   const double Np = d.Np, nk = nm;  // algorithmic work counts the selected k-points only
   PROF_BEGIN(PROF_APPLY);
-  // strain channels in the real basis (each wave paired with its opposite)
+  // strain channels of the paired-basis columns, in the same basis
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
@@ -612,20 +616,20 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   // (columns of converged k-points are computed from their last strains and not used).
   const int ny = 6 * ncol, nt = ncol * sv.nk;
   const long sy = (long)d.Np * ny;
-  PROF_KERNEL(PROF_OP_REAL, 4.0 * Np * Np * ny * nk, 8.0 * Np * Np + 32.0 * Np * ny * nk);
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * ny * nk, 8.0 * Np * Np + 32.0 * Np * ny * nk);
   gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, nullptr, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
                nullptr, 2, msk, 1, 0, 0, d.Br);
-  PROF_KERNEL(PROF_OP_REAL, 4.0 * Np * Np * nt, 8.0 * Np * Np + 32.0 * Np * nt);
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * nt, 8.0 * Np * Np + 32.0 * Np * nt);
   gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, nullptr, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
                nullptr, 2, nullptr, 1, 0, 0, d.Dr);
   PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
-  // Omega X: Omega_s acting on the Np x (3 ncol) view of the columns.
-  PROF_KERNEL(PROF_OP_GEMM, 8.0 * Np * Np * 3 * ncol * nk, 16.0 * (Np * Np + 2.0 * Np * 3 * ncol * nk));
-  gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, d.Os, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
-               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 1, msk, 1);
+  // Omega X: the real Omega_s acting on the Np x (3 ncol) view of the columns.
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 3 * ncol * nk, 8.0 * Np * Np + 32.0 * Np * 3 * ncol * nk);
+  gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, nullptr, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
+               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 2, msk, 1, 0, 0, d.Or);
 }
 
 // The k-point selection of one eigensolver step: a device mask and its host count.
@@ -727,14 +731,17 @@ void precondition(Solver& sv) {
     Design& d = *sv.d;
     PROF_BEGIN(PROF_APPLY);
     launch_jacobi<R>(d.Dm, d.Bm, d.Os, sv.Kv, d.N, d.Np, d.c2, sv.sigma_d, (const C_t<R>*)sv.Rp, n3 * sv.s, sv.s,
-                     sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream, sv.kjac);
+                     sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream, sv.kjac, d.N);
     PROF_END(PROF_APPLY, 0, (double)sv.njac * 3.0 * d.N * sv.s * (sizeof(C_t<R>) + 16.0));
     KCHK(hipGetLastError());
   }
-  if (sv.npen > 0) {  // the pencil factors: forward and backward super-block solves
+  if (sv.npen > 0) {  // the pencil factors (plane-wave basis): forward and backward super-block solves
+    Design& d = *sv.d;
+    launch_pair<C_t<R>>((C_t<R>*)sv.Rp, n3, n3 * sv.s, sv.s, d.N, d.Np, sv.nk, -1, ctx->stream, sv.kpen);
     KCHK(potrs_batched<R>((const C_t<R>*)sv.A, (int)n3, n3, n3 * n3, sv.nk, (const C_t<R>*)sv.Dinv,
                           (n3 / 64) * 4096, (C_t<R>*)sv.Rp, n3, n3 * sv.s, (C_t<R>*)sv.Zp, n3, n3 * sv.s, sv.s,
                           ctx->stream, ctx->hk(), (const C_t<R>*)sv.SBinv, sv.kpen, sv.fmap, sv.npen));
+    launch_pair<C_t<R>>((C_t<R>*)sv.Rp, n3, n3 * sv.s, sv.s, d.N, d.Np, sv.nk, 1, ctx->stream, sv.kpen);
     launch_widen<R>((const C_t<R>*)sv.Rp, n3 * sv.s, n3 * sv.s, sv.Big + sv.s * n3, sv.sBig, sv.nk, ctx->stream,
                     sv.kpen);
     KCHK(hipGetLastError());
@@ -927,7 +934,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     HIPCHK(hipMemcpy2DAsync(sv.Big, sv.sBig * sizeof(double2), init, n3 * s * sizeof(double2), n3 * s * sizeof(double2),
                             nk, hipMemcpyDeviceToDevice, st));
   } else {
-    launch_unit_columns(sv.Big, n3, sv.sBig, idx_d, s, nk, st);
+    launch_unit_columns(sv.Big, n3, sv.sBig, idx_d, s, nk, st, d.Np, d.N);
   }
   KCHK(hipGetLastError());
   apply_ops(sv, sv.Big, 0, s);
@@ -1109,6 +1116,7 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
   HIPCHK(hipMemcpyAsync(sel_d, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
   double2* Xs = dbuf<double2>(ctx, "Xsel", (long)nk * n3 * nsel);
   launch_gather_cols(sv.Big, n3, sv.sBig, sel_d, nsel, n3, nk, Xs, n3 * nsel, st);
+  launch_pair<double2>(Xs, n3, n3 * nsel, nsel, d.N, d.Np, nk, -1, st);  // back to plane waves
   double* lam = dbuf<double>(ctx, "lam_sel", (long)nk * nsel);
   std::vector<double> th((size_t)nk * sv.s), lh((size_t)nk * nsel);
   HIPCHK(hipMemcpyAsync(th.data(), sv.theta, th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
