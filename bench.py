@@ -158,7 +158,7 @@ def main():
         upd = ("phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
                else f"phx::nrhs_kernel<double, 1, {nbk}, 1>")
         return {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", fpn, "mfma"),
-                "op_gemm": ("phx::zgemm_kernel<double, 0, 0, 64, 64, 3>", "fp64", "mfma"),
+                "op_gemm": ("phx::opgemm_kernel", "fp64", "mfma"),
                 "solve_upd": (upd, fpn, "hbm")}
 
     # The library counts the work of the padded problem (Np = 64 ceil(N / 64) waves per
@@ -419,8 +419,8 @@ def main():
 
 
 def kernel_source_sha(kernel: str):
-    """SHA-256 of the text of the template definition of `kernel` ("phx::name<...>") in the
-    HIP sources, or None."""
+    """SHA-256 of the text of the definition of `kernel` ("phx::name" or "phx::name<...>":
+    the whole template) in the HIP sources, or None."""
     import glob
     import hashlib
     base = kernel.split("<")[0].split("::")[-1]
@@ -429,7 +429,8 @@ def kernel_source_sha(kernel: str):
         i = src.find(f" void {base}(")
         if i < 0:
             continue
-        start = src.rfind("template <", 0, i)
+        # the template line of a template kernel, else the line after the previous definition
+        start = max(src.rfind("template <", 0, i), src.rfind("\n}\n", 0, i) + 3)
         end = src.index("\n}\n", i) + 3
         return hashlib.sha256(src[start:end].encode()).hexdigest()
     return None

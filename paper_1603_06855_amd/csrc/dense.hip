@@ -24,9 +24,7 @@ namespace phx {
 // (w % WM) * 32 .. +32 and columns (w / WM) * 32 .. +32 with 2 x 2 MFMA blocks.
 // Shapes: 64 x 64 (WM = 2) for square work, 128 x 32 (WM = 4) for the narrow
 // right-hand-side blocks of the triangular solves and subspace updates.
-// MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update), 3 a real
-// k-shared operator (g.Ar) times a complex block: two real products per complex one
-// instead of three (the matrix-free operator products).
+// MODE: 0 general, 1 lower-triangular tile grid (Hermitian rank-k update).
 template <typename R, int OPA, int OPB, int BM, int BN, int MODE>
 __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
@@ -71,7 +69,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
     tj = (int)(tile_lin / tm);
   }
   const int row0 = ti * BM, col0 = tj * BN;
-  const int b = (int)bat;
+  const int b = g.bidx ? g.bidx[bat / g.kdiv] * g.kdiv + (int)(bat % g.kdiv) : (int)bat;
   if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
   const int sp = blockIdx.z;
   const C* A = g.A + (long)(g.amap ? g.amap[b] : b / g.dA) * g.sA;
@@ -108,11 +106,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPA == 0) { i = row0 + (gi % (BM / VA)) * VA + q; k = k0 + gi / (BM / VA); }
         else { k = k0 + (gi % (KS / VA)) * VA + q; i = row0 + gi / (KS / VA); }
         C v = mk<R>(0, 0);
-        if constexpr (MODE == 3) {
-          if (i < g.M && k < kend) v = mk<R>(g.Ar[i + (long)k * g.lda], 0);
-        } else {
-          if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
-        }
+        if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
         ra[r * VA + q] = v;
       }
     }
@@ -140,7 +134,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPA == 0) { ii = (gi % (BM / VA)) * VA + q; kk = gi / (BM / VA); }
         else { kk = (gi % (KS / VA)) * VA + q; ii = gi / (KS / VA); }
         Asr[kk][ii] = ra[r * VA + q].x;
-        if constexpr (MODE != 3) Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
+        Asi[kk][ii] = OPA == 0 ? ra[r * VA + q].y : -ra[r * VA + q].y;
       }
     }
 #pragma unroll
@@ -161,22 +155,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
 #pragma unroll
     for (int kk = 0; kk < KS / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      if constexpr (MODE == 3) {  // real A: t1 = A Re B, t2 = A Im B
-        R ar[2], br[2], bi[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          ar[x] = Asr[kr][wr * 32 + x * 16 + (lane & 15)];
-          br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
-          bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
-            t2[x][y] = mfma16(bi[y], ar[x], t2[x][y]);
-          }
-      } else {
+      {
         R ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
@@ -237,13 +216,166 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         // row l/16 + 4r of the 16x16 block, column l%16 in both (here rows are C columns).
         const int col = col0 + wc * 32 + y * 16 + (sizeof(R) == 8 ? ((lane >> 4) + 4 * r) : (((lane >> 4) << 2) + r));
         if (row < g.M && col < g.N) {
-          const C acc = MODE == 3 ? mk<R>(t1[x][y][r], t2[x][y][r])
-                                  : mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
+          const C acc = mk<R>(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
           C v = cmul(g.alpha, acc);
           if (useBeta) v = cadd(v, cmul(g.beta, Cb[row + (long)col * ldc]));
           Cb[row + (long)col * ldc] = v;
         }
       }
+}
+
+// Real k-shared operators times complex blocks (OpArgs): one 64 x 64 output tile per
+// workgroup of 4 waves, two real MFMA products per complex one (A Re B and A Im B), one LDS
+// stage of KS = 8 with the next stage's global loads in flight.  The tiles of all the
+// launch's products form one list: within a product the 64-row tiles of one (item, column
+// tile) are consecutive, so they share that block's columns, and the list is dealt to
+// the 8 XCDs in contiguous ranges (workgroups go to XCDs round-robin by linear id).  Only
+// listed items have tiles, so converged k-points cost nothing and the work of every XCD
+// is the same.
+__device__ __forceinline__ long op_tiles(const OpSeg& s, int tm) {
+  const int tn = (s.ncolk > 0 ? s.nb * s.ncolk + 63 : s.N + 63) / 64;
+  return (long)tm * tn * (s.ncolk > 0 ? 1 : s.nb);
+}
+
+__global__ __launch_bounds__(256, 3) void opgemm_kernel(OpArgs g) {
+  constexpr int BM = 64, BN = 64, KS = 8;
+  __shared__ double As[KS][BM + 4], Bsr[KS][BN + 4], Bsi[KS][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int tm = (g.M + BM - 1) / BM;
+  const long c0 = op_tiles(g.seg[0], tm), c1 = g.nseg > 1 ? op_tiles(g.seg[1], tm) : 0;
+  const long c2 = g.nseg > 2 ? op_tiles(g.seg[2], tm) : 0;
+  long logical;
+  {
+    const long total = c0 + c1 + c2, lin = blockIdx.x;
+    const long per = total / 8, rem = total % 8, xcd = lin % 8, idx = lin / 8;
+    logical = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  }
+  int si = 0;
+  if (logical >= c0) {
+    logical -= c0;
+    si = 1;
+    if (logical >= c1) {
+      logical -= c1;
+      si = 2;
+    }
+  }
+  const OpSeg S = si == 0 ? g.seg[0] : (si == 1 ? g.seg[1] : g.seg[2]);
+  const int ncols = S.ncolk > 0 ? S.nb * S.ncolk : S.N;
+  const int tn = (ncols + BN - 1) / BN;
+  const int ti = (int)(logical % tm);
+  const long rest = logical / tm;
+  const int tj = (int)(rest % tn), bat = (int)(rest / tn);
+  const int row0 = ti * BM, col0 = tj * BN;
+  const double2* B = S.B;
+  double2* Cb = S.C;
+  if (S.ncolk == 0) {
+    const long it = S.bidx ? S.bidx[bat] : bat;
+    B += it * S.sB;
+    Cb += it * S.sC;
+  }
+  // the stored column of output column j of this product
+  auto colof = [&](int j) -> long { return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.ncolk + j % S.ncolk : j; };
+
+  // staging: A 64 x 8 (two consecutive rows per thread), B 8 x 64 (two consecutive k of one
+  // column per thread); the thread's B column is fixed for the whole tile
+  const int ai = (tid % 32) * 2, ak = tid / 32;
+  const int bk = (tid % 4) * 2, bj = tid / 4;
+  const bool bvalid = col0 + bj < ncols;
+  const double2* bcol = B + (bvalid ? colof(col0 + bj) : 0) * S.ldb;
+  double ra[2];
+  double2 rb[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = row0 + ai + q, k = k0 + ak;
+      ra[q] = (i < g.M && k < g.K) ? S.A[i + (long)k * g.lda] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = k0 + bk + q;
+      rb[q] = (bvalid && k < g.K) ? bcol[k] : make_double2(0, 0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) As[ak][ai + q] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      Bsr[bk + q][bj] = rb[q].x;
+      Bsi[bk + q][bj] = rb[q].y;
+    }
+  };
+  typedef acc_t<double>::type ACC;
+  ACC t1[2][2], t2[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      t1[x][y] = (ACC){0, 0, 0, 0};
+      t2[x][y] = (ACC){0, 0, 0, 0};
+    }
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < g.K; k0 += KS) {
+    const bool more = k0 + KS < g.K;
+    if (more) load(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double ar[2], br[2], bi[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        ar[x] = As[kr][wr * 32 + x * 16 + (lane & 15)];
+        br[x] = Bsr[kr][wc * 32 + x * 16 + (lane & 15)];
+        bi[x] = Bsi[kr][wc * 32 + x * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          t1[x][y] = mfma16(br[y], ar[x], t1[x][y]);
+          t2[x][y] = mfma16(bi[y], ar[x], t2[x][y]);
+        }
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+  // epilogue: lane l, register r of a 16 x 16 block holds row l % 16, column l / 16 + 4 r
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = col0 + wc * 32 + y * 16 + (lane >> 4) + 4 * r;
+      if (col >= ncols) continue;
+      double2* cc = Cb + colof(col) * S.ldc;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int row = row0 + wr * 32 + x * 16 + (lane & 15);
+        if (row < g.M) cc[row] = make_double2(t1[x][y][r], t2[x][y][r]);
+      }
+    }
+}
+
+int opgemm(const OpArgs& g, hipStream_t st) {
+  if (g.nseg < 1 || g.nseg > 3 || g.M <= 0 || g.K <= 0) return (int)hipErrorInvalidValue;
+  const int tm = (g.M + 63) / 64;
+  long total = 0;
+  for (int s = 0; s < g.nseg; ++s) {
+    const OpSeg& q = g.seg[s];
+    if (q.nb < 0 || (q.ncolk > 0 && !q.bidx)) return (int)hipErrorInvalidValue;
+    const int ncols = q.ncolk > 0 ? q.nb * q.ncolk : q.N;
+    total += (long)tm * ((ncols + 63) / 64) * (q.ncolk > 0 ? 1 : q.nb);
+  }
+  if (total == 0) return 0;
+  if (total > 0x7fffffffL) return (int)hipErrorInvalidValue;
+  if (g.ev0) hipExtLaunchKernelGGL(opgemm_kernel, dim3((unsigned)total), dim3(256), 0, st, g.ev0, g.ev1, 0, g);
+  else hipLaunchKernelGGL(opgemm_kernel, dim3((unsigned)total), dim3(256), 0, st, g);
+  return (int)hipGetLastError();
 }
 
 // Tall-skinny products C = A W (beta = 0, alpha = 1) with K <= 64, N <= 16 NB: the
@@ -261,7 +393,7 @@ __global__ __launch_bounds__(256, 2) void skinny_kernel(GemmArgs<R> g) {
   __shared__ R Wr[64][NC + 1], Wi[64][NC + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int b = blockIdx.y;
+  const int b = g.bidx ? g.bidx[blockIdx.y / g.kdiv] * g.kdiv + blockIdx.y % g.kdiv : blockIdx.y;
   if (g.kact && !g.kact[b / g.kdiv]) return;  // whole workgroup: a converged k-point
   const C* A = g.A + (long)(b / g.dA) * g.sA;
   const C* W = g.B + (long)(b / g.dB) * g.sB;
@@ -448,7 +580,7 @@ template <typename R>
 __global__ void zgemm_reduce_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   const long MN = (long)g.M * g.N;
-  const int b = blockIdx.y;
+  const int b = g.bidx ? g.bidx[blockIdx.y / g.kdiv] * g.kdiv + blockIdx.y % g.kdiv : blockIdx.y;
   if (g.kact && !g.kact[b / g.kdiv]) return;
   C* Cb = g.Cm + (long)(b / g.dC) * g.sC;
   const bool useBeta = (g.beta.x != 0 || g.beta.y != 0);
@@ -482,11 +614,15 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     g.ksplit = 1;
   }
   if (g.ksplit > 1) g.ev0 = g.ev1 = nullptr;  // two kernels: no single-kernel timing
+  // Listed batch items only (tiled, tall-skinny and reduction kernels): the grid covers
+  // nbat * kdiv items.
+  if (g.bidx && g.nbat <= 0) return 0;
+  const unsigned nbatch = g.bidx ? (unsigned)(g.nbat * g.kdiv) : (unsigned)g.batch;
   // Tall-skinny updates (the eigensolver's basis times a small coefficient matrix).
-  if (opa == 0 && opb == 0 && !g.tri && !g.op && !g.amap && g.ksplit == 1 && g.K <= 64 && g.N <= 64 &&
+  if (opa == 0 && opb == 0 && !g.tri && !g.amap && g.ksplit == 1 && g.K <= 64 && g.N <= 64 &&
       (g.M >= 256 || g.csplit > 0) &&
       g.alpha.x == 1 && g.alpha.y == 0 && g.beta.x == 0 && g.beta.y == 0) {
-    dim3 grid2((unsigned)((g.M + 64 * 4 - 1) / (64 * 4)), (unsigned)g.batch);
+    dim3 grid2((unsigned)((g.M + 64 * 4 - 1) / (64 * 4)), nbatch);
     if (g.N <= 16) PHX_LAUNCH((skinny_kernel<R, 1, 4>), grid2);
     else if (g.N <= 32) PHX_LAUNCH((skinny_kernel<R, 2, 4>), grid2);
     else if (g.N <= 48) PHX_LAUNCH((skinny_kernel<R, 3, 4>), grid2);
@@ -497,7 +633,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.amap && g.ksplit > 1) return (int)hipErrorInvalidValue;
   // Few right-hand sides (N <= 32, B not transposed): one streaming pass over A (for
   // FP32 A^H with more than 256 rows the LDS-staged 128 x 32 tiles below read A faster).
-  if (!g.tri && !g.op && !g.tiled && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 &&
+  if (!g.tri && !g.bidx && !g.tiled && opb == 0 && g.ksplit == 1 && g.N <= 32 && g.K > 0 &&
       (opa == 0 || sizeof(R) == 8 || g.M <= 256)) {
     constexpr int X = 1;
     dim3 grid2((unsigned)((g.M + 64 * X - 1) / (64 * X)), (unsigned)g.batch);
@@ -512,13 +648,13 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   }
   // Narrow outputs (N <= 32: triangular solves and updates with the s search
   // vectors) use 128 x 32 tiles; everything else 64 x 64.
-  const bool narrow = !g.tri && !g.op && g.N <= 32;
+  const bool narrow = !g.tri && g.N <= 32;
   const int BM = narrow ? 128 : 64, BN = narrow ? 32 : 64;
   long ntiles;
   const long tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   if (g.tri) ntiles = tm * (tm + 1) / 2;
   else ntiles = tm * tn;
-  dim3 grid((unsigned)ntiles, (unsigned)g.batch, (unsigned)g.ksplit);
+  dim3 grid((unsigned)ntiles, nbatch, (unsigned)g.ksplit);
 #define PHX_GEMM_LAUNCH(BMv, BNv, T)                                      \
   do {                                                                     \
     if (opa == 0 && opb == 0) PHX_LAUNCH((zgemm_kernel<R, 0, 0, BMv, BNv, T>), grid); \
@@ -527,13 +663,10 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
     else PHX_LAUNCH((zgemm_kernel<R, 1, 1, BMv, BNv, T>), grid);            \
   } while (0)
   // The lower-triangular tile grid (Hermitian rank-k update of the Cholesky trailing
-  // matrix) and the k-shared operator products are their own instantiations.
+  // matrix) is its own instantiation.
   if (g.tri) {
     if (opa == 0 && opb == 1) PHX_LAUNCH((zgemm_kernel<R, 0, 1, 64, 64, 1>), grid);
     else return (int)hipErrorInvalidValue;
-  } else if (g.op) {
-    if (g.op != 2 || opa != 0 || opb != 0 || !g.Ar) return (int)hipErrorInvalidValue;
-    PHX_LAUNCH((zgemm_kernel<R, 0, 0, 64, 64, 3>), grid);
   } else if (narrow) {
     PHX_GEMM_LAUNCH(128, 32, 0);
   } else {
@@ -543,7 +676,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   if (g.ksplit > 1) {
     long MN = (long)g.M * g.N;
     unsigned nb = (unsigned)std::min<long>((MN + 255) / 256, 1024);
-    hipLaunchKernelGGL((zgemm_reduce_kernel<R>), dim3(nb, g.batch), dim3(256), 0, st, g);
+    hipLaunchKernelGGL((zgemm_reduce_kernel<R>), dim3(nb, nbatch), dim3(256), 0, st, g);
   }
   return (int)hipGetLastError();
 }

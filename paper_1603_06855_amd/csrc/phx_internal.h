@@ -20,7 +20,6 @@ struct GemmArgs {
   C_t<R>* Cm; long ldc, sC; int dC;
   C_t<R> alpha, beta;
   int tri;
-  int op;  // 2: A is a real k-shared operator (Ar, stride 0), the matrix-free operator products
   const int* kact;  // optional device mask: batch item b is skipped when kact[b / kdiv] == 0
   int kdiv;
   int ksplit;
@@ -29,11 +28,38 @@ struct GemmArgs {
   const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
   hipEvent_t ev0, ev1;  // optional: recorded at the start and the end of the (single) kernel's execution
   int tiled;            // 1: always the LDS-tiled kernel, never the streaming few-RHS one
-  const R* Ar;          // op == 2: the operator is real (Ar, ld lda) and A is unused
+  // optional device list: only nbat * kdiv batch items run, grid item i being batch item
+  // bidx[i / kdiv] * kdiv + i % kdiv (tiled, tall-skinny and split-K reduction kernels)
+  const int* bidx;
+  int nbat;
 };
 
 template <typename R>
 int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);
+
+// Products of k-shared real operators with complex blocks, C = A B (the matrix-free
+// operator products in the paired basis), up to three of them in one launch.  A: M x K
+// real, column-major (ld lda), shared by every batch item of its product.  Batched form
+// (ncolk == 0): item b of the product has B at B + it * sB (K x N, ld ldb) and C at
+// C + it * sC (M x N, ld ldc), it = bidx[b] when bidx is given (the listed items only),
+// else b, for b < nb.  Column-listed form (ncolk > 0): one product over N = nb * ncolk
+// columns, column j being column j % ncolk of item bidx[j / ncolk], stored in B and C at
+// column bidx[j / ncolk] * ncolk + j % ncolk.
+struct OpSeg {
+  const double* A;
+  const double2* B;
+  double2* C;
+  long ldb, sB, ldc, sC;
+  int N, nb, ncolk;
+  const int* bidx;
+};
+struct OpArgs {
+  OpSeg seg[3];
+  int nseg, M, K;
+  long lda;
+  hipEvent_t ev0, ev1;  // optional: recorded at the kernel's start and end
+};
+int opgemm(const OpArgs& g, hipStream_t st);
 
 // Optional timing hook around kernel launches (class id, algorithmic flops/bytes).
 enum ProfClass {

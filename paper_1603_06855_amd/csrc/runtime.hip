@@ -548,6 +548,9 @@ struct Solver {
   int* kact;   // per k: 1 while a wanted band of that k-point has not met the tolerance
   int* kfar;   // per k: active and not yet near convergence (folded Rayleigh-Ritz)
   int* knear;  // per k: active and near convergence (explicit re-orthonormalisation, images recomputed)
+  int* lact;   // the k-points of kact, kfar and knear listed in ascending order (3 nk ints in all)
+  int* lfar;
+  int* lnear;
   int* fmap;   // per k: index of its preconditioner factor (NULL: its own)
   int nact;    // active k-points (host count of kact)
   int nfar, nnear;
@@ -563,18 +566,18 @@ struct Solver {
 template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
-          int ksplit = 1, C_t<R>* Cpart = nullptr, int op = 0, const int* kact = nullptr, int kdiv = 1,
-          int csplit = 0, int cgap = 0, const R* Ar = nullptr) {
+          int ksplit = 1, C_t<R>* Cpart = nullptr, const int* kact = nullptr, int kdiv = 1, int csplit = 0,
+          int cgap = 0, const int* bidx = nullptr, int nbat = 0) {
   GemmArgs<R> g{};
-  g.Ar = Ar;
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &g.ev0, &g.ev1);
     ctx->pk.set = false;
   }
   g.csplit = csplit;
   g.cgap = cgap;
-  g.op = op;
   g.kact = kact;
+  g.bidx = bidx;
+  g.nbat = nbat;
   g.kdiv = kdiv;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.lda = lda; g.sA = sA; g.dA = dA;
@@ -587,12 +590,12 @@ void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const 
 
 const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
 
-// K and Omega applied (FP64, matrix-free) to ncol columns of the S block of Big
-// starting at column c0; results to the same columns of the KS and OS blocks.
-// The strain blocks Y (Np x 6 ncol per k) and traces t (Np x ncol per k) of all k
-// are contiguous, so the two compliance products are single GEMMs over every k.
-// msk (device, per k; NULL: sv.kact) selects the k-points, nm counts them.
-void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = nullptr, int nm = -1) {
+// K and Omega applied (FP64, matrix-free, paired basis) to ncol columns of the S block of
+// Big starting at column c0; results to the same columns of the KS and OS blocks.
+// msk (device, per k; NULL: sv.kact) selects the k-points, nm counts them and lst lists
+// them (device, nm entries).
+void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = nullptr, int nm = -1,
+               const int* lst = nullptr) {
   phx_ctx* ctx = sv.ctx;
   Design& d = *sv.d;
   hipStream_t st = ctx->stream;
@@ -600,7 +603,9 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   if (!msk) {
     msk = sv.kact;
     nm = sv.nact;
+    lst = sv.lact;
   }
+  if (nm <= 0) return;
   double2* X = Big + c0 * n3;
   const double Np = d.Np, nk = nm;  // algorithmic work counts the selected k-points only
   PROF_BEGIN(PROF_APPLY);
@@ -608,34 +613,36 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
   KCHK(hipGetLastError());
-  // The compliance products with the real operators: 4 Np^2 flops per complex column (two
-  // real products); the operator (8 B per entry) read once, the block read and written
-  // once.  The deviatoric product runs one batch item per k-point (shared operator,
-  // stride 0) so that converged k-points are skipped; the volumetric one (a sixth of the
-  // columns, too narrow per k for a full tile) runs over all k-points as one product
-  // (columns of converged k-points are computed from their last strains and not used).
-  const int ny = 6 * ncol, nt = ncol * sv.nk;
-  const long sy = (long)d.Np * ny;
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * ny * nk, 8.0 * Np * Np + 32.0 * Np * ny * nk);
-  gemm<double>(ctx, 0, 0, d.Np, ny, d.Np, sv.nk, nullptr, d.Np, 0, 1, sv.Y, d.Np, sy, 1, sv.Zy, d.Np, sy, ONE, ZERO, 1,
-               nullptr, 2, msk, 1, 0, 0, d.Br);
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * nt, 8.0 * Np * Np + 32.0 * Np * nt);
-  gemm<double>(ctx, 0, 0, d.Np, nt, d.Np, 1, nullptr, d.Np, 0, 1, sv.Tr, d.Np, 0, 1, sv.Zt, d.Np, 0, ONE, ZERO, 1,
-               nullptr, 2, nullptr, 1, 0, 0, d.Dr);
+  // The three real operator products in one launch, over the listed k-points: the
+  // deviatoric compliance Bm times the strain channels, Omega_s times the columns, and the
+  // volumetric compliance Dm times the traces (one column per vector: the traces of the
+  // listed k-points form one product).  4 Np^2 flops per complex column (two real
+  // products); each operator (8 B per entry) read once, each block read and written once.
+  const int ny = 6 * ncol;
+  OpArgs a{};
+  a.nseg = 3;
+  a.M = a.K = d.Np;
+  a.lda = d.Np;
+  a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, (long)d.Np * ny, (long)d.Np, (long)d.Np * ny, ny, nm, 0, lst};
+  a.seg[1] = OpSeg{d.Or, X, Big + (2 * m + c0) * n3, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 3 * ncol, nm, 0, lst};
+  a.seg[2] = OpSeg{d.Dr, sv.Tr, sv.Zt, (long)d.Np, 0, (long)d.Np, 0, 0, nm, ncol, lst};
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 10.0 * ncol * nk, 3.0 * 8.0 * Np * Np + 32.0 * Np * 10.0 * ncol * nk);
+  if (ctx->pk.set) {
+    ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &a.ev0, &a.ev1);
+    ctx->pk.set = false;
+  }
+  KCHK(opgemm(a, st));
   PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N);
   PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
   KCHK(hipGetLastError());
-  // Omega X: the real Omega_s acting on the Np x (3 ncol) view of the columns.
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 3 * ncol * nk, 8.0 * Np * Np + 32.0 * Np * 3 * ncol * nk);
-  gemm<double>(ctx, 0, 0, d.Np, 3 * ncol, d.Np, sv.nk, nullptr, d.Np, 0, 1, X, d.Np, sv.sBig, 1,
-               Big + (2 * m + c0) * n3, d.Np, sv.sBig, ONE, ZERO, 1, nullptr, 2, msk, 1, 0, 0, d.Or);
 }
 
 // The k-point selection of one eigensolver step: a device mask and its host count.
 struct Sel {
-  const int* d;
-  int n;
+  const int* d;  // per-k mask
+  int n;         // its count
+  const int* l;  // the selected k-points, listed (n entries)
 };
 
 void gram(Solver& sv, double2* Big, int block, Sel k) {
@@ -644,7 +651,7 @@ void gram(Solver& sv, double2* Big, int block, Sel k) {
   const long n3 = sv.n3, m = sv.m;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(sv.ctx, 1, 0, m, m, n3, sv.nk, Big, n3, sv.sBig, 1, Big + block * m * n3, n3, sv.sBig, 1, sv.G, m,
-               m * m, ONE, ZERO, sv.ksplit, sv.Gpart, 0, k.d, 1);
+               m * m, ONE, ZERO, sv.ksplit, sv.Gpart, k.d, 1, 0, 0, k.l, k.n);
   PROF_END(PROF_GRAM, 8.0 * m * m * 3.0 * sv.d->N * k.n, 16.0 * 2 * m * 3.0 * sv.d->N * k.n);
 }
 
@@ -659,12 +666,12 @@ void gram(Solver& sv, double2* Big, int block, Sel k) {
 // workgroups share a row, so reading and writing the same array is safe.  Frozen
 // k-points are skipped and keep their basis.
 void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, long sC, long c0, int split,
-                     const int* msk) {
+                     Sel k) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
   if (ncol > 64 || K > 64) fail(ctx, PHX_EINVAL, "in-place basis update needs at most 64 columns");
   gemm<double>(ctx, 0, 0, n3, ncol, K, 3 * sv.nk, sv.Big + a0 * n3, n3, n3 * m, 1, C, m, sC, 3, sv.Big + c0 * n3, n3,
-               n3 * m, ONE, ZERO, 1, nullptr, 0, msk, 3, split, split);
+               n3 * m, ONE, ZERO, 1, nullptr, k.d, 3, split, split, k.l, k.n);
 }
 
 void cholqr(Solver& sv, Sel k) {
@@ -678,7 +685,7 @@ void cholqr(Solver& sv, Sel k) {
   // [S | KS | OS] <- [S | KS | OS] C0 for every k: batch 3 nk, C0 shared by the three blocks
   // (in place: see update_in_place)
   PROF_BEGIN(PROF_UPDATE);
-  update_in_place(sv, 0, m, m, sv.C0, m * m, 0, 0, k.d);
+  update_in_place(sv, 0, m, m, sv.C0, m * m, 0, 0, k);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * m * m * k.n, 16.0 * 2 * 3 * 3.0 * sv.d->N * m * k.n);
 }
 
@@ -694,8 +701,8 @@ void rayleigh_ritz(Solver& sv, Sel k) {
   PROF_BEGIN(PROF_UPDATE);
   // In place (see update_in_place), X first: it reads the whole old basis and writes only
   // X, which the product for P does not read; P then reads W and the old P and writes P.
-  update_in_place(sv, 0, s, m, sv.Cr, m * s, 0, 0, k.d);
-  update_in_place(sv, s, s, m - s, sv.Cr + s, m * s, 2 * s, 0, k.d);
+  update_in_place(sv, 0, s, m, sv.Cr, m * s, 0, 0, k);
+  update_in_place(sv, s, s, m - s, sv.Cr + s, m * s, 2 * s, 0, k);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * (2.0 * m - s) * s * k.n,
            16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * k.n);
 }
@@ -709,7 +716,7 @@ void rayleigh_ritz_fused(Solver& sv, Sel k) {
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   PROF_BEGIN(PROF_GRAM);
   gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
-               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, 0, k.d, 1);
+               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, k.d, 1, 0, 0, k.l, k.n);
   PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * k.n, 16.0 * 3 * m * 3.0 * sv.d->N * k.n);
   PROF_BEGIN(PROF_SMALL);
   // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
@@ -719,7 +726,7 @@ void rayleigh_ritz_fused(Solver& sv, Sel k) {
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
-  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s, k.d);
+  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s, k);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * k.n, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * k.n);
 }
 
@@ -912,6 +919,20 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   std::vector<char> near_k(nk, 0);
   sv.kfar = dbuf<int>(ctx, "kfar", nk);
   sv.knear = dbuf<int>(ctx, "knear", nk);
+  sv.lact = dbuf<int>(ctx, "klist", 3L * nk);
+  sv.lfar = sv.lact + nk;
+  sv.lnear = sv.lact + 2 * nk;
+  // the lists of the active, far and near k-points, from the host masks
+  std::vector<int> lists_h(3L * nk);
+  auto upload_lists = [&](const std::vector<int>& a, const std::vector<int>& f, const std::vector<int>& n) {
+    int na = 0, nf = 0, nn = 0;
+    for (int k = 0; k < nk; ++k) {
+      if (a[k]) lists_h[na++] = k;
+      if (f[k]) lists_h[nk + nf++] = k;
+      if (n[k]) lists_h[2 * nk + nn++] = k;
+    }
+    HIPCHK(hipMemcpyAsync(sv.lact, lists_h.data(), 3L * nk * sizeof(int), hipMemcpyHostToDevice, st));
+  };
   sv.kjac = dbuf<int>(ctx, "kjac", nk);
   sv.kpen = dbuf<int>(ctx, "kpen", nk);
   for (int k = 0; k < nk; ++k) {
@@ -923,6 +944,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(sv.kjac, jac_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(sv.kpen, penm_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+  upload_lists(act_h, far_h, near_h);
   sv.nact = sv.nfar = nk;
   sv.nnear = 0;
   sv.njac = ctx->opt.precond == 0 ? 0 : nk;
@@ -947,7 +969,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   out.converged = false;
   int it = 0;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
-    const Sel all{sv.kact, sv.nact}, far{sv.kfar, sv.nfar}, nearsel{sv.knear, sv.nnear};
+    const Sel all{sv.kact, sv.nact, sv.lact}, far{sv.kfar, sv.nfar, sv.lfar}, nearsel{sv.knear, sv.nnear, sv.lnear};
     // rr_fused 2: a k-point far from convergence takes both orthonormalisations in the small
     // space (one Gram product and one basis update per iteration); otherwise one explicit
     // Omega-CholQR of the basis first
@@ -977,8 +999,8 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     // recomputed from the vectors every iteration (with FP64 unit roundoff: residual below
     // 1e-13/tol, i.e. only the last iterations of an FP64-tolerance solve).
     if (sv.nnear > 0) {
-      apply_ops(sv, sv.Big, 0, s, sv.knear, sv.nnear);
-      apply_ops(sv, sv.Big, 2 * s, s, sv.knear, sv.nnear);
+      apply_ops(sv, sv.Big, 0, s, sv.knear, sv.nnear, sv.lnear);
+      apply_ops(sv, sv.Big, 2 * s, s, sv.knear, sv.nnear, sv.lnear);
     }
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
@@ -1085,6 +1107,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
         HIPCHK(hipMemcpyAsync(sv.knear, near_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(sv.kjac, jac_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(sv.kpen, penm_h.data(), nk * sizeof(int), hipMemcpyHostToDevice, st));
+        upload_lists(act_h, far_h, near_h);
       }
       sv.nact = na;
       sv.nfar = nf;
