@@ -237,8 +237,10 @@ __device__ __forceinline__ long op_tiles(const OpSeg& s, int tm) {
   return (long)tm * tn * (s.ncolk > 0 ? 1 : s.nb);
 }
 
+template <int KS>
 __global__ __launch_bounds__(256, 3) void opgemm_kernel(OpArgs g) {
-  constexpr int BM = 64, BN = 64, KS = 8;
+  constexpr int BM = 64, BN = 64;
+  constexpr int RA = KS / 8, RB = KS / 4;  // per thread: RA row pairs of A, RB consecutive k of B
   __shared__ double As[KS][BM + 4], Bsr[KS][BN + 4], Bsi[KS][BN + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
@@ -274,34 +276,43 @@ __global__ __launch_bounds__(256, 3) void opgemm_kernel(OpArgs g) {
     B += it * S.sB;
     Cb += it * S.sC;
   }
-  // the stored column of output column j of this product
-  auto colof = [&](int j) -> long { return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.ncolk + j % S.ncolk : j; };
+  // where column j of this product is stored in B and in C
+  auto boff = [&](int j) -> long {
+    return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.sB + (long)(j % S.ncolk) * S.ldb : (long)j * S.ldb;
+  };
+  auto coff = [&](int j) -> long {
+    return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.sC + (long)(j % S.ncolk) * S.ldc : (long)j * S.ldc;
+  };
 
-  // staging: A 64 x 8 (two consecutive rows per thread), B 8 x 64 (two consecutive k of one
-  // column per thread); the thread's B column is fixed for the whole tile
+  // staging: A 64 x KS (RA pairs of consecutive rows per thread, k = ak + 8 r), B KS x 64
+  // (RB consecutive k of one column per thread); the thread's B column is fixed for the tile
   const int ai = (tid % 32) * 2, ak = tid / 32;
-  const int bk = (tid % 4) * 2, bj = tid / 4;
+  const int bk = (tid % 4) * RB, bj = tid / 4;
   const bool bvalid = col0 + bj < ncols;
-  const double2* bcol = B + (bvalid ? colof(col0 + bj) : 0) * S.ldb;
-  double ra[2];
-  double2 rb[2];
+  const double2* bcol = B + (bvalid ? boff(col0 + bj) : 0);
+  double ra[2 * RA];
+  double2 rb[RB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = row0 + ai + q, k = k0 + ak;
-      ra[q] = (i < g.M && k < g.K) ? S.A[i + (long)k * g.lda] : 0.0;
-    }
+    for (int r = 0; r < RA; ++r)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < 2; ++q) {
+        const int i = row0 + ai + q, k = k0 + ak + 8 * r;
+        ra[2 * r + q] = (i < g.M && k < g.K) ? S.A[i + (long)k * g.lda] : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
       const int k = k0 + bk + q;
       rb[q] = (bvalid && k < g.K) ? bcol[k] : make_double2(0, 0);
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) As[ak][ai + q] = ra[q];
+    for (int r = 0; r < RA; ++r)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < 2; ++q) As[ak + 8 * r][ai + q] = ra[2 * r + q];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
       Bsr[bk + q][bj] = rb[q].x;
       Bsi[bk + q][bj] = rb[q].y;
     }
@@ -352,7 +363,7 @@ __global__ __launch_bounds__(256, 3) void opgemm_kernel(OpArgs g) {
     for (int r = 0; r < 4; ++r) {
       const int col = col0 + wc * 32 + y * 16 + (lane >> 4) + 4 * r;
       if (col >= ncols) continue;
-      double2* cc = Cb + colof(col) * S.ldc;
+      double2* cc = Cb + coff(col);
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         const int row = row0 + wr * 32 + x * 16 + (lane & 15);
@@ -373,8 +384,14 @@ int opgemm(const OpArgs& g, hipStream_t st) {
   }
   if (total == 0) return 0;
   if (total > 0x7fffffffL) return (int)hipErrorInvalidValue;
-  if (g.ev0) hipExtLaunchKernelGGL(opgemm_kernel, dim3((unsigned)total), dim3(256), 0, st, g.ev0, g.ev1, 0, g);
-  else hipLaunchKernelGGL(opgemm_kernel, dim3((unsigned)total), dim3(256), 0, st, g);
+#define PHX_OP_LAUNCH(KSv)                                                                              \
+  do {                                                                                                   \
+    if (g.ev0)                                                                                           \
+      hipExtLaunchKernelGGL(opgemm_kernel<KSv>, dim3((unsigned)total), dim3(256), 0, st, g.ev0, g.ev1, 0, g); \
+    else hipLaunchKernelGGL(opgemm_kernel<KSv>, dim3((unsigned)total), dim3(256), 0, st, g);           \
+  } while (0)
+  PHX_OP_LAUNCH(8);  // a 16-deep stage measured slower
+#undef PHX_OP_LAUNCH
   return (int)hipGetLastError();
 }
 

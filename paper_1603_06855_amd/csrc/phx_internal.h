@@ -42,9 +42,10 @@ int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);
 // real, column-major (ld lda), shared by every batch item of its product.  Batched form
 // (ncolk == 0): item b of the product has B at B + it * sB (K x N, ld ldb) and C at
 // C + it * sC (M x N, ld ldc), it = bidx[b] when bidx is given (the listed items only),
-// else b, for b < nb.  Column-listed form (ncolk > 0): one product over N = nb * ncolk
-// columns, column j being column j % ncolk of item bidx[j / ncolk], stored in B and C at
-// column bidx[j / ncolk] * ncolk + j % ncolk.
+// else b, for b < nb.  Column-listed form (ncolk > 0): one product over the nb * ncolk
+// columns of the listed items packed side by side (so the 64-column tiles are full),
+// column j being column j % ncolk of item it = bidx[j / ncolk], stored in B at
+// it * sB + (j % ncolk) * ldb and in C at it * sC + (j % ncolk) * ldc.
 struct OpSeg {
   const double* A;
   const double2* B;

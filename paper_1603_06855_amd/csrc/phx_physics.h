@@ -28,15 +28,19 @@ template <typename R>
 void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, const double* Kv, int N, int Np,
                      int nk, double c2, const double* sigma, C_t<R>* A, long sA, int full, hipStream_t st);
 // kact (optional, device): per-k mask; k-points with kact[k] == 0 are skipped.
+// pairN = 0 (strain only): Mandel strain (Np x 6 ncol per k) and trace (Np x ncol per k).
 // pairN = N > 0: the displacement columns, the strain channels, the stresses and the
-// forces are all in the paired basis of launch_realify (each wave n_p with -n_p).
+// forces are all in the paired basis of launch_realify (each wave n_p with -n_p), and the
+// strain is split into five deviatoric channels (Np x 5 ncol per k) and the volumetric one
+// (Np x ncol per k); the force kernel takes only this form (pairN = N required).
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
                    double2* tr, hipStream_t st, const int* kact = nullptr, int pairN = 0);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
                   double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr, int pairN = 0);
 // Mr = Re(U^H Mc U), U the unitary pairing each wave n_p with -n_p (see realify_kernel):
 // real symmetric for the Fourier matrix of a real field and for its inverse.
-void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st);
+// Mc2 (optional): the same for Mc + Mc2.
+void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st, const double2* Mc2 = nullptr);
 void launch_zero(double2* X, long n, hipStream_t st);
 // pairN = N > 0: the unit columns in the paired basis (launch_realify); Np: rows per component.
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st, int Np,

@@ -255,11 +255,25 @@ __device__ __forceinline__ void from_pair(double2& a, double2& b) {
   b = w;
 }
 
-// Mandel strain (6 channels, Np x 6 ncol per k) and trace (Np x ncol per k) of ncol
-// displacement columns.  pairN = N > 0: the columns X and the outputs are all in the
-// paired basis (to_pair): one thread takes both waves of a pair, returns them to plane
-// waves, forms their strains and pairs the channels again (padding rows from N on are
-// taken as they are).
+// Strain channels of ncol displacement columns, two formats:
+// pairN = 0: Mandel strain (6 channels, Np x 6 ncol per k) and trace K . x (Np x ncol per k),
+// for the compliance Bm on all six channels plus Dm on the trace (the adjoint's fields).
+// pairN = N > 0: everything in the paired basis (to_pair), and the strain in the orthonormal
+// basis that separates the compliance's two parts: the volumetric channel
+// t0 = (e11 + e22 + e33)/sqrt3 (Np x ncol per k, for Phi_vol^-1 = Dm + Bm) and five deviatoric
+// channels (e11 - e22)/sqrt2, (e11 + e22 - 2 e33)/sqrt6 and the three Mandel shears
+// (Np x 5 ncol per k, for Bm = Phi_dev^-1): six operator products per vector instead of
+// seven.  One thread takes both waves of a pair, returns them to plane waves, forms their
+// strains and pairs the channels again (padding rows from N on are taken as they are).
+__device__ __forceinline__ void dev_channels(const double2 (&y)[6], double2 t, double2 (&c)[5], double2& t0) {
+  const double r2 = 0.70710678118654752440, r3 = 0.57735026918962576451, r6 = 0.40824829046386301637;
+  t0 = cscale(t, r3);
+  c[0] = cscale(csub(y[0], y[1]), r2);
+  c[1] = cscale(csub(cadd(y[0], y[1]), cscale(y[2], 2.0)), r6);
+  c[2] = y[3];
+  c[3] = y[4];
+  c[4] = y[5];
+}
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
                               double2* Y, double2* tr, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,13 +283,22 @@ __global__ void strain_kernel(const double2* X, long ldx, long sX, const double*
   const int c = (pairN - 1) / 2;
   if (pairN > 0 && p > c && p < pairN) return;  // the partner thread writes this row
   const double2* x = X + (long)k * sX + (long)j * ldx;
-  double2* y = Y + (long)k * Np * 6 * ncol + (long)(6 * j) * Np;
+  const int nch = pairN > 0 ? 5 : 6;
+  double2* y = Y + (long)k * Np * nch * ncol + (long)(nch * j) * Np;
   double2* tp = tr + (long)k * Np * ncol + (long)j * Np;
   double2 ya[6], ta;
-  if (pairN == 0 || p >= pairN || p == c) {
+  if (pairN == 0) {
     wave_strain(Kv + ((long)k * Np + p) * 3, x[p], x[Np + p], x[2 * Np + p], ya, ta);
     for (int ch = 0; ch < 6; ++ch) y[ch * Np + p] = ya[ch];
     tp[p] = ta;
+    return;
+  }
+  double2 ca[5], t0a;
+  if (p >= pairN || p == c) {
+    wave_strain(Kv + ((long)k * Np + p) * 3, x[p], x[Np + p], x[2 * Np + p], ya, ta);
+    dev_channels(ya, ta, ca, t0a);
+    for (int ch = 0; ch < 5; ++ch) y[ch * Np + p] = ca[ch];
+    tp[p] = t0a;
     return;
   }
   const int pb = pairN - 1 - p;
@@ -285,23 +308,43 @@ __global__ void strain_kernel(const double2* X, long ldx, long sX, const double*
     xb[d] = x[d * Np + pb];
     from_pair(xa[d], xb[d]);
   }
-  double2 yb[6], tb;
+  double2 yb[6], tb, cb[5], t0b;
   wave_strain(Kv + ((long)k * Np + p) * 3, xa[0], xa[1], xa[2], ya, ta);
   wave_strain(Kv + ((long)k * Np + pb) * 3, xb[0], xb[1], xb[2], yb, tb);
-  for (int ch = 0; ch < 6; ++ch) {
-    to_pair(ya[ch], yb[ch]);
-    y[ch * Np + p] = ya[ch];
-    y[ch * Np + pb] = yb[ch];
+  dev_channels(ya, ta, ca, t0a);
+  dev_channels(yb, tb, cb, t0b);
+  for (int ch = 0; ch < 5; ++ch) {
+    to_pair(ca[ch], cb[ch]);
+    y[ch * Np + p] = ca[ch];
+    y[ch * Np + pb] = cb[ch];
   }
-  to_pair(ta, tb);
-  tp[p] = ta;
-  tp[pb] = tb;
+  to_pair(t0a, t0b);
+  tp[p] = t0a;
+  tp[pb] = t0b;
 }
 
-// Mandel stress coefficients S = Zy + (Zt / 3) [1,1,1,0,0,0] and the force
-// (2 pi V)^2 B(K_p)^T S_p.  KX: 3Np x ncol per k (ld ldk, k-stride sK).  pairN = N > 0:
-// Zy, Zt and KX are in the paired basis (to_pair); the stresses of a pair go back to plane
-// waves, and their forces are paired again.
+// The force (2 pi V)^2 B(K_p)^T S_p of the stress in the paired basis and the channel format
+// of strain_kernel's pairN > 0: Zy holds the five deviatoric channels (Bm times the strain
+// channels, Np x 5 ncol per k) and Zt the volumetric one (Np x ncol per k); the Mandel
+// stress is S_diag = z0 u0 + z1 u1 + z2 u2 (u0 = (1,1,1)/sqrt3, u1 = (1,-1,0)/sqrt2,
+// u2 = (1,1,-2)/sqrt6) and the three shears.  KX: 3Np x ncol per k (ld ldk, k-stride sK),
+// paired basis.  One thread takes both waves of a pair (p < c); padding rows from N on,
+// and the centre, alone.
+__device__ __forceinline__ void force_of(const double* K, const double2 (&z)[5], double2 zt, double c2,
+                                         double2 (&o)[3]) {
+  const double r2 = 0.70710678118654752440, r3 = 0.57735026918962576451, r6 = 0.40824829046386301637;
+  const double2 v = cscale(zt, r3), a = cscale(z[0], r2), b = cscale(z[1], r6);
+  double2 S[6];
+  S[0] = cadd(cadd(v, a), b);
+  S[1] = cadd(csub(v, a), b);
+  S[2] = csub(v, cscale(b, 2.0));
+  S[3] = z[2];
+  S[4] = z[3];
+  S[5] = z[4];
+  const double2 zero = make_double2(0, 0);
+  wave_force(K, S, zero, c2, o);
+}
+
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
                              double2* KX, long ldk, long sK, const int* kact, int pairN) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,27 +352,27 @@ __global__ void force_kernel(const double2* Zy, const double2* Zt, const double*
   const int k = blockIdx.z;
   if (p >= Np || (kact && !kact[k])) return;
   const int c = (pairN - 1) / 2;
-  if (pairN > 0 && p > c && p < pairN) return;
-  const double2* z = Zy + (long)k * Np * 6 * ncol + (long)(6 * j) * Np;
+  if (p > c && p < pairN) return;  // the partner thread writes this row
+  const double2* z = Zy + (long)k * Np * 5 * ncol + (long)(5 * j) * Np;
   const double2* zt = Zt + (long)k * Np * ncol + (long)j * Np;
   double2* o = KX + (long)k * sK + (long)j * ldk;
-  double2 za[6], fa[3];
-  for (int ch = 0; ch < 6; ++ch) za[ch] = z[ch * Np + p];
-  if (pairN == 0 || p >= pairN || p == c) {
-    wave_force(Kv + ((long)k * Np + p) * 3, za, zt[p], c2, fa);
+  double2 za[5], fa[3];
+  for (int ch = 0; ch < 5; ++ch) za[ch] = z[ch * Np + p];
+  if (p >= pairN || p == c) {
+    force_of(Kv + ((long)k * Np + p) * 3, za, zt[p], c2, fa);
     for (int d = 0; d < 3; ++d) o[d * Np + p] = fa[d];
     return;
   }
   const int pb = pairN - 1 - p;
-  double2 zq[6], fb[3];
-  for (int ch = 0; ch < 6; ++ch) {
-    zq[ch] = z[ch * Np + pb];
-    from_pair(za[ch], zq[ch]);
+  double2 zb[5], fb[3];
+  for (int ch = 0; ch < 5; ++ch) {
+    zb[ch] = z[ch * Np + pb];
+    from_pair(za[ch], zb[ch]);
   }
   double2 ta = zt[p], tb = zt[pb];
   from_pair(ta, tb);
-  wave_force(Kv + ((long)k * Np + p) * 3, za, ta, c2, fa);
-  wave_force(Kv + ((long)k * Np + pb) * 3, zq, tb, c2, fb);
+  force_of(Kv + ((long)k * Np + p) * 3, za, ta, c2, fa);
+  force_of(Kv + ((long)k * Np + pb) * 3, zb, tb, c2, fb);
   for (int d = 0; d < 3; ++d) {
     to_pair(fa[d], fb[d]);
     o[d * Np + p] = fa[d];
@@ -341,13 +384,14 @@ __global__ void force_kernel(const double2* Zy, const double2* Zt, const double*
 // matrix of a real field on the waves n_p, n_{N-1-p} = -n_p, or its inverse) in the basis
 // u_p = (e_p + e_pb)/sqrt2, u_pb = i (e_p - e_pb)/sqrt2 (p < c = (N-1)/2, pb = N-1-p),
 // u_c = e_c, where it is real symmetric: Mr[a][b] = Re(u_a^H Mc u_b) (the imaginary part is
-// rounding).  Rows and columns from N on (the padding) are copied.  Column-major.
-__global__ void realify_kernel(const double2* Mc, int N, int Np, double* Mr) {
+// rounding).  Rows and columns from N on (the padding) are copied.  Column-major.  Mc2
+// (optional): the same for Mc + Mc2.
+__global__ void realify_kernel(const double2* Mc, const double2* Mc2, int N, int Np, double* Mr) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)Np * Np) return;
   const int a = (int)(e % Np), b = (int)(e / Np);
   if (a >= N || b >= N) {
-    Mr[e] = Mc[e].x;
+    Mr[e] = Mc[e].x + (Mc2 ? Mc2[e].x : 0.0);
     return;
   }
   const int c = (N - 1) / 2;
@@ -362,7 +406,10 @@ __global__ void realify_kernel(const double2* Mc, int N, int Np, double* Mr) {
   double2 aa, ba, ab, bb;
   basis(a, pa, qa, aa, ba);
   basis(b, pb, qb, ab, bb);
-  auto m = [&](int r, int col) { return Mc[r + (long)col * Np]; };
+  auto m = [&](int r, int col) {
+    const long i = r + (long)col * Np;
+    return Mc2 ? cadd(Mc[i], Mc2[i]) : Mc[i];
+  };
   double2 v = cmul(cmulc(ab, aa), m(pa, pb));  // conj(al_a) al_b M[pa][pb]
   if (qb != pb) v = cadd(v, cmul(cmulc(bb, aa), m(pa, qb)));
   if (qa != pa) v = cadd(v, cmul(cmulc(ab, ba), m(qa, pb)));
@@ -763,9 +810,9 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
                      ldk, sK, kact, pairN);
 }
 
-void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st) {
+void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st, const double2* Mc2) {
   const long n = (long)Np * Np;
-  hipLaunchKernelGGL(realify_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Mc, N, Np, Mr);
+  hipLaunchKernelGGL(realify_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Mc, Mc2, N, Np, Mr);
 }
 
 void launch_zero(double2* X, long n, hipStream_t st) {

@@ -399,9 +399,9 @@ struct Design {
   double2* Os = nullptr;   // Np x Np
   double2* Dm = nullptr;   // Pv^{-1} - Pd^{-1}
   double2* Bm = nullptr;   // Pd^{-1}
-  // Dm, Bm and Os in the basis pairing each wave n_p with -n_p (launch_realify), where they
-  // are real: the eigensolver's vectors live in that basis
-  double* Dr = nullptr;
+  // Phi_vol^-1 = Dm + Bm, Bm = Phi_dev^-1 and Os in the basis pairing each wave n_p with -n_p
+  // (launch_realify), where they are real: the eigensolver's vectors live in that basis
+  double* Vr = nullptr;
   double* Br = nullptr;
   double* Or = nullptr;
 };
@@ -508,10 +508,10 @@ void setup_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, co
   d.Bm = inv + NN;
   // the operators in the basis where they are real: each product with a complex block takes
   // two real products instead of three
-  d.Dr = dbuf<double>(ctx, tag + "opr", 3 * NN);
-  d.Br = d.Dr + NN;
-  d.Or = d.Dr + 2 * NN;
-  launch_realify(d.Dm, d.N, d.Np, d.Dr, st);
+  d.Vr = dbuf<double>(ctx, tag + "opr", 3 * NN);
+  d.Br = d.Vr + NN;
+  d.Or = d.Vr + 2 * NN;
+  launch_realify(d.Dm, d.N, d.Np, d.Vr, st, d.Bm);
   launch_realify(d.Bm, d.N, d.Np, d.Br, st);
   launch_realify(d.Os, d.N, d.Np, d.Or, st);
   KCHK(hipGetLastError());
@@ -611,22 +611,24 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   PROF_BEGIN(PROF_APPLY);
   // strain channels of the paired-basis columns, in the same basis
   launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N);
-  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 7.0) * Np);
+  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 6.0) * Np);
   KCHK(hipGetLastError());
   // The three real operator products in one launch, over the listed k-points: the
-  // deviatoric compliance Bm times the strain channels, Omega_s times the columns, and the
-  // volumetric compliance Dm times the traces (one column per vector: the traces of the
-  // listed k-points form one product).  4 Np^2 flops per complex column (two real
-  // products); each operator (8 B per entry) read once, each block read and written once.
-  const int ny = 6 * ncol;
+  // deviatoric compliance Bm times the five deviatoric strain channels, Omega_s times the
+  // columns, and the volumetric compliance Phi_vol^-1 times the volumetric channel (one
+  // column per vector: those of the listed k-points form one product); nine operator
+  // columns per vector.  4 Np^2 flops per complex column (two real products); each
+  // operator (8 B per entry) read once, each block read and written once.
+  const int ny = 5 * ncol;
   OpArgs a{};
   a.nseg = 3;
   a.M = a.K = d.Np;
   a.lda = d.Np;
-  a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, (long)d.Np * ny, (long)d.Np, (long)d.Np * ny, ny, nm, 0, lst};
-  a.seg[1] = OpSeg{d.Or, X, Big + (2 * m + c0) * n3, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 3 * ncol, nm, 0, lst};
-  a.seg[2] = OpSeg{d.Dr, sv.Tr, sv.Zt, (long)d.Np, 0, (long)d.Np, 0, 0, nm, ncol, lst};
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 10.0 * ncol * nk, 3.0 * 8.0 * Np * Np + 32.0 * Np * 10.0 * ncol * nk);
+  // (each product over the listed k-points' columns packed side by side)
+  a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, (long)d.Np * ny, (long)d.Np, (long)d.Np * ny, 0, nm, ny, lst};
+  a.seg[1] = OpSeg{d.Or, X, Big + (2 * m + c0) * n3, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nm, 3 * ncol, lst};
+  a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, (long)d.Np * ncol, (long)d.Np, (long)d.Np * ncol, 0, nm, ncol, lst};
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 9.0 * ncol * nk, 3.0 * 8.0 * Np * Np + 32.0 * Np * 9.0 * ncol * nk);
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &a.ev0, &a.ev1);
     ctx->pk.set = false;
@@ -634,7 +636,7 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   KCHK(opgemm(a, st));
   PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N);
-  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (7.0 + 3.0) * Np);
+  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (6.0 + 3.0) * Np);
   KCHK(hipGetLastError());
 }
 
