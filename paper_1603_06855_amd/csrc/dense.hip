@@ -277,11 +277,16 @@ __global__ __launch_bounds__(256, 3) void opgemm_kernel(OpArgs g) {
     Cb += it * S.sC;
   }
   // where column j of this product is stored in B and in C
+  const int kd = S.kdiv > 0 ? S.kdiv : 1;
   auto boff = [&](int j) -> long {
-    return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.sB + (long)(j % S.ncolk) * S.ldb : (long)j * S.ldb;
+    if (S.ncolk == 0) return (long)j * S.ldb;
+    const int e = S.bidx[j / S.ncolk];
+    return (long)(e / kd) * S.sB + (long)((e % kd) * S.ncolk + j % S.ncolk) * S.ldb;
   };
   auto coff = [&](int j) -> long {
-    return S.ncolk > 0 ? (long)S.bidx[j / S.ncolk] * S.sC + (long)(j % S.ncolk) * S.ldc : (long)j * S.ldc;
+    if (S.ncolk == 0) return (long)j * S.ldc;
+    const int e = S.bidx[j / S.ncolk];
+    return (long)(e / kd) * S.sC + (long)((e % kd) * S.ncolk + j % S.ncolk) * S.ldc;
   };
 
   // staging: A 64 x KS (RA pairs of consecutive rows per thread, k = ak + 8 r), B KS x 64

@@ -43,9 +43,10 @@ int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);
 // (ncolk == 0): item b of the product has B at B + it * sB (K x N, ld ldb) and C at
 // C + it * sC (M x N, ld ldc), it = bidx[b] when bidx is given (the listed items only),
 // else b, for b < nb.  Column-listed form (ncolk > 0): one product over the nb * ncolk
-// columns of the listed items packed side by side (so the 64-column tiles are full),
-// column j being column j % ncolk of item it = bidx[j / ncolk], stored in B at
-// it * sB + (j % ncolk) * ldb and in C at it * sC + (j % ncolk) * ldc.
+// columns of the listed entries packed side by side (so the 64-column tiles are full),
+// column j being column q = j % ncolk of entry e = bidx[j / ncolk], which is group
+// g = e % kdiv of item it = e / kdiv (kdiv >= 1): stored in B at
+// it * sB + (g * ncolk + q) * ldb and in C at it * sC + (g * ncolk + q) * ldc.
 struct OpSeg {
   const double* A;
   const double2* B;
@@ -53,6 +54,7 @@ struct OpSeg {
   long ldb, sB, ldc, sC;
   int N, nb, ncolk;
   const int* bidx;
+  int kdiv;
 };
 struct OpArgs {
   OpSeg seg[3];

@@ -33,10 +33,12 @@ void launch_assemble(const double2* Dm, const double2* Bm, const double2* Os, co
 // forces are all in the paired basis of launch_realify (each wave n_p with -n_p), and the
 // strain is split into five deviatoric channels (Np x 5 ncol per k) and the volumetric one
 // (Np x ncol per k); the force kernel takes only this form (pairN = N required).
+// cmask (optional, device, per k * ncol + j): columns whose entry is 0 are skipped.
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st, const int* kact = nullptr, int pairN = 0);
+                   double2* tr, hipStream_t st, const int* kact = nullptr, int pairN = 0, const int* cmask = nullptr);
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact = nullptr, int pairN = 0);
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact, int pairN,
+                  const int* cmask = nullptr);
 // Mr = Re(U^H Mc U), U the unitary pairing each wave n_p with -n_p (see realify_kernel):
 // real symmetric for the Fourier matrix of a real field and for its inverse.
 // Mc2 (optional): the same for Mc + Mc2.

@@ -275,11 +275,11 @@ __device__ __forceinline__ void dev_channels(const double2 (&y)[6], double2 t, d
   c[4] = y[5];
 }
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
-                              double2* Y, double2* tr, const int* kact, int pairN) {
+                              double2* Y, double2* tr, const int* kact, int pairN, const int* cmask) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np || (kact && !kact[k])) return;
+  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const int c = (pairN - 1) / 2;
   if (pairN > 0 && p > c && p < pairN) return;  // the partner thread writes this row
   const double2* x = X + (long)k * sX + (long)j * ldx;
@@ -329,7 +329,8 @@ __global__ void strain_kernel(const double2* X, long ldx, long sX, const double*
 // stress is S_diag = z0 u0 + z1 u1 + z2 u2 (u0 = (1,1,1)/sqrt3, u1 = (1,-1,0)/sqrt2,
 // u2 = (1,1,-2)/sqrt6) and the three shears.  KX: 3Np x ncol per k (ld ldk, k-stride sK),
 // paired basis.  One thread takes both waves of a pair (p < c); padding rows from N on,
-// and the centre, alone.
+// and the centre, alone.  cmask (optional, per k * ncol + j): columns whose entry is 0 are
+// skipped (strain_kernel takes the same mask).
 __device__ __forceinline__ void force_of(const double* K, const double2 (&z)[5], double2 zt, double c2,
                                          double2 (&o)[3]) {
   const double r2 = 0.70710678118654752440, r3 = 0.57735026918962576451, r6 = 0.40824829046386301637;
@@ -346,11 +347,11 @@ __device__ __forceinline__ void force_of(const double* K, const double2 (&z)[5],
 }
 
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
-                             double2* KX, long ldk, long sK, const int* kact, int pairN) {
+                             double2* KX, long ldk, long sK, const int* kact, int pairN, const int* cmask) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np || (kact && !kact[k])) return;
+  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const int c = (pairN - 1) / 2;
   if (p > c && p < pairN) return;  // the partner thread writes this row
   const double2* z = Zy + (long)k * Np * 5 * ncol + (long)(5 * j) * Np;
@@ -454,7 +455,8 @@ __global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* id
 // R = KX - theta OX per column (one block per (column, k)); writes R into Rp in the
 // preconditioner precision, the residual norm and the relative residual
 // rn = |R| / ((|theta| + sigma) |OX|).  Columns with rn below act_tol are locked: their
-// residual and their previous-direction (P) column are zeroed.
+// residual, their previous-direction (P) column with its images and the images of their
+// search direction (W) are zeroed.
 template <typename R>
 __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, long mcols, long sBig,
                                                        const double* theta, int s, const double* sigma,
@@ -494,13 +496,18 @@ __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, lo
   if (rel < act_tol) {
     // Converged column: it stops feeding the search space (soft locking).  Its
     // preconditioned residual and its previous-direction column are zeroed, so the
-    // next orthonormalisation drops them instead of amplifying rounding noise.
+    // next orthonormalisation drops them instead of amplifying rounding noise, and so
+    // are the images of its search direction (K W, Omega W), which the operator
+    // products then skip: the direction itself is zero.
     double2* pc = S + (2L * s + j) * n3;
+    double2* wc = S + ((long)s + j) * n3;
     for (long i = threadIdx.x; i < n3; i += 256) {
       r[i] = mk<R>(0, 0);
       pc[i] = make_double2(0, 0);
       pc[mcols * n3 + i] = make_double2(0, 0);
       pc[2 * mcols * n3 + i] = make_double2(0, 0);
+      wc[mcols * n3 + i] = make_double2(0, 0);
+      wc[2 * mcols * n3 + i] = make_double2(0, 0);
     }
   }
 }
@@ -799,15 +806,15 @@ template void launch_assemble<float>(const double2*, const double2*, const doubl
                                      double, const double*, float2*, long, int, hipStream_t);
 
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
-                   double2* tr, hipStream_t st, const int* kact, int pairN) {
+                   double2* tr, hipStream_t st, const int* kact, int pairN, const int* cmask) {
   hipLaunchKernelGGL(strain_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
-                     tr, kact, pairN);
+                     tr, kact, pairN, cmask);
 }
 
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
-                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact, int pairN) {
+                  double2* KX, long ldk, long sK, hipStream_t st, const int* kact, int pairN, const int* cmask) {
   hipLaunchKernelGGL(force_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
-                     ldk, sK, kact, pairN);
+                     ldk, sK, kact, pairN, cmask);
 }
 
 void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st, const double2* Mc2) {

@@ -593,9 +593,12 @@ const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0};
 // K and Omega applied (FP64, matrix-free, paired basis) to ncol columns of the S block of
 // Big starting at column c0; results to the same columns of the KS and OS blocks.
 // msk (device, per k; NULL: sv.kact) selects the k-points, nm counts them and lst lists
-// them (device, nm entries).
+// them (device, nm entries).  cl (optional, device): only the nc columns it lists
+// (entries k * ncol + j) go through the operator products, and cm (device, per
+// k * ncol + j) marks the same columns for the strain and force kernels; the images of the
+// other columns are left as they are.
 void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = nullptr, int nm = -1,
-               const int* lst = nullptr) {
+               const int* lst = nullptr, const int* cl = nullptr, int nc = 0, const int* cm = nullptr) {
   phx_ctx* ctx = sv.ctx;
   Design& d = *sv.d;
   hipStream_t st = ctx->stream;
@@ -610,8 +613,9 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   const double Np = d.Np, nk = nm;  // algorithmic work counts the selected k-points only
   PROF_BEGIN(PROF_APPLY);
   // strain channels of the paired-basis columns, in the same basis
-  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N);
-  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (3.0 + 6.0) * Np);
+  launch_strain(X, n3, sv.sBig, sv.Kv, d.Np, ncol, sv.nk, sv.Y, sv.Tr, st, msk, d.N, cl ? cm : nullptr);
+  const double ncv = cl ? (double)nc : nk * ncol;  // vectors through the operators
+  PROF_END(PROF_APPLY, 0, 16.0 * ncv * (3.0 + 6.0) * Np);
   KCHK(hipGetLastError());
   // The three real operator products in one launch, over the listed k-points: the
   // deviatoric compliance Bm times the five deviatoric strain channels, Omega_s times the
@@ -624,19 +628,29 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   a.nseg = 3;
   a.M = a.K = d.Np;
   a.lda = d.Np;
-  // (each product over the listed k-points' columns packed side by side)
-  a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, (long)d.Np * ny, (long)d.Np, (long)d.Np * ny, 0, nm, ny, lst};
-  a.seg[1] = OpSeg{d.Or, X, Big + (2 * m + c0) * n3, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nm, 3 * ncol, lst};
-  a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, (long)d.Np * ncol, (long)d.Np, (long)d.Np * ncol, 0, nm, ncol, lst};
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 9.0 * ncol * nk, 3.0 * 8.0 * Np * Np + 32.0 * Np * 9.0 * ncol * nk);
+  // (each product over the listed k-points' columns, or the listed vectors' columns, packed
+  // side by side)
+  const long sy = (long)d.Np * ny, st1 = (long)d.Np * ncol;
+  double2* OX = Big + (2 * m + c0) * n3;
+  if (cl) {
+    a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nc, 5, cl, ncol};
+    a.seg[1] = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nc, 3, cl, ncol};
+    a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nc, 1, cl, ncol};
+  } else {
+    a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nm, ny, lst, 1};
+    a.seg[1] = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nm, 3 * ncol, lst, 1};
+    a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nm, ncol, lst, 1};
+  }
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 9.0 * ncv, 3.0 * 8.0 * Np * Np + 32.0 * Np * 9.0 * ncv);
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &a.ev0, &a.ev1);
     ctx->pk.set = false;
   }
   KCHK(opgemm(a, st));
   PROF_BEGIN(PROF_APPLY);
-  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N);
-  PROF_END(PROF_APPLY, 0, 16.0 * nk * ncol * (6.0 + 3.0) * Np);
+  launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N,
+               cl ? cm : nullptr);
+  PROF_END(PROF_APPLY, 0, 16.0 * ncv * (6.0 + 3.0) * Np);
   KCHK(hipGetLastError());
 }
 
@@ -924,6 +938,11 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   sv.lact = dbuf<int>(ctx, "klist", 3L * nk);
   sv.lfar = sv.lact + nk;
   sv.lnear = sv.lact + 2 * nk;
+  // the search directions of the next step that are not zero (their column is not soft
+  // locked): a list of k * s + j and a mask per k * s + j, rebuilt every iteration
+  int* wl_d = dbuf<int>(ctx, "wcols", 2L * nk * s);
+  int* wm_d = wl_d + (long)nk * s;
+  std::vector<int> wcols_h(2L * nk * s);
   // the lists of the active, far and near k-points, from the host masks
   std::vector<int> lists_h(3L * nk);
   auto upload_lists = [&](const std::vector<int>& a, const std::vector<int>& f, const std::vector<int>& n) {
@@ -1117,8 +1136,19 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
       sv.njac = nj;
       sv.npen = np;
     }
+    // The open columns of the active k-points, by the residual kernel's own test (a column
+    // whose relative residual is below tol was soft locked there: its residual and the
+    // images of its search direction are zero, and its direction will be zero).
+    int nw = 0;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < s; ++j) {
+        const bool open = act_h[k] && !(rn_h[(size_t)k * s + j] < tol);
+        wcols_h[(size_t)nk * s + (size_t)k * s + j] = open;
+        if (open) wcols_h[nw++] = k * s + j;
+      }
+    HIPCHK(hipMemcpyAsync(wl_d, wcols_h.data(), 2L * nk * s * sizeof(int), hipMemcpyHostToDevice, st));
     precondition<R>(sv);
-    apply_ops(sv, sv.Big, s, s);
+    apply_ops(sv, sv.Big, s, s, nullptr, -1, nullptr, wl_d, nw, wm_d);
   }
   out.iters = it;
   out.theta.resize((size_t)nk * s);
