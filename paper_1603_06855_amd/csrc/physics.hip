@@ -671,9 +671,36 @@ __global__ void field_coef_kernel(const double2* X, long ldx, long sX, int nsel,
   o[8 * N] = z[5 * Np];
 }
 
+// The synthesis phases exp(-i 2 pi m (i + 1/2) / nv), m = -M..M, i = 0..nv-1, as a table in
+// dynamic LDS, [m + M][i], when (2M+1) nv <= SYNTH_PH (the launchers size the LDS); else
+// each phase is computed where it is used.
+constexpr int SYNTH_PH = 4096;
+extern __shared__ double2 synth_ph[];
+struct Phases {
+  bool tab;
+  int M, nv;
+  __device__ __forceinline__ double2 operator()(int mi, int i) const {  // mi = m + M
+    return tab ? synth_ph[mi * nv + i] : voxel_phase(mi - M, i, nv, -1);
+  }
+};
+__device__ __forceinline__ Phases phase_table(int M, int nv) {
+  const int n = (2 * M + 1) * nv;
+  const bool tab = n <= SYNTH_PH;
+  if (tab) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) synth_ph[e] = voxel_phase(e / nv - M, e % nv, nv, -1);
+    __syncthreads();
+  }
+  return Phases{tab, M, nv};
+}
+static inline size_t synth_lds(int M, int nv) {
+  const long n = (2L * M + 1) * nv;
+  return n <= SYNTH_PH ? (size_t)n * sizeof(double2) : 0;
+}
+
 // Synthesis g_e = sum_p c_p exp(-i 2 pi n_p . s_e), first two axes:
 // H1[fc][n1][n2][i3] then H2[fc][n1][i2][i3] (fc = field x column).
 __global__ void synth_pass1(const double2* Fc, int M, int nv, long nfc, double2* H1) {
+  const Phases ph = phase_table(M, nv);
   const int L = 2 * M + 1;
   const long total = nfc * L * L * nv;
   const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -682,11 +709,12 @@ __global__ void synth_pass1(const double2* Fc, int M, int nv, long nfc, double2*
   const long r = id / nv;  // fc, n1, n2
   const double2* src = Fc + r * L;
   double2 acc = make_double2(0, 0);
-  for (int n3 = 0; n3 < L; ++n3) acc = cadd(acc, cmul(voxel_phase(n3 - M, i3, nv, -1), src[n3]));
+  for (int n3 = 0; n3 < L; ++n3) acc = cadd(acc, cmul(ph(n3, i3), src[n3]));
   H1[id] = acc;
 }
 
 __global__ void synth_pass2(const double2* H1, int M, int nv, long nfc, double2* H2) {
+  const Phases ph = phase_table(M, nv);
   const int L = 2 * M + 1;
   const long total = nfc * L * nv * nv;
   const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -696,7 +724,7 @@ __global__ void synth_pass2(const double2* H1, int M, int nv, long nfc, double2*
   const long fn1 = id / ((long)nv * nv);  // fc, n1
   const double2* src = H1 + fn1 * L * nv + i3;
   double2 acc = make_double2(0, 0);
-  for (int n2 = 0; n2 < L; ++n2) acc = cadd(acc, cmul(voxel_phase(n2 - M, i2, nv, -1), src[(long)n2 * nv]));
+  for (int n2 = 0; n2 < L; ++n2) acc = cadd(acc, cmul(ph(n2, i2), src[(long)n2 * nv]));
   H2[id] = acc;
 }
 
@@ -706,6 +734,7 @@ __global__ void synth_pass2(const double2* H1, int M, int nv, long nfc, double2*
 // and d omega / d rho_e = lscale * (d lambda / d rho_e) / (2 omega_SI) (0 at omega = 0).
 __global__ void energy_kernel(const double2* H2, int M, int nv, int ncols, const double* rho, MaterialND mat,
                               double v, double c2, const double* lam_nd, double lscale, double* out) {
+  const Phases ph = phase_table(M, nv);
   const int L = 2 * M + 1;
   const long nvox = (long)nv * nv * nv;
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -717,7 +746,7 @@ __global__ void energy_kernel(const double2* H2, int M, int nv, int ncols, const
   for (int q = 0; q < 9; ++q) {
     const double2* src = H2 + ((long)col * 9 + q) * L * nv * nv + i23;
     double2 acc = make_double2(0, 0);
-    for (int n1 = 0; n1 < L; ++n1) acc = cadd(acc, cmul(voxel_phase(n1 - M, i1, nv, -1), src[(long)n1 * nv * nv]));
+    for (int n1 = 0; n1 < L; ++n1) acc = cadd(acc, cmul(ph(n1, i1), src[(long)n1 * nv * nv]));
     f[q] = acc;
   }
   const double u2 = cabs2(f[0]) + cabs2(f[1]) + cabs2(f[2]);
@@ -923,15 +952,16 @@ void launch_gather_cols(const double2* X, long ldx, long sX, const int* sel, int
 void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, double2* H2, hipStream_t st) {
   const int L = 2 * M + 1;
   const long nfc = ncols * 9;
-  hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), 0, st, Fc, M, nv, nfc, H1);
-  hipLaunchKernelGGL(synth_pass2, dim3(nblk(nfc * L * nv * nv, 256)), dim3(256), 0, st, H1, M, nv, nfc, H2);
+  const size_t lds = synth_lds(M, nv);
+  hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), lds, st, Fc, M, nv, nfc, H1);
+  hipLaunchKernelGGL(synth_pass2, dim3(nblk(nfc * L * nv * nv, 256)), dim3(256), lds, st, H1, M, nv, nfc, H2);
 }
 
 void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rho, const MaterialND& mat, double v,
                    double c2, const double* lam_nd, double lscale, double* out, hipStream_t st) {
   const long nvox = (long)nv * nv * nv;
-  hipLaunchKernelGGL(energy_kernel, dim3(nblk(nvox, 256), ncols), dim3(256), 0, st, H2, M, nv, ncols, rho, mat, v,
-                     c2, lam_nd, lscale, out);
+  hipLaunchKernelGGL(energy_kernel, dim3(nblk(nvox, 256), ncols), dim3(256), synth_lds(M, nv), st, H2, M, nv, ncols,
+                     rho, mat, v, c2, lam_nd, lscale, out);
 }
 
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st) {
