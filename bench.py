@@ -158,7 +158,7 @@ def main():
         upd = ("phx::zgemm_kernel<float, 1, 0, 128, 32, 0>" if fp_chol == "float"
                else f"phx::nrhs_kernel<double, 1, {nbk}, 1>")
         return {"herk": (f"phx::zgemm_kernel<{fp_chol}, 0, 1, 64, 64, 1>", fpn, "mfma"),
-                "op_gemm": ("phx::opgemm_kernel", "fp64", "mfma"),
+                "op_gemm": ("phx::opgemm_kernel<8>", "fp64", "mfma"),
                 "solve_upd": (upd, fpn, "hbm")}
 
     # The library counts the work of the padded problem (Np = 64 ceil(N / 64) waves per
