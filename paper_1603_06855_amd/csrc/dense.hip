@@ -670,7 +670,7 @@ int zgemm(const GemmArgs<R>& g0, int opa, int opb, hipStream_t st) {
   }
   // Narrow outputs (N <= 32: triangular solves and updates with the s search
   // vectors) use 128 x 32 tiles; everything else 64 x 64.
-  const bool narrow = !g.tri && g.N <= 32;
+  const bool narrow = !g.tri && g.N <= 32 && g.tiled != 2;
   const int BM = narrow ? 128 : 64, BN = narrow ? 32 : 64;
   long ntiles;
   const long tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;

@@ -27,7 +27,7 @@ struct GemmArgs {
   int csplit, cgap;  // tall-skinny only: output column j >= csplit (if > 0) is stored at j + cgap
   const int* amap;   // optional device map: batch item b reads A item amap[b] (instead of b / dA)
   hipEvent_t ev0, ev1;  // optional: recorded at the start and the end of the (single) kernel's execution
-  int tiled;            // 1: always the LDS-tiled kernel, never the streaming few-RHS one
+  int tiled;            // 1: always the LDS-tiled kernel, never the streaming few-RHS one; 2: and always 64 x 64 tiles
   // optional device list: only nbat * kdiv batch items run, grid item i being batch item
   // bidx[i / kdiv] * kdiv + i % kdiv (tiled, tall-skinny and split-K reduction kernels)
   const int* bidx;

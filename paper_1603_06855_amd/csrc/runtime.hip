@@ -567,7 +567,7 @@ template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
           int ksplit = 1, C_t<R>* Cpart = nullptr, const int* kact = nullptr, int kdiv = 1, int csplit = 0,
-          int cgap = 0, const int* bidx = nullptr, int nbat = 0) {
+          int cgap = 0, const int* bidx = nullptr, int nbat = 0, int tiled = 0) {
   GemmArgs<R> g{};
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &g.ev0, &g.ev1);
@@ -578,6 +578,7 @@ void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const 
   g.kact = kact;
   g.bidx = bidx;
   g.nbat = nbat;
+  g.tiled = tiled;
   g.kdiv = kdiv;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.lda = lda; g.sA = sA; g.dA = dA;
@@ -1184,9 +1185,13 @@ void adjoint_chunk(Solver& sv, const std::vector<int>& sel, double* out) {
   double2* Zy = dbuf<double2>(ctx, "Zysel", (long)nk * d.Np * 6 * nsel);
   double2* Zt = dbuf<double2>(ctx, "Ztsel", (long)nk * d.Np * nsel);
   launch_strain(Xs, n3, n3 * nsel, sv.Kv, d.Np, nsel, nk, Y, Tr, st);
-  const long sy = (long)d.Np * 6 * nsel, st_ = (long)d.Np * nsel;
-  gemm<double>(ctx, 0, 0, d.Np, 6 * nsel, d.Np, nk, d.Bm, d.Np, 0, 1, Y, d.Np, sy, 1, Zy, d.Np, sy, ONE, ZERO);
-  gemm<double>(ctx, 0, 0, d.Np, nsel, d.Np, nk, d.Dm, d.Np, 0, 1, Tr, d.Np, st_, 1, Zt, d.Np, st_, ONE, ZERO);
+  // the strain blocks of all k-points are contiguous: each compliance product is one wide
+  // product (the operator read once, not once per k-point), always on 64 x 64 tiles, so a
+  // k-point's result does not depend on how many k-points share the product
+  gemm<double>(ctx, 0, 0, d.Np, 6 * nsel * nk, d.Np, 1, d.Bm, d.Np, 0, 1, Y, d.Np, 0, 1, Zy, d.Np, 0, ONE, ZERO, 1,
+               nullptr, nullptr, 1, 0, 0, nullptr, 0, 2);
+  gemm<double>(ctx, 0, 0, d.Np, nsel * nk, d.Np, 1, d.Dm, d.Np, 0, 1, Tr, d.Np, 0, 1, Zt, d.Np, 0, ONE, ZERO, 1,
+               nullptr, nullptr, 1, 0, 0, nullptr, 0, 2);
   const long ncols = (long)nk * nsel;
   const int L = 2 * d.M + 1;
   double2* Fc = dbuf<double2>(ctx, "Fc", ncols * 9 * d.N);
