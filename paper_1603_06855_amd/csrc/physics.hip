@@ -762,6 +762,74 @@ __global__ void energy_kernel(const double2* H2, int M, int nv, int ncols, const
   out[(long)col * nvox + e] = (lam > 0 && om > 0) ? lscale * dlam / (2.0 * om) : 0.0;
 }
 
+// The same two passes with each input slab read once: every output of a pass is an L-term
+// sum over one axis, and the naive forms above read each input once per output along that
+// axis (nv times), which leaves them bound by cache bandwidth.
+// synth_pass2, one block per (fc, n1): the L x nv slab H1[fc][n1][.][.] into LDS after the
+// phase table, then all nv x nv outputs H2[fc][n1][i2][i3] from it (L nv <= SYNTH_SLAB, dynamic
+// LDS 2 L nv entries).
+constexpr int SYNTH_SLAB = 2048;
+__global__ void synth_pass2_slab(const double2* H1, int M, int nv, double2* H2) {
+  const int L = 2 * M + 1;
+  double2* slab = synth_ph + L * nv;
+  const long fn1 = blockIdx.x;  // fc, n1
+  const double2* src = H1 + fn1 * L * nv;
+  for (int e = threadIdx.x; e < L * nv; e += blockDim.x) slab[e] = src[e];
+  const Phases ph = phase_table(M, nv);  // fills the table and synchronises
+  double2* dst = H2 + fn1 * (long)nv * nv;
+  for (int e = threadIdx.x; e < nv * nv; e += blockDim.x) {
+    const int i2 = e / nv, i3 = e % nv;
+    double2 acc = make_double2(0, 0);
+    for (int n2 = 0; n2 < L; ++n2) acc = cadd(acc, cmul(ph(n2, i2), slab[n2 * nv + i3]));
+    dst[e] = acc;
+  }
+}
+
+// energy_kernel with a 16 x 16 tile of (i1, i23) voxels per block (i23 = i2 nv + i3): the
+// 9 x L x 16 slab of H2 for the tile's i23 into LDS, read once per 16 values of i1.
+constexpr int ENERGY_T = 16;
+__global__ __launch_bounds__(256) void energy_slab_kernel(const double2* H2, int M, int nv, int ncols,
+                                                          const double* rho, MaterialND mat, double v, double c2,
+                                                          const double* lam_nd, double lscale, double* out) {
+  double2* const synth_dyn = synth_ph;  // dynamic LDS: the phase table, then the slab
+  const int L = 2 * M + 1;
+  const long nvv = (long)nv * nv, nvox = nvv * nv;
+  double2* slab = synth_dyn + L * nv;  // [q][n1][j], j < ENERGY_T
+  for (int e = threadIdx.x; e < L * nv; e += blockDim.x) synth_dyn[e] = voxel_phase(e / nv - M, e % nv, nv, -1);
+  const int col = blockIdx.y;
+  const long t23 = blockIdx.x;                          // i23 tile
+  const int ti1 = blockIdx.z;                           // i1 tile
+  const long i23_0 = t23 * ENERGY_T;
+  const double2* src = H2 + (long)col * 9 * L * nvv;
+  for (int e = threadIdx.x; e < 9 * L * ENERGY_T; e += blockDim.x) {
+    const int j = e % ENERGY_T, qn = e / ENERGY_T;      // qn = q L + n1
+    const long i23 = i23_0 + j;
+    slab[e] = i23 < nvv ? src[(long)qn * nvv + i23] : make_double2(0, 0);
+  }
+  __syncthreads();
+  const int j = threadIdx.x % ENERGY_T, i1 = ti1 * ENERGY_T + threadIdx.x / ENERGY_T;
+  const long i23 = i23_0 + j;
+  if (i1 >= nv || i23 >= nvv) return;
+  double2 f[9];
+  for (int q = 0; q < 9; ++q) {
+    double2 acc = make_double2(0, 0);
+    for (int n1 = 0; n1 < L; ++n1) acc = cadd(acc, cmul(synth_dyn[n1 * nv + i1], slab[(q * L + n1) * ENERGY_T + j]));
+    f[q] = acc;
+  }
+  const long e = (long)i1 * nvv + i23;
+  const double u2 = cabs2(f[0]) + cabs2(f[1]) + cabs2(f[2]);
+  const double2 tr = cadd(cadd(f[3], f[4]), f[5]);
+  double s2 = 0;
+  for (int q = 3; q < 9; ++q) s2 += cabs2(f[q]);
+  const double t2 = cabs2(tr) / 3.0;
+  const double lam = lam_nd[col];
+  const double r = rho[e];
+  const double wp = (mat.p == 1.0) ? 1.0 : mat.p * pow(r, mat.p - 1.0);
+  const double dlam = -v * wp * (lam * mat.ddens * u2 + c2 * (mat.dcvol * t2 + mat.dcdev * (s2 - t2)));
+  const double om = sqrt(fmax(lam, 0.0) * lscale);
+  out[(long)col * nvox + e] = (lam > 0 && om > 0) ? lscale * dlam / (2.0 * om) : 0.0;
+}
+
 // grad_e = sum_col weight[col] * sens[col][e], summed in column order.
 __global__ void weighted_sum_kernel(const double* sens, const double* wgt, int ncols, long nvox, double* grad) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -954,14 +1022,26 @@ void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, dou
   const long nfc = ncols * 9;
   const size_t lds = synth_lds(M, nv);
   hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), lds, st, Fc, M, nv, nfc, H1);
-  hipLaunchKernelGGL(synth_pass2, dim3(nblk(nfc * L * nv * nv, 256)), dim3(256), lds, st, H1, M, nv, nfc, H2);
+  if (lds > 0 && (long)L * nv <= SYNTH_SLAB)
+    hipLaunchKernelGGL(synth_pass2_slab, dim3((unsigned)(nfc * L)), dim3(256), 2 * lds, st, H1, M, nv, H2);
+  else
+    hipLaunchKernelGGL(synth_pass2, dim3(nblk(nfc * L * nv * nv, 256)), dim3(256), lds, st, H1, M, nv, nfc, H2);
 }
 
 void launch_energy(const double2* H2, int M, int nv, int ncols, const double* rho, const MaterialND& mat, double v,
                    double c2, const double* lam_nd, double lscale, double* out, hipStream_t st) {
   const long nvox = (long)nv * nv * nv;
-  hipLaunchKernelGGL(energy_kernel, dim3(nblk(nvox, 256), ncols), dim3(256), synth_lds(M, nv), st, H2, M, nv, ncols,
-                     rho, mat, v, c2, lam_nd, lscale, out);
+  const int L = 2 * M + 1;
+  const size_t slab = ((size_t)L * nv + 9 * L * ENERGY_T) * sizeof(double2);
+  if (slab <= 64 * 1024) {
+    const long nvv = (long)nv * nv;
+    const dim3 grid((unsigned)((nvv + ENERGY_T - 1) / ENERGY_T), (unsigned)ncols, (unsigned)((nv + ENERGY_T - 1) / ENERGY_T));
+    hipLaunchKernelGGL(energy_slab_kernel, grid, dim3(256), slab, st, H2, M, nv, ncols, rho, mat, v, c2, lam_nd,
+                       lscale, out);
+  } else {
+    hipLaunchKernelGGL(energy_kernel, dim3(nblk(nvox, 256), ncols), dim3(256), synth_lds(M, nv), st, H2, M, nv, ncols,
+                       rho, mat, v, c2, lam_nd, lscale, out);
+  }
 }
 
 void launch_weighted_sum(const double* sens, const double* wgt, int ncols, long nvox, double* grad, hipStream_t st) {
