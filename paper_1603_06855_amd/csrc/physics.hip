@@ -765,6 +765,24 @@ __global__ void energy_kernel(const double2* H2, int M, int nv, int ncols, const
 // The same two passes with each input slab read once: every output of a pass is an L-term
 // sum over one axis, and the naive forms above read each input once per output along that
 // axis (nv times), which leaves them bound by cache bandwidth.
+// synth_pass1, one block per (fc, n1): the L x L coefficients Fc[fc][n1][.][.] into LDS after
+// the phase table, then the L x nv outputs H1[fc][n1][n2][i3] (dynamic LDS L nv + L^2 entries).
+__global__ void synth_pass1_slab(const double2* Fc, int M, int nv, double2* H1) {
+  const int L = 2 * M + 1;
+  double2* slab = synth_ph + L * nv;
+  const long fn1 = blockIdx.x;  // fc, n1
+  const double2* src = Fc + fn1 * L * L;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) slab[e] = src[e];
+  const Phases ph = phase_table(M, nv);  // fills the table and synchronises
+  double2* dst = H1 + fn1 * (long)L * nv;
+  for (int e = threadIdx.x; e < L * nv; e += blockDim.x) {
+    const int n2 = e / nv, i3 = e % nv;
+    double2 acc = make_double2(0, 0);
+    for (int n3 = 0; n3 < L; ++n3) acc = cadd(acc, cmul(ph(n3, i3), slab[n2 * L + n3]));
+    dst[e] = acc;
+  }
+}
+
 // synth_pass2, one block per (fc, n1): the L x nv slab H1[fc][n1][.][.] into LDS after the
 // phase table, then all nv x nv outputs H2[fc][n1][i2][i3] from it (L nv <= SYNTH_SLAB, dynamic
 // LDS 2 L nv entries).
@@ -1021,7 +1039,11 @@ void launch_synth(const double2* Fc, int M, int nv, long ncols, double2* H1, dou
   const int L = 2 * M + 1;
   const long nfc = ncols * 9;
   const size_t lds = synth_lds(M, nv);
-  hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), lds, st, Fc, M, nv, nfc, H1);
+  if (lds > 0)
+    hipLaunchKernelGGL(synth_pass1_slab, dim3((unsigned)(nfc * L)), dim3(256), lds + (size_t)L * L * sizeof(double2),
+                       st, Fc, M, nv, H1);
+  else
+    hipLaunchKernelGGL(synth_pass1, dim3(nblk(nfc * L * L * nv, 256)), dim3(256), lds, st, Fc, M, nv, nfc, H1);
   if (lds > 0 && (long)L * nv <= SYNTH_SLAB)
     hipLaunchKernelGGL(synth_pass2_slab, dim3((unsigned)(nfc * L)), dim3(256), 2 * lds, st, H1, M, nv, H2);
   else
