@@ -408,7 +408,7 @@ int opgemm(const OpArgs& g, hipStream_t st) {
 // one stripe's whole row block is in flight at once.  Three real products per complex
 // product (Karatsuba).
 template <typename R, int NB, int ST>
-__global__ __launch_bounds__(256, 2) void skinny_kernel(GemmArgs<R> g) {
+__global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
   typedef C_t<R> C;
   typedef typename acc_t<R>::type ACC;
   constexpr int NC = 16 * NB;
@@ -433,12 +433,6 @@ __global__ __launch_bounds__(256, 2) void skinny_kernel(GemmArgs<R> g) {
     const int i0 = blockIdx.x * 64 * ST + wave * 16 * ST + 16 * stripe;
     if (i0 >= g.M) break;
     const int i = i0 + li;
-    C av[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = 4 * q + lg;
-      av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
-    }
     ACC t1[NB], t2[NB], t3[NB];
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
@@ -447,15 +441,24 @@ __global__ __launch_bounds__(256, 2) void skinny_kernel(GemmArgs<R> g) {
       t3[y] = (ACC){0, 0, 0, 0};
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {  // k >= K: A is zero there and W's rows are zero
-      const int k = 4 * q + lg;
-      const R ar = av[q].x, ai = av[q].y, as = ar + ai;
+    for (int h = 0; h < 2; ++h) {  // two halves of the k range, 8 loads in flight each
+      C av[8];
 #pragma unroll
-      for (int y = 0; y < NB; ++y) {
-        const R br = Wr[k][16 * y + li], bi = Wi[k][16 * y + li];
-        t1[y] = mfma16(br, ar, t1[y]);
-        t2[y] = mfma16(bi, ai, t2[y]);
-        t3[y] = mfma16(br + bi, as, t3[y]);
+      for (int q = 0; q < 8; ++q) {
+        const int k = 32 * h + 4 * q + lg;
+        av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {  // k >= K: A is zero there and W's rows are zero
+        const int k = 32 * h + 4 * q + lg;
+        const R ar = av[q].x, ai = av[q].y, as = ar + ai;
+#pragma unroll
+        for (int y = 0; y < NB; ++y) {
+          const R br = Wr[k][16 * y + li], bi = Wi[k][16 * y + li];
+          t1[y] = mfma16(br, ar, t1[y]);
+          t2[y] = mfma16(bi, ai, t2[y]);
+          t3[y] = mfma16(br + bi, as, t3[y]);
+        }
       }
     }
 #pragma unroll
