@@ -303,6 +303,8 @@ def main():
         o32x, d32x = ctx.sens_batch_dev(cells, rho_dev, q[sub_idx], nb, ext, "mixed")
         torch.cuda.synchronize()
         om_err, sens_err, n_timed, n_ext, n_left = 0.0, 0.0, 0, 0, 0
+        om_band = np.zeros(nb)           # max over designs and k of |dw|/w, per band
+        sens_band = {}                   # band -> max sensitivity error of its cluster
         for d in range(args.designs):
             om32 = res[0][d].cpu().numpy()[sub_idx]
             dw32 = res[1][d].cpu().numpy()[sub_idx]
@@ -310,6 +312,7 @@ def main():
             dw32x = d32x[d].cpu().numpy()
             rel = np.where(om64 > 1e-3 * om64.max(), np.abs(om32 - om64) / np.maximum(om64, 1e-300), 0.0)
             om_err = max(om_err, float(rel.max()))
+            om_band = np.maximum(om_band, rel.max(axis=0))
             for k in range(len(sub_idx)):
                 w = om64[k]
                 done = set()
@@ -339,8 +342,12 @@ def main():
                         n_ext += 1
                     e = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
                     sens_err = max(sens_err, float(e))
+                    for c in cl:
+                        sens_band[c + 1] = max(sens_band.get(c + 1, 0.0), float(e))
         gate = {"designs": args.designs, "k_points": int(len(sub_idx)), "source": "timed step",
                 "max_rel_omega_err": om_err, "max_sens_err": sens_err,
+                "rel_omega_err_per_band": [float(f"{e:.2e}") for e in om_band],
+                "sens_err_per_band": {str(b): float(f"{e:.2e}") for b, e in sorted(sens_band.items())},
                 "sens_clusters_from_timed_step": n_timed, "sens_clusters_from_bands_3_to_10": n_ext,
                 "sens_clusters_not_compared": n_left,
                 "pass": bool(om_err <= 1e-6 and sens_err <= 1e-6 and n_left == 0)}
