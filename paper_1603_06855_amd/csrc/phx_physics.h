@@ -44,6 +44,23 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
 // Mc2 (optional): the same for Mc + Mc2.
 void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st, const double2* Mc2 = nullptr);
 void launch_zero(double2* X, long n, hipStream_t st);
+// Omega_s times listed columns as an exact convolution with the density's Fourier
+// table (orders M <= OMEGA_CONV_MAX_M; the same product as the dense real operator
+// Re(U^H Omega_s U) in the paired basis, rows N .. Np-1 copied).  Column u < nb ncolk:
+// e = bidx[u / ncolk], stored at (e / kdiv) sB + ((e % kdiv) ncolk + u % ncolk) ldb in X
+// (input) and Y (output, not aliasing X), Np rows each.  Ch: launch_omega_table's
+// (4M+1)^3 table of the design.
+struct ConvCols {
+  const double2* X;
+  double2* Y;
+  long sB, ldb;
+  int nb, ncolk, kdiv;
+  const int* bidx;
+};
+constexpr int OMEGA_CONV_MAX_M = 5;
+// T0: the density table of launch_dft ((4M+1)^3, differences -2M..2M per axis).
+void launch_omega_table(const double2* T0, int M, double2* Ch, hipStream_t st);
+void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st);
 // pairN = N > 0: the unit columns in the paired basis (launch_realify); Np: rows per component.
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st, int Np,
                          int pairN);

@@ -12,6 +12,8 @@
 // the two isotropic projectors shared by every voxel; hence the 6N x 6N matrix
 // of Eq. (7) is Phi_vol (x) P_vol + Phi_dev (x) P_dev and its inverse splits the
 // same way.  Displacement vectors are stored component-major: row c*Np + p.
+#include <cmath>
+
 #include "phx_common.h"
 #include "phx_internal.h"
 #include "phx_physics.h"
@@ -646,6 +648,220 @@ __global__ void pair_kernel(T* X, long ldx, long sX, int ncol, int N, int Np, in
 }
 
 // ---------------------------------------------------------------------------
+// Omega_s X as a convolution.  Omega_s[p][q] = ghat_rho(n_p - n_q) (a3), so
+// Omega_s x is the linear convolution of the density's Fourier table over the
+// differences [-2M, 2M]^3 with the coefficients of x over [-M, M]^3; on the
+// cyclic grid of L2 = 4M + 1 points per axis no difference wraps, so DFTs of
+// length L2 along n3 and n2, a Toeplitz product along n1 (the table transformed
+// along n2 and n3, ochat), and the inverse DFTs reproduce it exactly (up to
+// rounding): about 0.7 MFLOP per column at M = 5 against 4 N^2 = 7 MFLOP for
+// the dense real operator.
+// ---------------------------------------------------------------------------
+
+// Ch[d1][g2][g3] = L2^-2 sum_{d2, d3} T0[d1][d2][d3] exp(-i 2 pi (g2 (d2 - 2M) + g3 (d3 - 2M)) / L2):
+// the density table T0 (first of the three tables of launch_dft) transformed along
+// its last two axes, with the two inverse transforms' normalisation.
+__global__ void omega_table_kernel(const double2* T0, int M, double2* Ch) {
+  const int L2 = 4 * M + 1, M2 = 2 * M;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= L2 * L2 * L2) return;
+  const int g3 = id % L2, g2 = (id / L2) % L2, d1 = id / (L2 * L2);
+  double2 acc = make_double2(0, 0);
+  for (int d2 = 0; d2 < L2; ++d2)
+    for (int d3 = 0; d3 < L2; ++d3) {
+      int j = (g2 * (d2 - M2) + g3 * (d3 - M2)) % L2;
+      if (j < 0) j += L2;
+      double s, c;
+      sincospi(2.0 * j / L2, &s, &c);
+      const double2 t = T0[((long)d1 * L2 + d2) * L2 + d3];
+      acc.x += t.x * c + t.y * s;  // t exp(-i phi)
+      acc.y += t.y * c - t.x * s;
+    }
+  Ch[id] = cscale(acc, 1.0 / ((double)L2 * L2));
+}
+
+struct ConvArgs {
+  ConvCols c;
+  const double2* Ch;
+  int Np;
+  double cs[21], sn[21];  // cos and sin of 2 pi j / L2, j < L2 (L2 <= 21)
+};
+
+// Length-L2 DFT, exp(-i 2 pi g m / L2), of L = 2M+1 coefficients at m = -M..M
+// (x[M + m]) to out[g os], g < L2.  The pairs m, -m and g, L2 - g share their
+// cosines and sines: X[g] = P - iQ and X[L2 - g] = P + iQ with
+// P = x_0 + sum_m (x_m + x_-m) cos, Q = sum_m (x_m - x_-m) sin.
+template <int M>
+__device__ __forceinline__ void conv_fwd(const double2 (&x)[2 * M + 1], const ConvArgs& a, double2* out, int os) {
+  constexpr int L2 = 4 * M + 1, H = 2 * M;
+  double2 s[M], d[M];
+  double2 f0 = x[M];
+#pragma unroll
+  for (int m = 1; m <= M; ++m) {
+    s[m - 1] = cadd(x[M + m], x[M - m]);
+    d[m - 1] = csub(x[M + m], x[M - m]);
+    f0 = cadd(f0, s[m - 1]);
+  }
+  out[0] = f0;
+#pragma unroll
+  for (int g = 1; g <= H; ++g) {
+    double2 P = x[M], Q = make_double2(0, 0);
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+      const double cv = a.cs[(g * m) % L2], sv = a.sn[(g * m) % L2];
+      P.x = fma(s[m - 1].x, cv, P.x);
+      P.y = fma(s[m - 1].y, cv, P.y);
+      Q.x = fma(d[m - 1].x, sv, Q.x);
+      Q.y = fma(d[m - 1].y, sv, Q.y);
+    }
+    out[g * os] = make_double2(P.x + Q.y, P.y - Q.x);
+    out[(L2 - g) * os] = make_double2(P.x - Q.y, P.y + Q.x);
+  }
+}
+
+// Inverse of conv_fwd restricted to n = -M..M (unnormalised): y[n] = sum_g Y[g]
+// exp(+i 2 pi g n / L2) to out[(M + n) os]; y[n] = P + iQ, y[-n] = P - iQ with
+// P = Y_0 + sum_g (Y_g + Y_-g) cos, Q = sum_g (Y_g - Y_-g) sin.
+template <int M>
+__device__ __forceinline__ void conv_inv(const double2 (&Y)[4 * M + 1], const ConvArgs& a, double2* out, int os) {
+  constexpr int L2 = 4 * M + 1, H = 2 * M;
+  double2 S[H], D[H];
+  double2 y0 = Y[0];
+#pragma unroll
+  for (int g = 1; g <= H; ++g) {
+    S[g - 1] = cadd(Y[g], Y[L2 - g]);
+    D[g - 1] = csub(Y[g], Y[L2 - g]);
+    y0 = cadd(y0, S[g - 1]);
+  }
+  out[M * os] = y0;
+#pragma unroll
+  for (int n = 1; n <= M; ++n) {
+    double2 P = Y[0], Q = make_double2(0, 0);
+#pragma unroll
+    for (int g = 1; g <= H; ++g) {
+      const double cv = a.cs[(g * n) % L2], sv = a.sn[(g * n) % L2];
+      P.x = fma(S[g - 1].x, cv, P.x);
+      P.y = fma(S[g - 1].y, cv, P.y);
+      Q.x = fma(D[g - 1].x, sv, Q.x);
+      Q.y = fma(D[g - 1].y, sv, Q.y);
+    }
+    out[(M + n) * os] = make_double2(P.x - Q.y, P.y + Q.x);
+    out[(M - n) * os] = make_double2(P.x + Q.y, P.y - Q.x);
+  }
+}
+
+// One workgroup per column of one component (Np rows, paired basis): the column is
+// taken to plane waves, transformed along n3 (lines (a1, a2)) and n2 (lines (a1, g3)),
+// multiplied along n1 by the Toeplitz matrix of ochat per line (g2, g3), transformed
+// back along n2 and n3 and returned to the paired basis.  Every stage of one column
+// lives in one LDS buffer of L L2^2 complex values; a stage reads its lines into
+// registers, waits, and overwrites the buffer.  Rows N .. Np-1 (padding) are copied
+// (the dense operator is the identity there).
+template <int M>
+__global__ __launch_bounds__(256, 2) void omega_conv_kernel(ConvArgs a) {
+  constexpr int L = 2 * M + 1, L2 = 4 * M + 1, N = L * L * L, c = (N - 1) / 2, P2 = L2 * L2;
+  static_assert(L * L2 <= 256, "one line per thread in the n2 and n3 stages");
+  __shared__ double2 buf[L * P2];
+  const int tid = threadIdx.x;
+  const long u = blockIdx.x;
+  const int e = a.c.bidx[u / a.c.ncolk];
+  const long off = (long)(e / a.c.kdiv) * a.c.sB + (long)((e % a.c.kdiv) * a.c.ncolk + (int)(u % a.c.ncolk)) * a.c.ldb;
+  const double2* x = a.c.X + off;
+  double2* y = a.c.Y + off;
+
+  for (int p = tid; p <= c; p += 256) {
+    if (p == c) {
+      buf[c] = x[c];
+    } else {
+      double2 va = x[p], vb = x[N - 1 - p];
+      from_pair(va, vb);
+      buf[p] = va;
+      buf[N - 1 - p] = vb;
+    }
+  }
+  for (int r = N + tid; r < a.Np; r += 256) y[r] = x[r];
+  __syncthreads();
+  {  // along n3: [a1][a2][a3] -> [a1][a2][g3]
+    double2 v[L];
+    const bool act = tid < L * L;
+    if (act)
+#pragma unroll
+      for (int i = 0; i < L; ++i) v[i] = buf[tid * L + i];
+    __syncthreads();
+    if (act) conv_fwd<M>(v, a, buf + tid * L2, 1);
+    __syncthreads();
+  }
+  {  // along n2: [a1][a2][g3] -> [a1][g2][g3]
+    double2 v[L];
+    const bool act = tid < L * L2;
+    const int a1 = tid / L2, g3 = tid % L2;
+    if (act)
+#pragma unroll
+      for (int i = 0; i < L; ++i) v[i] = buf[(a1 * L + i) * L2 + g3];
+    __syncthreads();
+    if (act) conv_fwd<M>(v, a, buf + a1 * P2 + g3, L2);
+    __syncthreads();
+  }
+  // along n1: w[i] = sum_j Ch[i - j + 2M][g2][g3] v[j], in place per line l = g2 L2 + g3
+  for (int l = tid; l < P2; l += 256) {
+    double2 v[L], w[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      v[i] = buf[i * P2 + l];
+      w[i] = make_double2(0, 0);
+    }
+#pragma unroll
+    for (int dd = 0; dd < L2; ++dd) {
+      const double2 t = a.Ch[(long)dd * P2 + l];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const int j = i + 2 * M - dd;
+        if (j >= 0 && j < L) {
+          w[i].x = fma(t.x, v[j].x, w[i].x);
+          w[i].x = fma(-t.y, v[j].y, w[i].x);
+          w[i].y = fma(t.x, v[j].y, w[i].y);
+          w[i].y = fma(t.y, v[j].x, w[i].y);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) buf[i * P2 + l] = w[i];
+  }
+  __syncthreads();
+  {  // back along n2: [a1][g2][g3] -> [a1][a2][g3]
+    double2 v[L2];
+    const bool act = tid < L * L2;
+    const int a1 = tid / L2, g3 = tid % L2;
+    if (act)
+#pragma unroll
+      for (int i = 0; i < L2; ++i) v[i] = buf[(a1 * L2 + i) * L2 + g3];
+    __syncthreads();
+    if (act) conv_inv<M>(v, a, buf + a1 * L * L2 + g3, L2);
+    __syncthreads();
+  }
+  {  // back along n3: [a1][a2][g3] -> [a1][a2][a3]
+    double2 v[L2];
+    const bool act = tid < L * L;
+    if (act)
+#pragma unroll
+      for (int i = 0; i < L2; ++i) v[i] = buf[tid * L2 + i];
+    __syncthreads();
+    if (act) conv_inv<M>(v, a, buf + tid * L, 1);
+    __syncthreads();
+  }
+  for (int p = tid; p <= c; p += 256) {
+    if (p == c) {
+      y[c] = buf[c];
+    } else {
+      double2 va = buf[p], vb = buf[N - 1 - p];
+      to_pair(va, vb);
+      y[p] = va;
+      y[N - 1 - p] = vb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a8: adjoint.  Coefficients of the displacement (3) and Mandel stress (6)
 // fields of selected Ritz vectors, on the (2M+1)^3 wave grid:
 // Fc[col][f][p], col = k * nsel + j.
@@ -935,6 +1151,39 @@ void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np
 void launch_realify(const double2* Mc, int N, int Np, double* Mr, hipStream_t st, const double2* Mc2) {
   const long n = (long)Np * Np;
   hipLaunchKernelGGL(realify_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Mc, Mc2, N, Np, Mr);
+}
+
+void launch_omega_table(const double2* T0, int M, double2* Ch, hipStream_t st) {
+  const int L2 = 4 * M + 1, n = L2 * L2 * L2;
+  hipLaunchKernelGGL(omega_table_kernel, dim3(nblk(n, 128)), dim3(128), 0, st, T0, M, Ch);
+}
+
+void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st) {
+  const long units = (long)c.nb * c.ncolk;
+  if (units <= 0) return;
+  ConvArgs a{};
+  a.c = c;
+  a.Ch = Ch;
+  a.Np = Np;
+  const int L2 = 4 * M + 1;
+  for (int j = 0; j <= L2 / 2; ++j) {  // exactly even cosines and odd sines
+    const double t = 2.0 * M_PI * j / L2;
+    a.cs[j] = std::cos(t);
+    a.sn[j] = std::sin(t);
+    if (j > 0) {
+      a.cs[L2 - j] = a.cs[j];
+      a.sn[L2 - j] = -a.sn[j];
+    }
+  }
+  const dim3 grid((unsigned)units), blk(256);
+  switch (M) {
+    case 1: hipLaunchKernelGGL(omega_conv_kernel<1>, grid, blk, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(omega_conv_kernel<2>, grid, blk, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(omega_conv_kernel<3>, grid, blk, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(omega_conv_kernel<4>, grid, blk, 0, st, a); break;
+    case 5: hipLaunchKernelGGL(omega_conv_kernel<5>, grid, blk, 0, st, a); break;
+    default: break;
+  }
 }
 
 void launch_zero(double2* X, long n, hipStream_t st) {

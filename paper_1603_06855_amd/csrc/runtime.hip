@@ -65,6 +65,7 @@ struct Opts {
   double kshare_dist = 0.15; // ... if within this Cartesian distance (cycles per a) of the group's first
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
+  int omega_conv = 1;        // 1: Omega_s X as a convolution (M <= 5); 0: the dense real operator
   int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
   int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
   double degen_tol = 1e-8;   // bands closer than this (relative, in omega) form one degenerate cluster
@@ -404,6 +405,7 @@ struct Design {
   double* Vr = nullptr;
   double* Br = nullptr;
   double* Or = nullptr;
+  double2* Ch = nullptr;  // the density table transformed along n2, n3 (launch_omega_table), M <= 5
 };
 
 MaterialND nondim(const phx_cell& c) {
@@ -484,6 +486,11 @@ void setup_design(phx_ctx* ctx, const phx_cell& cell, const double* rho_host, co
   launch_fields(d.rho_d, (int)d.nvox, d.mat, F, st);
   launch_dft(F, d.nv, d.M, d.v, G1, G2, d.tab, st);
   KCHK(hipGetLastError());
+  if (d.M <= OMEGA_CONV_MAX_M) {
+    d.Ch = dbuf<double2>(ctx, tag + "och", (size_t)L2 * L2 * L2);
+    launch_omega_table(d.tab, d.M, d.Ch, st);
+    KCHK(hipGetLastError());
+  }
 
   const long NN = (long)d.Np * d.Np;
   double2* ops = dbuf<double2>(ctx, tag + "ops", 3 * NN);  // Os, Pv, Pd -> Os, factors
@@ -618,36 +625,54 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   const double ncv = cl ? (double)nc : nk * ncol;  // vectors through the operators
   PROF_END(PROF_APPLY, 0, 16.0 * ncv * (3.0 + 6.0) * Np);
   KCHK(hipGetLastError());
-  // The three real operator products in one launch, over the listed k-points: the
-  // deviatoric compliance Bm times the five deviatoric strain channels, Omega_s times the
-  // columns, and the volumetric compliance Phi_vol^-1 times the volumetric channel (one
-  // column per vector: those of the listed k-points form one product); nine operator
-  // columns per vector.  4 Np^2 flops per complex column (two real products); each
-  // operator (8 B per entry) read once, each block read and written once.
+  // The real operator products in one launch, over the listed k-points: the deviatoric
+  // compliance Bm times the five deviatoric strain channels, the volumetric compliance
+  // Phi_vol^-1 times the volumetric channel and, unless it is applied as a convolution
+  // (option omega_conv, M <= 5), Omega_s times the columns (one column per vector: those
+  // of the listed k-points form one product); six or nine operator columns per vector.
+  // 4 Np^2 flops per complex column (two real products); each operator (8 B per entry)
+  // read once, each block read and written once.
+  const bool conv = ctx->opt.omega_conv && d.Ch;
   const int ny = 5 * ncol;
   OpArgs a{};
-  a.nseg = 3;
   a.M = a.K = d.Np;
   a.lda = d.Np;
   // (each product over the listed k-points' columns, or the listed vectors' columns, packed
   // side by side)
   const long sy = (long)d.Np * ny, st1 = (long)d.Np * ncol;
   double2* OX = Big + (2 * m + c0) * n3;
+  OpSeg sb, so, sw;
   if (cl) {
-    a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nc, 5, cl, ncol};
-    a.seg[1] = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nc, 3, cl, ncol};
-    a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nc, 1, cl, ncol};
+    sb = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nc, 5, cl, ncol};
+    so = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nc, 3, cl, ncol};
+    sw = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nc, 1, cl, ncol};
   } else {
-    a.seg[0] = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nm, ny, lst, 1};
-    a.seg[1] = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nm, 3 * ncol, lst, 1};
-    a.seg[2] = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nm, ncol, lst, 1};
+    sb = OpSeg{d.Br, sv.Y, sv.Zy, (long)d.Np, sy, (long)d.Np, sy, 0, nm, ny, lst, 1};
+    so = OpSeg{d.Or, X, OX, (long)d.Np, sv.sBig, (long)d.Np, sv.sBig, 0, nm, 3 * ncol, lst, 1};
+    sw = OpSeg{d.Vr, sv.Tr, sv.Zt, (long)d.Np, st1, (long)d.Np, st1, 0, nm, ncol, lst, 1};
   }
-  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * 9.0 * ncv, 3.0 * 8.0 * Np * Np + 32.0 * Np * 9.0 * ncv);
+  a.seg[0] = sb;
+  if (conv) {
+    a.nseg = 2;
+    a.seg[1] = sw;
+  } else {
+    a.nseg = 3;
+    a.seg[1] = so;
+    a.seg[2] = sw;
+  }
+  const double nop = conv ? 6.0 : 9.0;
+  PROF_KERNEL(PROF_OP_GEMM, 4.0 * Np * Np * nop * ncv, (double)a.nseg * 8.0 * Np * Np + 32.0 * Np * nop * ncv);
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &a.ev0, &a.ev1);
     ctx->pk.set = false;
   }
   KCHK(opgemm(a, st));
+  if (conv) {
+    PROF_BEGIN(PROF_APPLY);
+    launch_omega_conv(ConvCols{so.B, so.C, so.sB, so.ldb, so.nb, so.ncolk, so.kdiv, so.bidx}, d.M, d.Np, d.Ch, st);
+    PROF_END(PROF_APPLY, 0, 32.0 * 3.0 * ncv * Np);
+    KCHK(hipGetLastError());
+  }
   PROF_BEGIN(PROF_APPLY);
   launch_force(sv.Zy, sv.Zt, sv.Kv, d.Np, ncol, sv.nk, d.c2, Big + (m + c0) * n3, n3, sv.sBig, st, msk, d.N,
                cl ? cm : nullptr);
@@ -1432,6 +1457,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "kstreams") { if (!(v >= 1 && v <= 16 && v == (int)v)) return bad(); ctx->opt.kstreams = (int)v; }
   else if (k == "gram_split") { if (!(v >= 0 && v <= 16 && v == (int)v)) return bad(); ctx->opt.gram_split = (int)v; }
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
+  else if (k == "omega_conv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.omega_conv = (int)v; }
   else if (k == "degen_tol") { if (!(v >= 0 && v < 1e-2)) return bad(); ctx->opt.degen_tol = v; }
   else if (k == "mem_limit_gb") { if (!(v >= 0 && v < 1e6)) return bad(); ctx->opt.mem_limit_gb = v; }
   else if (k == "precond") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.precond = (int)v; }
