@@ -150,6 +150,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
  * blocking-sync event, leaving the core to the threads of concurrent design
  * streams; 1: it spins in hipStreamSynchronize),
+ * "omega_conv" (1, default: for orders M <= 5 the eigensolver's products Omega_s X are
+ * exact convolutions of the density's Fourier coefficients with the columns, by DFTs of
+ * length 4M+1 (Omega_s is Toeplitz in the wave index, Eqs. (6)-(7)); 0: products with the dense
+ * N x N matrix; both give the same result up to rounding),
  * "precond" (the eigensolver's preconditioner; 0: the Cholesky factor of the shifted
  * pencil K(k) + sigma Omega, assembled per k-point (or per group of k-points, see
  * "kshare"); 1: block Jacobi, the 3 x 3 diagonal block of that pencil for each plane wave,
