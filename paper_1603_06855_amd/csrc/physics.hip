@@ -769,17 +769,35 @@ __global__ __launch_bounds__(256, 2) void omega_conv_kernel(ConvArgs a) {
   const double2* x = a.c.X + off;
   double2* y = a.c.Y + off;
 
-  for (int p = tid; p <= c; p += 256) {
-    if (p == c) {
-      buf[c] = x[c];
-    } else {
-      double2 va = x[p], vb = x[N - 1 - p];
-      from_pair(va, vb);
-      buf[p] = va;
-      buf[N - 1 - p] = vb;
+  // every load of the column in flight together, and the table line of this thread's
+  // first n1 line (consumed three stages later) fetched meanwhile
+  constexpr int NPR = (c + 256) / 256;  // pairs (p, N-1-p), p <= c, per thread
+  double2 va[NPR], vb[NPR], t0[L2];
+#pragma unroll
+  for (int r = 0; r < NPR; ++r) {
+    const int p = tid + r * 256;
+    if (p < c) {
+      va[r] = x[p];
+      vb[r] = x[N - 1 - p];
+    } else if (p == c) {
+      va[r] = x[c];
     }
   }
+  if (tid < P2)
+#pragma unroll
+    for (int dd = 0; dd < L2; ++dd) t0[dd] = a.Ch[(long)dd * P2 + tid];
   for (int r = N + tid; r < a.Np; r += 256) y[r] = x[r];
+#pragma unroll
+  for (int r = 0; r < NPR; ++r) {
+    const int p = tid + r * 256;
+    if (p < c) {
+      from_pair(va[r], vb[r]);
+      buf[p] = va[r];
+      buf[N - 1 - p] = vb[r];
+    } else if (p == c) {
+      buf[c] = va[r];
+    }
+  }
   __syncthreads();
   {  // along n3: [a1][a2][a3] -> [a1][a2][g3]
     double2 v[L];
@@ -803,29 +821,35 @@ __global__ __launch_bounds__(256, 2) void omega_conv_kernel(ConvArgs a) {
     __syncthreads();
   }
   // along n1: w[i] = sum_j Ch[i - j + 2M][g2][g3] v[j], in place per line l = g2 L2 + g3
-  for (int l = tid; l < P2; l += 256) {
-    double2 v[L], w[L];
+  // (the first line of each thread with the table line fetched at the start)
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-      v[i] = buf[i * P2 + l];
-      w[i] = make_double2(0, 0);
-    }
-#pragma unroll
-    for (int dd = 0; dd < L2; ++dd) {
-      const double2 t = a.Ch[(long)dd * P2 + l];
+  for (int rnd = 0; rnd < (P2 + 255) / 256; ++rnd) {
+    const int l = tid + 256 * rnd;
+    if (l < P2) {
+      double2 v[L], w[L], t[L2];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
-        const int j = i + 2 * M - dd;
-        if (j >= 0 && j < L) {
-          w[i].x = fma(t.x, v[j].x, w[i].x);
-          w[i].x = fma(-t.y, v[j].y, w[i].x);
-          w[i].y = fma(t.x, v[j].y, w[i].y);
-          w[i].y = fma(t.y, v[j].x, w[i].y);
+        v[i] = buf[i * P2 + l];
+        w[i] = make_double2(0, 0);
+      }
+#pragma unroll
+      for (int dd = 0; dd < L2; ++dd) t[dd] = rnd == 0 ? t0[dd] : a.Ch[(long)dd * P2 + l];
+#pragma unroll
+      for (int dd = 0; dd < L2; ++dd) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const int j = i + 2 * M - dd;
+          if (j >= 0 && j < L) {
+            w[i].x = fma(t[dd].x, v[j].x, w[i].x);
+            w[i].x = fma(-t[dd].y, v[j].y, w[i].x);
+            w[i].y = fma(t[dd].x, v[j].y, w[i].y);
+            w[i].y = fma(t[dd].y, v[j].x, w[i].y);
+          }
         }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < L; ++i) buf[i * P2 + l] = w[i];
+      for (int i = 0; i < L; ++i) buf[i * P2 + l] = w[i];
+    }
   }
   __syncthreads();
   {  // back along n2: [a1][g2][g3] -> [a1][a2][g3]
