@@ -150,6 +150,11 @@ const char* phx_last_error(const phx_ctx* ctx);
  * "spin_wait" (0, default: the eigensolver's once-per-iteration host wait sleeps on a
  * blocking-sync event, leaving the core to the threads of concurrent design
  * streams; 1: it spins in hipStreamSynchronize),
+ * "guard_lock" (1..1e4, default 1000: the eigensolver's guard vectors, the block columns
+ * beyond the wanted bands, are soft locked once their relative residual is below
+ * guard_lock x the tolerance, the wanted bands' at the tolerance itself; the guards are
+ * not results, and a wanted band still counts as converged only at the tolerance; 1: every
+ * column locks at the tolerance),
  * "omega_conv" (1, default: for orders M <= 5 the eigensolver's products Omega_s X are
  * exact convolutions of the density's Fourier coefficients with the columns, by DFTs of
  * length 4M+1 (Omega_s is Toeplitz in the wave index, Eqs. (6)-(7)); 0: products with the dense

@@ -71,10 +71,12 @@ void launch_pair(T* X, long ldx, long sX, int ncol, int N, int Np, int nk, int d
                  const int* kact = nullptr);
 void launch_prolong(const double2* Xc, long ldc, long sXc, int Mc, int Npc, double2* X, long ldx, long sX, int M,
                     int Np, int s, int nk, hipStream_t st);
+// Columns j >= nlock (the guard vectors beyond the wanted bands) lock below guard_tol
+// instead of act_tol (nlock = s: every column at act_tol).
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
-                     hipStream_t st, const int* kact = nullptr);
+                     hipStream_t st, const int* kact = nullptr, int nlock = -1, double guard_tol = 0.0);
 template <typename R>
 void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st,
                   const int* kact = nullptr);

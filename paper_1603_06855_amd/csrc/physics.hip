@@ -456,14 +456,15 @@ __global__ void unit_columns_kernel(double2* X, long ldx, long sX, const int* id
 
 // R = KX - theta OX per column (one block per (column, k)); writes R into Rp in the
 // preconditioner precision, the residual norm and the relative residual
-// rn = |R| / ((|theta| + sigma) |OX|).  Columns with rn below act_tol are locked: their
-// residual, their previous-direction (P) column with its images and the images of their
-// search direction (W) are zeroed.
+// rn = |R| / ((|theta| + sigma) |OX|).  Columns with rn below act_tol (columns from nlock
+// on: below guard_tol) are locked: their residual, their previous-direction (P) column
+// with its images and the images of their search direction (W) are zeroed.
 template <typename R>
 __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, long mcols, long sBig,
                                                        const double* theta, int s, const double* sigma,
                                                        double act_tol, C_t<R>* Rp, long sR, double* rn,
-                                                       double* rnorm, const int* kact) {
+                                                       double* rnorm, const int* kact, int nlock,
+                                                       double guard_tol) {
   const int j = blockIdx.x, k = blockIdx.y;
   if (kact && !kact[k]) return;  // converged k-point: its residuals stay as they were
   double2* S = Big + (long)k * sBig;
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(256) void residual_kernel(double2* Big, long n3, lo
     rn[k * s + j] = rel;
     rnorm[k * s + j] = sqrt(sa[0]);
   }
-  if (rel < act_tol) {
+  if (rel < (j < nlock ? act_tol : guard_tol)) {
     // Converged column: it stops feeding the search space (soft locking).  Its
     // preconditioned residual and its previous-direction column are zeroed, so the
     // next orthonormalisation drops them instead of amplifying rounding noise, and so
@@ -1233,14 +1234,15 @@ template void launch_pair<float2>(float2*, long, long, int, int, int, int, int, 
 template <typename R>
 void launch_residual(double2* Big, long n3, long mcols, long sBig, const double* theta, int s, int nk,
                      const double* sigma, double act_tol, C_t<R>* Rp, long sR, double* rn, double* rnorm,
-                     hipStream_t st, const int* kact) {
+                     hipStream_t st, const int* kact, int nlock, double guard_tol) {
+  if (nlock < 0 || nlock > s) nlock = s;
   hipLaunchKernelGGL((residual_kernel<R>), dim3(s, nk), dim3(256), 0, st, Big, n3, mcols, sBig, theta, s, sigma,
-                     act_tol, Rp, sR, rn, rnorm, kact);
+                     act_tol, Rp, sR, rn, rnorm, kact, nlock, guard_tol);
 }
 template void launch_residual<double>(double2*, long, long, long, const double*, int, int, const double*, double,
-                                      double2*, long, double*, double*, hipStream_t, const int*);
+                                      double2*, long, double*, double*, hipStream_t, const int*, int, double);
 template void launch_residual<float>(double2*, long, long, long, const double*, int, int, const double*, double,
-                                     float2*, long, double*, double*, hipStream_t, const int*);
+                                     float2*, long, double*, double*, hipStream_t, const int*, int, double);
 
 template <typename R>
 void launch_widen(const C_t<R>* Rp, long sR, long n, double2* W, long sW, int nk, hipStream_t st, const int* kact) {

@@ -66,6 +66,7 @@ struct Opts {
   double kshare_rel = 0.5;   // ... and within this fraction of the shorter of the two wave vectors
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
   int omega_conv = 1;        // 1: Omega_s X as a convolution (M <= 5); 0: the dense real operator
+  double guard_lock = 1000;  // guard columns (beyond the wanted bands) lock below guard_lock x tol
   int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
   int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
   double degen_tol = 1e-8;   // bands closer than this (relative, in omega) form one degenerate cluster
@@ -1009,6 +1010,9 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   apply_ops(sv, sv.Big, 0, s);
 
   const double tol = tol_override > 0 ? tol_override : ctx->opt.tol[prec];
+  // the guard vectors (columns nb .. s-1) are not results: they may lock at a looser
+  // threshold (option guard_lock; the coarse start keeps one threshold)
+  const double gtol = tol_override > 0 ? tol : tol * ctx->opt.guard_lock;
   std::vector<double> rn_h((size_t)nk * s), rnorm_h((size_t)nk * s);
   std::vector<int> sw_h(nk);
   std::vector<char> kdone(nk, 0);
@@ -1051,7 +1055,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     }
     PROF_BEGIN(PROF_RESIDUAL);
     launch_residual<R>(sv.Big, n3, m, sv.sBig, sv.theta, s, nk, sv.sigma_d, tol, (C_t<R>*)sv.Rp, n3 * s,
-                       sv.rn, sv.rnorm, st, sv.kact);
+                       sv.rn, sv.rnorm, st, sv.kact, nb, gtol);
     PROF_END(PROF_RESIDUAL, 0, 16.0 * 2 * 3.0 * d.N * s * sv.nact + (double)sizeof(C_t<R>) * 3.0 * d.N * s * sv.nact);
     KCHK(hipGetLastError());
     // residual norms, Jacobi sweep counts and (first iteration) the factorisation flag,
@@ -1168,7 +1172,7 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
     int nw = 0;
     for (int k = 0; k < nk; ++k)
       for (int j = 0; j < s; ++j) {
-        const bool open = act_h[k] && !(rn_h[(size_t)k * s + j] < tol);
+        const bool open = act_h[k] && !(rn_h[(size_t)k * s + j] < (j < nb ? tol : gtol));
         wcols_h[(size_t)nk * s + (size_t)k * s + j] = open;
         if (open) wcols_h[nw++] = k * s + j;
       }
@@ -1458,6 +1462,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "gram_split") { if (!(v >= 0 && v <= 16 && v == (int)v)) return bad(); ctx->opt.gram_split = (int)v; }
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "omega_conv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.omega_conv = (int)v; }
+  else if (k == "guard_lock") { if (!(v >= 1 && v <= 1e4)) return bad(); ctx->opt.guard_lock = v; }
   else if (k == "degen_tol") { if (!(v >= 0 && v < 1e-2)) return bad(); ctx->opt.degen_tol = v; }
   else if (k == "mem_limit_gb") { if (!(v >= 0 && v < 1e6)) return bad(); ctx->opt.mem_limit_gb = v; }
   else if (k == "precond") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.precond = (int)v; }

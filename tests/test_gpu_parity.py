@@ -664,6 +664,8 @@ def test_kernel_class_timing(ctx):
     ("precond", (-1, 3, 0.5), (0, 1, 2)),
     ("degen_tol", (-1e-9, 0.1), (0, 1e-8)),
     ("mem_limit_gb", (-1,), (0, 8.0)),
+    ("omega_conv", (-1, 2, 0.5), (0, 1)),
+    ("guard_lock", (0.5, 2e4), (1, 1000, 1e4)),
     ("no_such_option", (1.0,), ()),
 ])
 def test_option_ranges(key, bad, good):

@@ -12,6 +12,9 @@
   Ritz values above the exact eigenvalues and each within its bound of one of them;
 * phx_bands_batch (host pointers, designs of uneven lattice and M) equals per-design calls;
 * option block <= nbands is rejected before any device work;
+* guard locking (option guard_lock): the guard vectors beyond the wanted bands locking at
+  1000 x the tolerance (the default) or at the tolerance itself leave the wanted bands'
+  frequencies and sensitivities the same within the solver tolerance;
 * degenerate clusters (Eq. 15 needs a simple eigenvalue): a design with the full cubic
   symmetry at Gamma and X, whose bands come in symmetry-forced doublets and triplets;
   PHX_WDEGEN, every member of a cluster carries the cluster mean, which matches the mean of
@@ -197,6 +200,41 @@ def test_host_batch_of_uneven_designs_equals_single_calls(ctx):
         oms2 = ctx.bands_batch(cells, rhos, q, 8, prec)
         for c, r, om in zip(cells, rhos, oms2):
             assert np.array_equal(om, ctx.bands(c, r, q, 8, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_guard_locking_keeps_the_wanted_bands(ctx, prec):
+    cell = synth.Cell("FCC", 1.0, 32, 5)
+    rho = synth.box_smoothed_uniform(32, 402)
+    q = phx.kpath("FCC", 24)[[2, 7, 13, 19]]
+    ctx.set_option("tol_fp64", 1e-10)
+    res = {}
+    try:
+        for g in (1, 1000):
+            ctx.set_option("guard_lock", g)
+            res[g] = ctx.sens(cell, rho, q, 12, (6, 7), prec)
+            log("guard_lock", g, prec, "iters", ctx.stat("iters"), "status", ctx.last_status)
+    finally:
+        ctx.set_option("guard_lock", 1000)
+        ctx.set_option("tol_fp64", 1e-8)
+    (om1, dw1), (om2, dw2) = res[1], res[1000]
+    assert np.all(om1 > 0)
+    om_rel = (np.abs(om2 - om1) / om1).max()
+    # sensitivities of bands 6 and 7 summed over each cluster of relative gap below 1e-4
+    # that lies inside them (a cluster reaching band 5 or 8 is not compared)
+    sens, n = 0.0, 0
+    for k in range(len(q)):
+        for cl in clusters(om1[k], 1e-4):
+            if not set(cl) & {5, 6} or not set(cl) <= {5, 6}:
+                continue
+            idx = [c - 5 for c in cl]
+            a, r = dw2[k, idx].sum(axis=0), dw1[k, idx].sum(axis=0)
+            sens = max(sens, float(np.abs(a - r).max() / np.abs(r).max()))
+            n += 1
+    log("  max rel omega diff", om_rel, "max sens diff", sens, "over", n, "clusters")
+    assert n >= len(q)
+    assert om_rel <= (1e-9 if prec == "fp64" else 1e-8)
+    assert sens <= (1e-7 if prec == "fp64" else 1e-5)
 
 
 def test_block_not_above_nbands_is_rejected():
