@@ -4,7 +4,10 @@ omega_conv = 1, the default for M <= 5) against the dense real operator in the p
 rounding, so the frequencies and the adjoint sensitivities agree far inside the solver
 tolerance.  Cases: FCC 32^3 M = 5 (with the coarse start at M = 2 and at M = 3), BCC 24^3
 M = 4, SC M = 2 and 3; k-points off Gamma (no zero modes), FP64 and mixed precision.  The
-solver-level parity tests against the oracle run with the default (the convolution).
+solver-level parity tests against the oracle run with the default (the convolution).  At
+M = 6, beyond the convolution kernel's orders, both settings take the dense product and give
+identical results (with the coarse start off: its order-4 solve would take the
+convolution).
 """
 import sys
 
@@ -83,3 +86,22 @@ def test_convolution_equals_dense_operator(ctx, case, prec):
     assert n >= len(q)
     assert om_rel.max() <= (1e-9 if prec == "fp64" else 1e-8)
     assert sens_rel <= (1e-7 if prec == "fp64" else 1e-5)
+
+
+def test_order_six_takes_the_dense_product(ctx):
+    cell = synth.Cell("SC", 1.0, 16, 6)
+    rho = synth.box_smoothed_uniform(16, 203)
+    q = phx.kpath("SC", 24)[[3, 9]]
+    log("case SC M=6 fp64 nk", len(q))
+    res = {}
+    ctx.set_option("coarse", 0)
+    try:
+        for conv in (0, 1):
+            ctx.set_option("omega_conv", conv)
+            res[conv] = ctx.sens(cell, rho, q, 8, (3, 6), "fp64")
+            log("  omega_conv", conv, "status", ctx.last_status, "iters", ctx.stat("iters"))
+    finally:
+        ctx.set_option("omega_conv", 1)
+        ctx.set_option("coarse", 1)
+    assert np.all(res[0][0] > 0)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
