@@ -649,12 +649,12 @@ __global__ void pair_kernel(T* X, long ldx, long sX, int ncol, int N, int Np, in
 }
 
 // ---------------------------------------------------------------------------
-// Omega_s X as a convolution.  Omega_s[p][q] = ghat_rho(n_p - n_q) (a3), so
+// Omega_s X as a convolution.  Omega_s[p][q] = ghat_rho(n_p - n_q) (Eqs. (6)-(7); gather_kernel), so
 // Omega_s x is the linear convolution of the density's Fourier table over the
 // differences [-2M, 2M]^3 with the coefficients of x over [-M, M]^3; on the
 // cyclic grid of L2 = 4M + 1 points per axis no difference wraps, so DFTs of
 // length L2 along n3 and n2, a Toeplitz product along n1 (the table transformed
-// along n2 and n3, ochat), and the inverse DFTs reproduce it exactly (up to
+// along n2 and n3, Ch), and the inverse DFTs reproduce it exactly (up to
 // rounding): about 0.7 MFLOP per column at M = 5 against 4 N^2 = 7 MFLOP for
 // the dense real operator.
 // ---------------------------------------------------------------------------
@@ -753,7 +753,7 @@ __device__ __forceinline__ void conv_inv(const double2 (&Y)[4 * M + 1], const Co
 
 // One workgroup per column of one component (Np rows, paired basis): the column is
 // taken to plane waves, transformed along n3 (lines (a1, a2)) and n2 (lines (a1, g3)),
-// multiplied along n1 by the Toeplitz matrix of ochat per line (g2, g3), transformed
+// multiplied along n1 by the Toeplitz matrix of the table Ch per line (g2, g3), transformed
 // back along n2 and n3 and returned to the paired basis.  Every stage of one column
 // lives in one LDS buffer of L L2^2 complex values; a stage reads its lines into
 // registers, waits, and overwrites the buffer.  Rows N .. Np-1 (padding) are copied
