@@ -60,7 +60,9 @@ struct ConvCols {
 constexpr int OMEGA_CONV_MAX_M = 5;
 // T0: the density table of launch_dft ((4M+1)^3, differences -2M..2M per axis).
 void launch_omega_table(const double2* T0, int M, double2* Ch, hipStream_t st);
-void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st);
+// ev0 / ev1 (optional): events the launch records at the kernel's start and end.
+void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 // pairN = N > 0: the unit columns in the paired basis (launch_realify); Np: rows per component.
 void launch_unit_columns(double2* X, long ldx, long sX, const int* idx, int s, int nk, hipStream_t st, int Np,
                          int pairN);

@@ -12,6 +12,8 @@
 // the two isotropic projectors shared by every voxel; hence the 6N x 6N matrix
 // of Eq. (7) is Phi_vol (x) P_vol + Phi_dev (x) P_dev and its inverse splits the
 // same way.  Displacement vectors are stored component-major: row c*Np + p.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "phx_common.h"
@@ -1183,7 +1185,8 @@ void launch_omega_table(const double2* T0, int M, double2* Ch, hipStream_t st) {
   hipLaunchKernelGGL(omega_table_kernel, dim3(nblk(n, 128)), dim3(128), 0, st, T0, M, Ch);
 }
 
-void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st) {
+void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1) {
   const long units = (long)c.nb * c.ncolk;
   if (units <= 0) return;
   ConvArgs a{};
@@ -1201,14 +1204,21 @@ void launch_omega_conv(const ConvCols& c, int M, int Np, const double2* Ch, hipS
     }
   }
   const dim3 grid((unsigned)units), blk(256);
+  // with ev0 set the launch records ev0 / ev1 at the kernel's start and end
+#define PHX_CONV_LAUNCH(Mv)                                                                   \
+  do {                                                                                        \
+    if (ev0) hipExtLaunchKernelGGL(omega_conv_kernel<Mv>, grid, blk, 0, st, ev0, ev1, 0, a); \
+    else hipLaunchKernelGGL(omega_conv_kernel<Mv>, grid, blk, 0, st, a);                      \
+  } while (0)
   switch (M) {
-    case 1: hipLaunchKernelGGL(omega_conv_kernel<1>, grid, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(omega_conv_kernel<2>, grid, blk, 0, st, a); break;
-    case 3: hipLaunchKernelGGL(omega_conv_kernel<3>, grid, blk, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(omega_conv_kernel<4>, grid, blk, 0, st, a); break;
-    case 5: hipLaunchKernelGGL(omega_conv_kernel<5>, grid, blk, 0, st, a); break;
+    case 1: PHX_CONV_LAUNCH(1); break;
+    case 2: PHX_CONV_LAUNCH(2); break;
+    case 3: PHX_CONV_LAUNCH(3); break;
+    case 4: PHX_CONV_LAUNCH(4); break;
+    case 5: PHX_CONV_LAUNCH(5); break;
     default: break;
   }
+#undef PHX_CONV_LAUNCH
 }
 
 void launch_zero(double2* X, long n, hipStream_t st) {

@@ -97,12 +97,13 @@ enum RtClass {
   PROF_UPDATE,
   PROF_RESIDUAL,
   PROF_ADJOINT,
+  PROF_OP_CONV,   // Omega_s X as a convolution (omega_conv_kernel)
   PROF_NCLASS
 };
 const char* const PROF_NAMES[PROF_NCLASS] = {"potrf_diag", "panel",      "herk",  "trsm_diag", "trsm_update",
                                              "solve_upd",  "solve_diag", "sbinv", "assemble",  "apply",
                                              "op_gemm",    "gram",      "small", "update",    "residual",
-                                             "adjoint"};
+                                             "adjoint",    "op_conv"};
 
 struct PendKernel {
   int cls;
@@ -669,9 +670,17 @@ void apply_ops(Solver& sv, double2* Big, int c0, int ncol, const int* msk = null
   }
   KCHK(opgemm(a, st));
   if (conv) {
-    PROF_BEGIN(PROF_APPLY);
-    launch_omega_conv(ConvCols{so.B, so.C, so.sB, so.ldb, so.nb, so.ncolk, so.kdiv, so.bidx}, d.M, d.Np, d.Ch, st);
-    PROF_END(PROF_APPLY, 0, 32.0 * 3.0 * ncv * Np);
+    // its own arithmetic per component column: the forward DFT lines (L^2 along n3, L L2
+    // along n2, 16M^2 + 14M flops each), the Toeplitz lines (L2^2 of L^2 complex
+    // multiply-adds) and the inverse lines (L L2 and L^2, 16M^2 + 16M flops each); the
+    // column read and written once (16 B per complex)
+    const double Md = d.M, L = 2 * Md + 1, L2 = 4 * Md + 1;
+    const double fcol = (L * L + L * L2) * (16 * Md * Md + 14 * Md) + L2 * L2 * 8 * L * L +
+                        (L * L2 + L * L) * (16 * Md * Md + 16 * Md);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ctx->prof.kernel_events(PROF_OP_CONV, 3.0 * ncv * fcol, 3.0 * ncv * 32.0 * d.N, &e0, &e1);
+    launch_omega_conv(ConvCols{so.B, so.C, so.sB, so.ldb, so.nb, so.ncolk, so.kdiv, so.bidx}, d.M, d.Np, d.Ch, st,
+                      e0, e1);
     KCHK(hipGetLastError());
   }
   PROF_BEGIN(PROF_APPLY);

@@ -633,7 +633,7 @@ def test_kernel_class_timing(ctx):
         ctx.set_option("profile", mode)
         ctx.bands(cell, rho, q, wl.nbands, "mixed")
         ctx.set_option("profile", 0)
-        for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
+        for c in ("herk", "op_gemm", "solve_upd", "solve_diag", "op_conv"):
             n, ms = ctx.stat(f"prof.{c}.count"), ctx.stat(f"prof.{c}.ms")
             fl, by = ctx.stat(f"prof.{c}.flops"), ctx.stat(f"prof.{c}.bytes")
             log(mode, c, n, ms, fl, by)
@@ -642,7 +642,7 @@ def test_kernel_class_timing(ctx):
         # mode 2 times only the launches that record their own events
         stage = ctx.stat("prof.gram.count")
         assert (stage > 0) if mode == 1 else (stage == 0)
-    for c in ("herk", "op_gemm", "solve_upd", "solve_diag"):
+    for c in ("herk", "op_gemm", "solve_upd", "solve_diag", "op_conv"):
         assert counts[1, c] == counts[2, c]
     ctx.set_option("precond", 2)
 
