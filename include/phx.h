@@ -155,6 +155,10 @@ const char* phx_last_error(const phx_ctx* ctx);
  * guard_lock x the tolerance, the wanted bands' at the tolerance itself; the guards are
  * not results, and a wanted band still counts as converged only at the tolerance; 1: every
  * column locks at the tolerance),
+ * "zskip" (1, default: the Gram product and the basis update of the eigensolver's
+ * Rayleigh-Ritz step do not load the basis columns known to be zero, the search and
+ * previous directions of soft-locked columns and their images; 0: they load every
+ * column; the results are identical),
  * "omega_conv" (1, default: for orders M <= 5 the eigensolver's products Omega_s X are
  * exact convolutions of the density's Fourier coefficients with the columns, by DFTs of
  * length 4M+1 (Omega_s is Toeplitz in the wave index, Eqs. (6)-(7)); 0: products with the dense

@@ -95,6 +95,15 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
 
   // Group index gi = tid + 256 * r.  OPA = 0 (A column-major, contiguous in i): group
   // (i-block, k) with i-block fastest; OPA = 1 (A^H, contiguous in k): (k-block, i).
+  // Columns known to be zero (GemmArgs::zrn) are not loaded: with OPA = 1 a group's i, and
+  // with OPB = 0 a group's j, is the same for every k.
+  bool za[GA], zb[GB];
+#pragma unroll
+  for (int r = 0; r < GA; ++r)
+    za[r] = OPA == 1 && zero_col(g, b / g.kdiv, row0 + (tid + 256 * r) / (KS / VA));
+#pragma unroll
+  for (int r = 0; r < GB; ++r)
+    zb[r] = OPB == 0 && g.zs > 0 && zero_col(g, b / g.kdiv, (col0 + (tid + 256 * r) / (KS / VB)) % (3 * g.zs));
   C ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPA == 0) { i = row0 + (gi % (BM / VA)) * VA + q; k = k0 + gi / (BM / VA); }
         else { k = k0 + (gi % (KS / VA)) * VA + q; i = row0 + gi / (KS / VA); }
         C v = mk<R>(0, 0);
-        if (i < g.M && k < kend) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
+        if (i < g.M && k < kend && !za[r]) v = (OPA == 0) ? A[i + (long)k * g.lda] : A[k + (long)i * g.lda];
         ra[r * VA + q] = v;
       }
     }
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(GemmArgs<R> g) {
         if (OPB == 0) { k = k0 + (gi % (KS / VB)) * VB + q; j = col0 + gi / (KS / VB); }
         else { j = col0 + (gi % (BN / VB)) * VB + q; k = k0 + gi / (BN / VB); }
         C w = mk<R>(0, 0);
-        if (j < g.N && k < kend) w = (OPB == 0) ? B[k + (long)j * g.ldb] : B[j + (long)k * g.ldb];
+        if (j < g.N && k < kend && !zb[r]) w = (OPB == 0) ? B[k + (long)j * g.ldb] : B[j + (long)k * g.ldb];
         rb[r * VB + q] = w;
       }
     }
@@ -428,6 +437,8 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
     Wi[k][j] = v.y;
   }
   __syncthreads();
+  // the columns of A known to be zero (bit k: column k, the same in every wave), not loaded
+  const unsigned long long zmask = __ballot(zero_col(g, b / g.kdiv, lane));
 #pragma unroll 1
   for (int stripe = 0; stripe < ST; ++stripe) {
     const int i0 = blockIdx.x * 64 * ST + wave * 16 * ST + 16 * stripe;
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int k = 32 * h + 4 * q + lg;
-        av[q] = (i < g.M && k < g.K) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
+        av[q] = (i < g.M && k < g.K && !((zmask >> k) & 1ull)) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {  // k >= K: A is zero there and W's rows are zero

@@ -32,7 +32,26 @@ struct GemmArgs {
   // bidx[i / kdiv] * kdiv + i % kdiv (tiled, tall-skinny and split-K reduction kernels)
   const int* bidx;
   int nbat;
+  // optional: columns of an eigensolver basis [X W P] (3 zs columns) that are known to be
+  // zero, whose loads are skipped (the result is the same: the data is zero).  Column
+  // c >= zs of k-point b / kdiv is zero when zfirst is set (W and P before the first
+  // step) or when zrn[(b / kdiv) zs + c % zs] is below ztol (c % zs < znb) or zgtol (the
+  // soft-locking test of the residual kernel, which zeroed those columns).  Used by the
+  // tiled kernel for the columns of A^H (OPA = 1) and of B (OPB = 0, columns taken modulo
+  // 3 zs) and by the tall-skinny kernel for the columns of A; the other kernels load them.
+  const double* zrn;
+  double ztol, zgtol;
+  int zs, znb, zfirst;
 };
+
+// The zero-column test of GemmArgs (false without zrn).
+template <typename R>
+__device__ __forceinline__ bool zero_col(const GemmArgs<R>& g, int kpt, int c) {
+  if (!g.zrn || c < g.zs || c >= 3 * g.zs) return false;
+  if (g.zfirst) return true;
+  const int j = c % g.zs;
+  return g.zrn[(long)kpt * g.zs + j] < (j < g.znb ? g.ztol : g.zgtol);
+}
 
 template <typename R>
 int zgemm(const GemmArgs<R>& g, int opa, int opb, hipStream_t st);

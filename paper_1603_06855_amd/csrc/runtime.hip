@@ -67,6 +67,7 @@ struct Opts {
   int spin_wait = 0;         // 1: the per-iteration host wait spins (hipStreamSynchronize)
   int omega_conv = 1;        // 1: Omega_s X as a convolution (M <= 5); 0: the dense real operator
   double guard_lock = 1000;  // guard columns (beyond the wanted bands) lock below guard_lock x tol
+  int zskip = 1;             // 1: the fused Rayleigh-Ritz step skips loading soft-locked (zero) columns
   int gram_split = 0;        // K-split of the Gram products (0: min(16, 3Np / 256))
   int kstreams = 1;          // single-design device calls: k-point ranges on this many streams
   double degen_tol = 1e-8;   // bands closer than this (relative, in omega) form one degenerate cluster
@@ -537,6 +538,13 @@ struct ChunkOut {
   bool converged = false;
 };
 
+// Columns of the eigensolver basis known to be zero (GemmArgs::zrn).
+struct ZeroCols {
+  const double* rn;
+  double tol, gtol;
+  int s, nb, first;
+};
+
 struct Solver {
   phx_ctx* ctx;
   Design* d;
@@ -570,14 +578,26 @@ struct Solver {
   void* Rp;    // nk x n3 x s
   void* Zp;
   int ksplit;
+  // the soft-locked columns of the current basis, whose W and P parts and images the last
+  // residual kernel zeroed (rn, the thresholds it used), or before the first step all of W
+  // and P; the fused Rayleigh-Ritz step's Gram product and update skip loading them
+  ZeroCols zc{nullptr, 0, 0, 0, 0, 0};
 };
 
 template <typename R>
 void gemm(phx_ctx* ctx, int opa, int opb, int M, int N, int K, int batch, const C_t<R>* A, long lda, long sA, int dA,
           const C_t<R>* B, long ldb, long sB, int dB, C_t<R>* Cm, long ldc, long sC, C_t<R> alpha, C_t<R> beta,
           int ksplit = 1, C_t<R>* Cpart = nullptr, const int* kact = nullptr, int kdiv = 1, int csplit = 0,
-          int cgap = 0, const int* bidx = nullptr, int nbat = 0, int tiled = 0) {
+          int cgap = 0, const int* bidx = nullptr, int nbat = 0, int tiled = 0, const ZeroCols* zc = nullptr) {
   GemmArgs<R> g{};
+  if (zc) {
+    g.zrn = zc->rn;
+    g.ztol = zc->tol;
+    g.zgtol = zc->gtol;
+    g.zs = zc->s;
+    g.znb = zc->nb;
+    g.zfirst = zc->first;
+  }
   if (ctx->pk.set) {
     ctx->prof.kernel_events(ctx->pk.cls, ctx->pk.flops, ctx->pk.bytes, &g.ev0, &g.ev1);
     ctx->pk.set = false;
@@ -718,12 +738,13 @@ void gram(Solver& sv, double2* Big, int block, Sel k) {
 // workgroups share a row, so reading and writing the same array is safe.  Frozen
 // k-points are skipped and keep their basis.
 void update_in_place(Solver& sv, long a0, long ncol, long K, const double2* C, long sC, long c0, int split,
-                     Sel k) {
+                     Sel k, const ZeroCols* zc = nullptr) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m;
   if (ncol > 64 || K > 64) fail(ctx, PHX_EINVAL, "in-place basis update needs at most 64 columns");
+  if (zc && a0 != 0) fail(ctx, PHX_EINVAL, "zero-column skipping needs the whole basis from column 0");
   gemm<double>(ctx, 0, 0, n3, ncol, K, 3 * sv.nk, sv.Big + a0 * n3, n3, n3 * m, 1, C, m, sC, 3, sv.Big + c0 * n3, n3,
-               n3 * m, ONE, ZERO, 1, nullptr, k.d, 3, split, split, k.l, k.n);
+               n3 * m, ONE, ZERO, 1, nullptr, k.d, 3, split, split, k.l, k.n, 0, zc);
 }
 
 void cholqr(Solver& sv, Sel k) {
@@ -767,8 +788,9 @@ void rayleigh_ritz_fused(Solver& sv, Sel k) {
   phx_ctx* ctx = sv.ctx;
   const long n3 = sv.n3, m = sv.m, s = sv.s;
   PROF_BEGIN(PROF_GRAM);
+  const ZeroCols* zc = sv.zc.rn ? &sv.zc : nullptr;
   gemm<double>(ctx, 1, 0, m, 2 * m, n3, sv.nk, sv.Big, n3, sv.sBig, 1, sv.Big + m * n3, n3, sv.sBig, 1, sv.G2, m,
-               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, k.d, 1, 0, 0, k.l, k.n);
+               2 * m * m, ONE, ZERO, sv.ksplit, sv.G2part, k.d, 1, 0, 0, k.l, k.n, 0, zc);
   PROF_END(PROF_GRAM, 8.0 * m * 2 * m * 3.0 * sv.d->N * k.n, 16.0 * 3 * m * 3.0 * sv.d->N * k.n);
   PROF_BEGIN(PROF_SMALL);
   // coefficients of the new X and P side by side (m x 2s per k), so that one pass over
@@ -778,7 +800,7 @@ void rayleigh_ritz_fused(Solver& sv, Sel k) {
   PROF_END(PROF_SMALL, 0, 0);
   KCHK(hipGetLastError());
   PROF_BEGIN(PROF_UPDATE);
-  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s, k);
+  update_in_place(sv, 0, 2 * s, m, sv.Cp, 2 * m * s, 0, (int)s, k, zc);
   PROF_END(PROF_UPDATE, 8.0 * 3 * 3.0 * sv.d->N * 2.0 * m * s * k.n, 16.0 * 3 * 3.0 * sv.d->N * (m + 2.0 * s) * k.n);
 }
 
@@ -1030,6 +1052,9 @@ void solve_chunk(phx_ctx* ctx, Design& d, const double* q, int nk, int nb, Chunk
   int it = 0;
   for (it = 0; it <= ctx->opt.maxit; ++it) {
     const Sel all{sv.kact, sv.nact, sv.lact}, far{sv.kfar, sv.nfar, sv.lfar}, nearsel{sv.knear, sv.nnear, sv.lnear};
+    // before the first step W and P are zero (the basis was cleared and only X written);
+    // after it, the columns the last residual kernel locked are
+    sv.zc = ctx->opt.zskip ? ZeroCols{sv.rn, tol, gtol, s, nb, it == 0 ? 1 : 0} : ZeroCols{nullptr, 0, 0, 0, 0, 0};
     // rr_fused 2: a k-point far from convergence takes both orthonormalisations in the small
     // space (one Gram product and one basis update per iteration); otherwise one explicit
     // Omega-CholQR of the basis first
@@ -1472,6 +1497,7 @@ int phx_set_option(phx_ctx* ctx, const char* key, double v) {
   else if (k == "spin_wait") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.spin_wait = (int)v; }
   else if (k == "omega_conv") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.omega_conv = (int)v; }
   else if (k == "guard_lock") { if (!(v >= 1 && v <= 1e4)) return bad(); ctx->opt.guard_lock = v; }
+  else if (k == "zskip") { if (!(v == 0 || v == 1)) return bad(); ctx->opt.zskip = (int)v; }
   else if (k == "degen_tol") { if (!(v >= 0 && v < 1e-2)) return bad(); ctx->opt.degen_tol = v; }
   else if (k == "mem_limit_gb") { if (!(v >= 0 && v < 1e6)) return bad(); ctx->opt.mem_limit_gb = v; }
   else if (k == "precond") { if (!(v == 0 || v == 1 || v == 2)) return bad(); ctx->opt.precond = (int)v; }

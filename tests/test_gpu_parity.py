@@ -666,6 +666,7 @@ def test_kernel_class_timing(ctx):
     ("mem_limit_gb", (-1,), (0, 8.0)),
     ("omega_conv", (-1, 2, 0.5), (0, 1)),
     ("guard_lock", (0.5, 2e4), (1, 1000, 1e4)),
+    ("zskip", (-1, 2, 0.5), (0, 1)),
     ("no_such_option", (1.0,), ()),
 ])
 def test_option_ranges(key, bad, good):

@@ -15,6 +15,8 @@
 * guard locking (option guard_lock): the guard vectors beyond the wanted bands locking at
   1000 x the tolerance (the default) or at the tolerance itself leave the wanted bands'
   frequencies and sensitivities the same within the solver tolerance;
+* zero-column skipping (option zskip): the Rayleigh-Ritz step's Gram product and basis
+  update skip loading the soft-locked columns, which are zero, and give bit-identical results;
 * degenerate clusters (Eq. 15 needs a simple eigenvalue): a design with the full cubic
   symmetry at Gamma and X, whose bands come in symmetry-forced doublets and triplets;
   PHX_WDEGEN, every member of a cluster carries the cluster mean, which matches the mean of
@@ -235,6 +237,22 @@ def test_guard_locking_keeps_the_wanted_bands(ctx, prec):
     assert n >= len(q)
     assert om_rel <= (1e-9 if prec == "fp64" else 1e-8)
     assert sens <= (1e-7 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_zero_column_skipping_is_exact(ctx, prec):
+    cell = synth.Cell("FCC", 1.0, 32, 5)
+    rho = synth.box_smoothed_uniform(32, 403)
+    q = phx.kpath("FCC", 24)[[1, 6, 12, 18, 23]]
+    res = {}
+    try:
+        for z in (0, 1):
+            ctx.set_option("zskip", z)
+            res[z] = ctx.sens(cell, rho, q, 12, (6, 7), prec)
+            log("zskip", z, prec, "iters", ctx.stat("iters"), "status", ctx.last_status)
+    finally:
+        ctx.set_option("zskip", 1)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
 
 
 def test_block_not_above_nbands_is_rejected():
