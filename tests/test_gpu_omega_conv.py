@@ -3,7 +3,7 @@ omega_conv = 1, the default for M <= 5) against the dense real operator in the p
 (omega_conv = 0), through whole solves: the two routes compute the same product up to
 rounding, so the frequencies and the adjoint sensitivities agree far inside the solver
 tolerance.  Cases: FCC 32^3 M = 5 (with the coarse start at M = 2 and at M = 3), BCC 24^3
-M = 4, SC M = 2 and 3; k-points off Gamma (no zero modes), FP64 and mixed precision.  The
+M = 4 (with the coarse start at M = 2 and at M = 1), SC M = 1, 2 and 3; k-points off Gamma (no zero modes), FP64 and mixed precision.  The
 solver-level parity tests against the oracle run with the default (the convolution).  At
 M = 6, beyond the convolution kernel's orders, both settings take the dense product and give
 identical results (with the coarse start off: its order-4 solve would take the
@@ -37,6 +37,8 @@ CASES = {
     "BCC-M4": (synth.Cell("BCC", 1.0, 24, 4), lambda: synth.gaussian_blob(24, "BCC", 303), "BCC", 2),
     "SC-M3": (synth.Cell("SC", 1.0, 16, 3), lambda: synth.box_smoothed_uniform(16, 202), "SC", 2),
     "SC-M2": (synth.Cell("SC", 1.0, 8, 2), lambda: synth.box_smoothed_uniform(8, 101), "SC", 2),
+    "SC-M1": (synth.Cell("SC", 1.0, 8, 1), lambda: synth.box_smoothed_uniform(8, 104), "SC", 2),
+    "BCC-M4-drop3": (synth.Cell("BCC", 1.0, 24, 4), lambda: synth.gaussian_blob(24, "BCC", 304), "BCC", 3),
 }
 
 
