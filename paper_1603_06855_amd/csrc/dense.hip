@@ -452,16 +452,16 @@ __global__ __launch_bounds__(256, 3) void skinny_kernel(GemmArgs<R> g) {
       t3[y] = (ACC){0, 0, 0, 0};
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {  // two halves of the k range, 8 loads in flight each
-      C av[8];
+    for (int h = 0; h < 4; ++h) {  // four quarters of the k range, 4 loads in flight each
+      C av[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = 32 * h + 4 * q + lg;
+      for (int q = 0; q < 4; ++q) {
+        const int k = 16 * h + 4 * q + lg;
         av[q] = (i < g.M && k < g.K && !((zmask >> k) & 1ull)) ? A[i + (long)k * g.lda] : mk<R>(0, 0);
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {  // k >= K: A is zero there and W's rows are zero
-        const int k = 32 * h + 4 * q + lg;
+      for (int q = 0; q < 4; ++q) {  // k >= K: A is zero there and W's rows are zero
+        const int k = 16 * h + 4 * q + lg;
         const R ar = av[q].x, ai = av[q].y, as = ar + ai;
 #pragma unroll
         for (int y = 0; y < NB; ++y) {
