@@ -137,8 +137,8 @@ const char* phx_last_error(const phx_ctx* ctx);
  * M - coarse_drop, at least 1),
  * "profile" (0, default: off; 1: every kernel class is timed with HIP events,
  * stage intervals on the library stream and, for the classes herk, op_gemm,
- * solve_upd and solve_diag, events that each launch records at its kernel's start
- * and end; 2: only the latter, which disturbs concurrent streams least),
+ * op_conv, solve_upd and solve_diag, events that each launch records at its kernel's
+ * start and end; 2: only the latter, which disturbs concurrent streams least),
  * "profile_reset" (any value: clears the class timers),
  * "kstreams" (1..16, default 1): phx_bands_dev, phx_sens_dev and phx_adjoint_dev
  * split the k-points into this many consecutive ranges solved concurrently on worker
@@ -189,7 +189,9 @@ int phx_set_option(phx_ctx* ctx, const char* key, double value);
  * "precond_switches" (solves that went from block Jacobi to the pencil factors),
  * "enomem_retries" (k-chunks solved again with fewer k-points), "mem_bytes" (device
  * workspace the context holds).  "prof.<class>.<ms|flops|bytes|count>"
- * reads the kernel-class timers (enabled with the option "profile"). */
+ * reads the kernel-class timers (enabled with the option "profile"); the classes:
+ * potrf_diag, panel, herk, trsm_diag, trsm_update, solve_upd, solve_diag, sbinv,
+ * assemble, apply, op_gemm, gram, small, update, residual, adjoint, op_conv. */
 int phx_get_stat(const phx_ctx* ctx, const char* key, double* value);
 
 /* ------------------------------------------------------------------ helpers */
