@@ -280,12 +280,14 @@ __device__ __forceinline__ void dev_channels(const double2 (&y)[6], double2 t, d
 }
 __global__ void strain_kernel(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol,
                               double2* Y, double2* tr, const int* kact, int pairN, const int* cmask) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const int c = (pairN - 1) / 2;
-  if (pairN > 0 && p > c && p < pairN) return;  // the partner thread writes this row
+  // paired basis: threads for the rows 0 .. c (row p < c with its partner N-1-p) and the
+  // padding rows N .. Np-1 only (launch_strain's grid)
+  if (pairN > 0 && p > c) p += pairN - 1 - c;
+  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const double2* x = X + (long)k * sX + (long)j * ldx;
   const int nch = pairN > 0 ? 5 : 6;
   double2* y = Y + (long)k * Np * nch * ncol + (long)(nch * j) * Np;
@@ -352,12 +354,14 @@ __device__ __forceinline__ void force_of(const double* K, const double2 (&z)[5],
 
 __global__ void force_kernel(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, double c2,
                              double2* KX, long ldk, long sK, const int* kact, int pairN, const int* cmask) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
-  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const int c = (pairN - 1) / 2;
-  if (p > c && p < pairN) return;  // the partner thread writes this row
+  // threads for the rows 0 .. c (row p < c with its partner N-1-p) and the padding rows
+  // N .. Np-1 only (launch_force's grid)
+  if (p > c) p += pairN - 1 - c;
+  if (p >= Np || (kact && !kact[k]) || (cmask && !cmask[k * ncol + j])) return;
   const double2* z = Zy + (long)k * Np * 5 * ncol + (long)(5 * j) * Np;
   const double2* zt = Zt + (long)k * Np * ncol + (long)j * Np;
   double2* o = KX + (long)k * sK + (long)j * ldk;
@@ -1165,13 +1169,15 @@ template void launch_assemble<float>(const double2*, const double2*, const doubl
 
 void launch_strain(const double2* X, long ldx, long sX, const double* Kv, int Np, int ncol, int nk, double2* Y,
                    double2* tr, hipStream_t st, const int* kact, int pairN, const int* cmask) {
-  hipLaunchKernelGGL(strain_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
+  const long rows = pairN > 0 ? (pairN - 1) / 2 + 1 + (Np - pairN) : Np;  // threads per column
+  hipLaunchKernelGGL(strain_kernel, dim3(nblk(rows, 256), ncol, nk), dim3(256), 0, st, X, ldx, sX, Kv, Np, ncol, Y,
                      tr, kact, pairN, cmask);
 }
 
 void launch_force(const double2* Zy, const double2* Zt, const double* Kv, int Np, int ncol, int nk, double c2,
                   double2* KX, long ldk, long sK, hipStream_t st, const int* kact, int pairN, const int* cmask) {
-  hipLaunchKernelGGL(force_kernel, dim3(nblk(Np, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
+  const long rows = (pairN - 1) / 2 + 1 + (Np - pairN);  // threads per column
+  hipLaunchKernelGGL(force_kernel, dim3(nblk(rows, 256), ncol, nk), dim3(256), 0, st, Zy, Zt, Kv, Np, ncol, c2, KX,
                      ldk, sK, kact, pairN, cmask);
 }
 
